@@ -1,0 +1,241 @@
+"""Mesh orientation, isoparametric mapping, metric terms and connectivity.
+
+Test infrastructure (see the package docstring).  Written from:
+  * Sec. 4.1, eq. (poly_mapping): x(xi) = sum_i x_i l_i(xi) of degree p_g = p,
+    J = det(grad x) > 0 (eq. jacobian_positive), G = J (grad x)^{-1};
+  * Sec. 4.2: exact metrics in 2D; in 3D the conservative curl form
+    (eqs. metric_interpolants, conservative_curl) with degree q+1 interpolants;
+    Nanson normals and facet Jacobians (eq. nanson);
+  * Sec. 4.5, eq. (jacobian_approx): J interpolated with degree p_g at the
+    mapping nodes, used in the mass matrix and entropy projection;
+  * Sec. 7.3 and Remark (connectivity): split-Cartesian meshes with local
+    orientation chosen so that facet quadrature nodes of neighbours coincide;
+  * Assumption (conformal): matching facet nodes across every interface.
+
+Readings (listed in the design notes): mapping and curl-interpolation nodes are
+equispaced simplex nodes; the curl-form columns give G_{l m} for m = 1, 2, 3
+(so that G equals the adjugate for affine maps); element-local coordinates
+(physical minus the element's first vertex) are used, which leaves G and J
+unchanged; orientation puts the largest global vertex id at local vertex d+1
+and (in 3D) the second largest at local vertex 3, the other two in increasing
+id order, swapped if the affine Jacobian is negative.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+from functools import lru_cache
+
+import numpy as np
+import torch
+
+from .poly1d import DT
+from .refelem import RefElement, pkd, pkd_grad
+
+
+# ------------------------------------------------------------------ nodes
+@lru_cache(maxsize=None)
+def equispaced(dim: int, N: int) -> torch.Tensor:
+    pts = []
+    if dim == 2:
+        for j in range(N + 1):
+            for i in range(N + 1 - j):
+                pts.append((-1 + 2 * i / N, -1 + 2 * j / N))
+    else:
+        for k in range(N + 1):
+            for j in range(N + 1 - k):
+                for i in range(N + 1 - j - k):
+                    pts.append((-1 + 2 * i / N, -1 + 2 * j / N, -1 + 2 * k / N))
+    return torch.tensor(pts, dtype=DT)
+
+
+def lagrange_matrices(dim: int, N: int, X: torch.Tensor):
+    """Interpolation matrix L[k, i] = l_i(X_k) and gradients dL[m][k, i] for the
+    degree-N Lagrange basis on equispaced nodes (through the PKD Vandermonde)."""
+    nodes = equispaced(dim, N)
+    Vn = pkd(dim, N, nodes)
+    VX = pkd(dim, N, X)
+    GX = pkd_grad(dim, N, X)
+    L = torch.linalg.solve(Vn.T, VX.T).T
+    dL = [torch.linalg.solve(Vn.T, GX[m].T).T for m in range(dim)]
+    return L, dL
+
+
+# ------------------------------------------------------------------ orientation
+def reference_vertices(dim: int) -> torch.Tensor:
+    if dim == 2:
+        return torch.tensor([[-1.0, -1.0], [1.0, -1.0], [-1.0, 1.0]], dtype=DT)
+    return torch.tensor([[-1.0, -1.0, -1.0], [1.0, -1.0, -1.0], [-1.0, 1.0, -1.0], [-1.0, -1.0, 1.0]], dtype=DT)
+
+
+def orient(elem_ids: np.ndarray, elem_x: np.ndarray):
+    """Local vertex order: last vertex = largest global id; in 3D local vertex 3 =
+    second largest; the remaining two by increasing id, swapped if det < 0."""
+    ne, nv = elem_ids.shape
+    dim = nv - 1
+    ids_out = np.empty_like(elem_ids)
+    x_out = np.empty_like(elem_x)
+    for e in range(ne):
+        order = list(np.argsort(elem_ids[e], kind="stable"))  # increasing id
+        # increasing: [o0, o1, (o2), top]
+        loc = order  # v1, v2, (v3), v_{d+1} in increasing order already puts max last
+        X = elem_x[e][loc]
+        A = (X[1:] - X[0]).T
+        if np.linalg.det(A) < 0:
+            loc = [loc[1], loc[0]] + loc[2:]
+        ids_out[e] = elem_ids[e][loc]
+        x_out[e] = elem_x[e][loc]
+    return ids_out, x_out
+
+
+# ------------------------------------------------------------------ geometry
+@dataclass
+class Geometry:
+    dim: int
+    p: int
+    q: int
+    vids: np.ndarray          # oriented global vertex ids [Ne, d+1]
+    vx: np.ndarray            # oriented vertex coords [Ne, d+1, d]
+    x_vol: torch.Tensor       # physical coords of volume nodes [Ne, Nq, d]
+    J: torch.Tensor           # interpolated Jacobian at volume nodes [Ne, Nq]
+    G: torch.Tensor           # metric terms at volume nodes [Ne, Nq, d(l), d(m)]
+    Gf: list                  # per facet: metric terms at facet nodes [Ne, Nqf, d, d]
+    nJ: list                  # per facet: G^T nhat at facet nodes [Ne, Nqf, d]
+    Jf: list                  # per facet: |G^T nhat| [Ne, Nqf]
+    n: list                   # per facet: unit normal [Ne, Nqf, d]
+    x_f: list                 # per facet: physical coords [Ne, Nqf, d]
+    J_exact: torch.Tensor     # det(grad x) at volume nodes (diagnostics only)
+
+
+def build_geometry(ref: RefElement, elem_ids: np.ndarray, elem_x: np.ndarray, warp) -> Geometry:
+    dim, p, q = ref.dim, ref.p, ref.q
+    vids, vx = orient(np.asarray(elem_ids), np.asarray(elem_x, dtype=np.float64))
+    ne = vids.shape[0]
+    # affine image of the mapping nodes, warped, then element-local coordinates
+    Xm = equispaced(dim, p)                             # mapping nodes (degree p_g = p)
+    lam = _barycentric(dim, Xm)                         # [Ng, d+1]
+    x_aff = np.einsum("gk,ekd->egd", lam.numpy(), vx)   # [Ne, Ng, d]
+    x_map = warp(x_aff.reshape(-1, dim)).reshape(ne, -1, dim)
+    origin = vx[:, 0, :]
+    xl = torch.tensor(x_map - origin[:, None, :], dtype=DT)   # local coords [Ne, Ng, d]
+    org = torch.tensor(origin, dtype=DT)
+
+    def grad_x(X):
+        L, dL = lagrange_matrices(dim, p, X)
+        xv = torch.einsum("ki,eid->ekd", L, xl)
+        gx = torch.stack([torch.einsum("ki,eic->ekc", dL[m], xl) for m in range(dim)], -1)  # [Ne,k,c,m] = dx_c/dxi_m
+        return xv, gx
+
+    # interpolated Jacobian (eq. jacobian_approx)
+    _, gx_map = grad_x(Xm)
+    Jmap = torch.linalg.det(gx_map)
+    Lvol, _ = lagrange_matrices(dim, p, ref.xi)
+    J = torch.einsum("ki,ei->ek", Lvol, Jmap)
+
+    def metrics(X):
+        xv, gx = grad_x(X)
+        if dim == 2:
+            G = torch.empty(gx.shape, dtype=DT)
+            G[..., 0, 0] = gx[..., 1, 1]
+            G[..., 0, 1] = -gx[..., 0, 1]
+            G[..., 1, 0] = -gx[..., 1, 0]
+            G[..., 1, 1] = gx[..., 0, 0]
+            return xv, G
+        # conservative curl form with degree q+1 interpolants
+        Xc = equispaced(3, q + 1)
+        xc, gc = grad_x(Xc)                  # [Ne, Nc, 3], [Ne, Nc, 3(comp), 3(ref)]
+        r1 = xc[..., 2:3] * gc[..., 1, :]    # x3 grad x2
+        r2 = xc[..., 2:3] * gc[..., 0, :]    # x3 grad x1
+        r3 = xc[..., 0:1] * gc[..., 1, :]    # x1 grad x2
+        _, dLc = lagrange_matrices(3, q + 1, X)
+
+        def curl(r):
+            dr = [torch.einsum("ki,eic->ekc", dLc[m], r) for m in range(3)]  # dr[m][..., c] = d r_c / d xi_m
+            return torch.stack([dr[1][..., 2] - dr[2][..., 1],
+                                dr[2][..., 0] - dr[0][..., 2],
+                                dr[0][..., 1] - dr[1][..., 0]], -1)
+
+        c1, c2, c3 = -curl(r1), curl(r2), curl(r3)
+        G = torch.stack([c1, c2, c3], -1)    # G[..., l, m]: column m from the m-th curl
+        return xv, G
+
+    xv, G = metrics(ref.xi)
+    x_vol = xv + org[:, None, :]
+    _, gx_vol = grad_x(ref.xi)
+    J_exact = torch.linalg.det(gx_vol)
+    Gf, nJ, Jf, nn, xf = [], [], [], [], []
+    for z in range(ref.Nf):
+        xfz, Gz = metrics(ref.xi_f[z])
+        v = torch.einsum("l,ekl m->ekm".replace(" ", ""), ref.nhat[z], Gz)
+        jf = torch.linalg.norm(v, dim=-1)
+        Gf.append(Gz)
+        nJ.append(v)
+        Jf.append(jf)
+        nn.append(v / jf[..., None])
+        xf.append(xfz + org[:, None, :])
+    return Geometry(dim, p, q, vids, vx, x_vol, J, G, Gf, nJ, Jf, nn, xf, J_exact)
+
+
+def _barycentric(dim: int, xi: torch.Tensor) -> torch.Tensor:
+    if dim == 2:
+        l2 = 0.5 * (1 + xi[:, 0])
+        l3 = 0.5 * (1 + xi[:, 1])
+        return torch.stack([1 - l2 - l3, l2, l3], -1)
+    l2 = 0.5 * (1 + xi[:, 0])
+    l3 = 0.5 * (1 + xi[:, 1])
+    l4 = 0.5 * (1 + xi[:, 2])
+    return torch.stack([1 - l2 - l3 - l4, l2, l3, l4], -1)
+
+
+# ------------------------------------------------------------------ connectivity
+# local facets: (vertex tuple, base start vertex); vertex indices are local 0-based
+FACETS = {
+    2: [((0, 1), 0), ((1, 2), 1), ((0, 2), 0)],
+    3: [((0, 1, 3), 0), ((1, 2, 3), 1), ((0, 2, 3), 0), ((0, 1, 2), 0)],
+}
+
+
+@dataclass
+class Connectivity:
+    nbr_elem: np.ndarray   # [Ne, Nf]
+    nbr_face: np.ndarray   # [Ne, Nf]
+    flip: np.ndarray       # [Ne, Nf] bool: LG facet coordinate reversed on the neighbour
+    node_map: np.ndarray   # [Ne, Nf, Nqf] index of the matching node on the neighbour facet
+
+
+def connectivity(vids: np.ndarray, q: int) -> Connectivity:
+    ne, nv = vids.shape
+    dim = nv - 1
+    faces = FACETS[dim]
+    nf = len(faces)
+    Qn = q + 1
+    table = {}
+    for e in range(ne):
+        for z, (verts, _) in enumerate(faces):
+            key = tuple(sorted(int(vids[e, v]) for v in verts))
+            table.setdefault(key, []).append((e, z))
+    nbr_elem = np.full((ne, nf), -1, dtype=np.int64)
+    nbr_face = np.full((ne, nf), -1, dtype=np.int64)
+    flip = np.zeros((ne, nf), dtype=bool)
+    nqf = Qn if dim == 2 else Qn * Qn
+    node_map = np.zeros((ne, nf, nqf), dtype=np.int64)
+    for key, lst in table.items():
+        if len(lst) != 2:
+            raise ValueError(f"non-conforming facet {key}: {lst}")
+        (e0, z0), (e1, z1) = lst
+        for (ea, za), (eb, zb) in (((e0, z0), (e1, z1)), ((e1, z1), (e0, z0))):
+            nbr_elem[ea, za] = eb
+            nbr_face[ea, za] = zb
+            sa = int(vids[ea, faces[za][1]])
+            sb = int(vids[eb, faces[zb][1]])
+            if dim == 3:
+                apex_a = int(vids[ea, faces[za][0][2]])
+                apex_b = int(vids[eb, faces[zb][0][2]])
+                if apex_a != apex_b:
+                    raise ValueError("facet collapse vertices differ; orientation failed")
+            fl = sa != sb
+            flip[ea, za] = fl
+            for j in range(nqf):
+                a1, a2 = j % Qn, j // Qn
+                b1 = (Qn - 1 - a1) if fl else a1
+                node_map[ea, za, j] = b1 + Qn * a2
+    return Connectivity(nbr_elem, nbr_face, flip, node_map)

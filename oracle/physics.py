@@ -1,0 +1,180 @@
+"""Compressible Euler physics for the entropy-stable scheme.
+
+Test infrastructure (see the package docstring).  Written from Sec. 7.1-7.2:
+  * eq. (euler): conservative variables (rho, rho v, E), fluxes, ideal gas;
+  * eq. (euler_entropy): S = -rho s/(gamma-1) with s = ln p - gamma ln rho; the
+    entropy variables are W = dS/dU (Sec. 2.2) and U(W) is their inverse;
+  * arithmetic and logarithmic means, the latter (a+ - a-)/(ln a+ - ln a-) with a
+    series for nearly equal arguments (ln(a+/a-) = 2 atanh f, f = (a+-a-)/(a++a-),
+    truncated after f^6/7 when f^2 < 1e-4);
+  * eq. (ranocha_flux): Ranocha's entropy-conservative, kinetic-energy
+    preserving flux.  Reading: the factor 1/2 in the energy component multiplies
+    v- . v+ only (the printed grouping is not consistent with f_m(U));
+  * Chandrashekar's entropy-conservative flux (cited for dissipation in Sec. 4.6),
+    used by the small 2D density-wave workload;
+  * eqs. (num_flux, wave_speed): f* = f# - lambda/2 (u+ - u-) with Davis' wave
+    speed; the entropy-conservative variant drops the dissipation.
+States are tensors [..., d+2]; directions n are [..., d].
+"""
+from __future__ import annotations
+
+import torch
+
+LOG_SERIES_THRESHOLD = 1.0e-4
+
+
+def prim(u: torch.Tensor, gamma: float):
+    d = u.shape[-1] - 2
+    rho = u[..., 0]
+    v = u[..., 1:1 + d] / rho[..., None]
+    p = (gamma - 1.0) * (u[..., d + 1] - 0.5 * rho * (v * v).sum(-1))
+    return rho, v, p
+
+
+def euler_flux(u: torch.Tensor, n: torch.Tensor, gamma: float) -> torch.Tensor:
+    """f(U, n) = sum_m n_m f_m(U)."""
+    d = u.shape[-1] - 2
+    rho, v, p = prim(u, gamma)
+    vn = (v * n).sum(-1)
+    out = [rho * vn]
+    for i in range(d):
+        out.append(rho * v[..., i] * vn + p * n[..., i])
+    out.append(vn * (u[..., d + 1] + p))
+    return torch.stack(out, -1)
+
+
+def entropy(u: torch.Tensor, gamma: float) -> torch.Tensor:
+    rho, v, p = prim(u, gamma)
+    s = torch.log(p) - gamma * torch.log(rho)
+    return -rho * s / (gamma - 1.0)
+
+
+def entropy_vars(u: torch.Tensor, gamma: float) -> torch.Tensor:
+    """W(U) = dS/dU."""
+    d = u.shape[-1] - 2
+    rho, v, p = prim(u, gamma)
+    s = torch.log(p) - gamma * torch.log(rho)
+    w1 = (gamma - s) / (gamma - 1.0) - 0.5 * rho * (v * v).sum(-1) / p
+    out = [w1]
+    for i in range(d):
+        out.append(rho * v[..., i] / p)
+    out.append(-rho / p)
+    return torch.stack(out, -1)
+
+
+def cons_from_entropy(w: torch.Tensor, gamma: float) -> torch.Tensor:
+    """U(W), the inverse of entropy_vars."""
+    d = w.shape[-1] - 2
+    b = -w[..., d + 1]                       # rho / p
+    v = w[..., 1:1 + d] / b[..., None]
+    s = gamma - (gamma - 1.0) * (w[..., 0] + 0.5 * b * (v * v).sum(-1))
+    rho = torch.exp(-(s + torch.log(b)) / (gamma - 1.0))
+    p = rho / b
+    E = p / (gamma - 1.0) + 0.5 * rho * (v * v).sum(-1)
+    return torch.cat([rho[..., None], rho[..., None] * v, E[..., None]], -1)
+
+
+def flux_potential(u: torch.Tensor, gamma: float) -> torch.Tensor:
+    """psi_m = W^T f_m - F_m = rho v_m for this entropy pair."""
+    d = u.shape[-1] - 2
+    rho, v, p = prim(u, gamma)
+    return rho[..., None] * v
+
+
+def _series(f2):
+    return 1.0 + f2 / 3.0 + f2 * f2 / 5.0 + f2 * f2 * f2 / 7.0
+
+
+def log_mean(am: torch.Tensor, ap: torch.Tensor) -> torch.Tensor:
+    """{a}_ln = (a+ - a-)/(ln a+ - ln a-); series branch for nearly equal args."""
+    f = (ap - am) / (ap + am)
+    f2 = f * f
+    small = f2 < LOG_SERIES_THRESHOLD
+    # the log branch is evaluated on safe arguments where the series is used,
+    # so that autograd never sees 0/0
+    dl = torch.log(ap) - torch.log(am)
+    dl_safe = torch.where(small, torch.ones_like(dl), dl)
+    num_safe = torch.where(small, torch.ones_like(dl), ap - am)
+    big = num_safe / dl_safe
+    ser = (am + ap) / (2.0 * _series(f2))
+    return torch.where(small, ser, big)
+
+
+def inv_log_mean(am: torch.Tensor, ap: torch.Tensor) -> torch.Tensor:
+    """1/{a}_ln."""
+    f = (ap - am) / (ap + am)
+    f2 = f * f
+    small = f2 < LOG_SERIES_THRESHOLD
+    dl = torch.log(ap) - torch.log(am)
+    dl_safe = torch.where(small, torch.ones_like(dl), dl)
+    num_safe = torch.where(small, torch.ones_like(dl), ap - am)
+    big = dl_safe / num_safe
+    ser = 2.0 * _series(f2) / (am + ap)
+    return torch.where(small, ser, big)
+
+
+def ranocha_flux(um: torch.Tensor, up: torch.Tensor, n: torch.Tensor, gamma: float) -> torch.Tensor:
+    """Directional EC flux f#(U-, U+, n) = sum_m n_m f#_m (eq. ranocha_flux)."""
+    d = um.shape[-1] - 2
+    rm, vm, pm = prim(um, gamma)
+    rp, vp, pp = prim(up, gamma)
+    rho_ln = log_mean(rm, rp)
+    inv_rp_ln = inv_log_mean(rm / pm, rp / pp)       # 1 / {rho/p}_ln
+    vavg = 0.5 * (vm + vp)
+    pavg = 0.5 * (pm + pp)
+    vn = (vavg * n).sum(-1)
+    f_rho = rho_ln * vn
+    out = [f_rho]
+    for i in range(d):
+        out.append(f_rho * vavg[..., i] + pavg * n[..., i])
+    vmvp = (vm * vp).sum(-1)
+    fE = f_rho * (0.5 * vmvp + inv_rp_ln / (gamma - 1.0)) \
+        + 0.5 * (pm * (vp * n).sum(-1) + pp * (vm * n).sum(-1))
+    out.append(fE)
+    return torch.stack(out, -1)
+
+
+def chandrashekar_flux(um: torch.Tensor, up: torch.Tensor, n: torch.Tensor, gamma: float) -> torch.Tensor:
+    """Chandrashekar's EC flux with beta = rho/(2p): f_rho = {rho}_ln {v}.n,
+    f_rhov = f_rho {v} + {rho}/(2{beta}) n, energy closing Tadmor's condition."""
+    d = um.shape[-1] - 2
+    rm, vm, pm = prim(um, gamma)
+    rp, vp, pp = prim(up, gamma)
+    bm = rm / (2.0 * pm)
+    bp = rp / (2.0 * pp)
+    rho_ln = log_mean(rm, rp)
+    inv_b_ln = inv_log_mean(bm, bp)
+    vavg = 0.5 * (vm + vp)
+    phat = 0.5 * (rm + rp) / (bm + bp)              # {rho} / (2 {beta})
+    vn = (vavg * n).sum(-1)
+    f_rho = rho_ln * vn
+    out = [f_rho]
+    for i in range(d):
+        out.append(f_rho * vavg[..., i] + phat * n[..., i])
+    vmvp = (vm * vp).sum(-1)
+    fE = f_rho * (0.5 * vmvp + 0.5 * inv_b_ln / (gamma - 1.0)) + phat * vn
+    out.append(fE)
+    return torch.stack(out, -1)
+
+
+EC_FLUXES = {0: ranocha_flux, 1: chandrashekar_flux}
+
+
+def davis_speed(um, up, n, gamma):
+    """lambda of eq. (wave_speed); ties take the interior (-) branch."""
+    rm, vm, pm = prim(um, gamma)
+    rp, vp, pp = prim(up, gamma)
+    a = (vm * n).sum(-1).abs()
+    b = (vp * n).sum(-1).abs()
+    cm = torch.sqrt(gamma * pm / rm)
+    cp = torch.sqrt(gamma * pp / rp)
+    return torch.where(a >= b, a, b) + torch.where(cm >= cp, cm, cp)
+
+
+def interface_flux(um, up, n, gamma, ecflux: int, dissipation: int):
+    """f*(U-, U+, n) of eq. (num_flux) with unit normal n."""
+    f = EC_FLUXES[ecflux](um, up, n, gamma)
+    if dissipation:
+        lam = davis_speed(um, up, n, gamma)
+        f = f - 0.5 * lam[..., None] * (up - um)
+    return f
