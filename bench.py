@@ -1,0 +1,190 @@
+#!/usr/bin/env python3
+"""Benchmark of the entropy-stable modal DSEM residual on one MI355X.
+
+A step is one classical RK4 step on the workload (4 residual evaluations, each
+the whole path: entropy projection, flux differencing, facet correction,
+interface flux, weight-adjusted inverse; plus the stage combinations), with the
+state resident in HBM.  Prints one JSON line:
+
+  value     FP64 residual evaluations x DOF per second (DOF = elements x (d+2) x modes)
+  roofline  for the dominant kernel (the right-hand-side kernel K2): algorithmic
+            flops per launch / its average duration, from HIP events recorded
+            around every launch on its stream during the timed steps
+  cpu_baseline  the dense FP64 oracle on a bounded sample of the same workload
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import workloads as wl  # noqa: E402
+
+METRIC = "FP64 residual evals × DOF/s and flux-pairs/s vs FP64 roofline; VJP/forward cost"
+
+WORKLOADS = {
+    "vortex_tri_M64_p4": lambda: wl.vortex_tri(M=64, degree=4),
+    "vortex_tri_M64_p8": lambda: wl.vortex_tri(M=64, degree=8),
+    "tgv_tet_M16_p4": lambda: wl.tgv_tet(M=16, degree=4),
+    "tgv_tet_M16_p6": lambda: wl.tgv_tet(M=16, degree=6),
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run_gpu(name: str, steps: int, warmup: int):
+    import torch
+
+    import paper_2312_07874_amd as esd
+    from paper_2312_07874_amd import perfmodel as pm
+
+    wk = WORKLOADS[name]()
+    t0 = time.perf_counter()
+    plan = esd.Plan.from_workload(wk)
+    log(f"[bench] {name}: plan {plan.info.n_elements} elements, p={wk.degree}, "
+        f"{plan.info.n_dof} DOF, setup {time.perf_counter() - t0:.1f}s")
+    x = plan.node_coords().cpu().numpy()
+    u = plan.project(torch.tensor(wk.state(x), device="cuda").contiguous())
+    plan.sync_status()
+    dt = 1e-4
+    for _ in range(warmup):
+        plan.rk4(u, dt, 1)
+    torch.cuda.synchronize()
+    plan.sync_status()
+    plan.set_timing(True)
+    plan.get_timing()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.rk4(u, dt, 1)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    plan.set_timing(False)
+    k1_ms, k2_ms, nlaunch = plan.get_timing()
+    plan.sync_status()
+    info = plan.info
+    n_res = 4 * steps
+    d, p = wk.dim, wk.degree
+    k2_avg_s = k2_ms / nlaunch * 1e-3
+    k1_avg_s = k1_ms / nlaunch * 1e-3
+    fl = pm.k2_flops(d, p, wk.ecflux, wk.dissipation) * info.n_elements
+    by = pm.k2_bytes(d, p) * info.n_elements
+    t_fl = fl / (pm.PEAK_FP64_TFLOPS * 1e12)
+    t_by = by / (pm.PEAK_HBM_GBS * 1e9)
+    if t_fl >= t_by:
+        roof = {"bound": "alu", "achieved": fl / k2_avg_s / 1e12, "peak": pm.PEAK_FP64_TFLOPS, "unit": "TFLOP/s"}
+    else:
+        roof = {"bound": "hbm", "achieved": by / k2_avg_s / 1e9, "peak": pm.PEAK_HBM_GBS, "unit": "GB/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = "k_rhs (K2)"
+    roof["algorithmic_flops_per_launch"] = fl
+    roof["algorithmic_bytes_per_launch"] = by
+    roof["avg_launch_ms"] = k2_avg_s * 1e3
+    return {
+        "workload": name,
+        "elements": info.n_elements,
+        "degree": p,
+        "dof": info.n_dof,
+        "value": n_res * info.n_dof / elapsed,
+        "ms_per_step": elapsed / steps * 1e3,
+        "ms_per_residual_k1_k2": (k1_ms + k2_ms) / nlaunch,
+        "k1_avg_ms": k1_avg_s * 1e3,
+        "k2_avg_ms": k2_avg_s * 1e3,
+        "flux_pairs_per_s": n_res * info.flux_pairs_paper / elapsed,
+        "flux_pairs_distinct_per_s": n_res * info.flux_pairs_distinct / elapsed,
+        "roofline": roof,
+        "k1_flop_rate_tflops": pm.k1_flops(d, p) * info.n_elements / k1_avg_s / 1e12,
+    }
+
+
+def cpu_baseline(name: str, budget_s: float):
+    """The oracle (dense FP64, PyTorch CPU) timed on a bounded element sample."""
+    import torch
+
+    from oracle import residual as R
+
+    wk = WORKLOADS[name]()
+    t0 = time.perf_counter()
+    prob = R.setup(wk.mesh(), wk.degree, wk.warp, wk.gamma, wk.ecflux, wk.dissipation)
+    ut = R.project(prob, torch.tensor(wk.state(prob.geo.x_vol.numpy())))
+    log(f"[bench] oracle setup {time.perf_counter() - t0:.1f}s")
+    rng = np.random.default_rng(0)
+    order = rng.permutation(prob.ne)
+    chunk = 8
+    done, spent = 0, 0.0
+    while spent < budget_s and done < prob.ne:
+        el = order[done:done + chunk]
+        t = time.perf_counter()
+        R.residual(prob, ut, el)
+        spent += time.perf_counter() - t
+        done += len(el)
+    ndof = done * prob.nc * prob.ref.Np
+    return {"value": ndof / spent, "unit": "DOF*residual-evals/s", "cores": torch.get_num_threads(),
+            "kind": "oracle",
+            "sample": f"dense oracle residual of {done} of {prob.ne} elements of {name} "
+                      f"(each with its neighbours' entropy projection), {spent:.1f}s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="vortex_tri_M64_p4", choices=sorted(WORKLOADS))
+    ap.add_argument("--extra", default="vortex_tri_M64_p8,tgv_tet_M16_p4,tgv_tet_M16_p6",
+                    help="comma-separated additional workloads reported under 'extra' ('' for none)")
+    ap.add_argument("--extra-steps", type=int, default=3)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (see the sharding "
+              "design notes); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    main_res = run_gpu(args.workload, args.steps, args.warmup)
+    extra = []
+    for name in [s for s in args.extra.split(",") if s]:
+        if name != args.workload:
+            extra.append(run_gpu(name, args.extra_steps, 1))
+    cpu = None if args.no_cpu_baseline else cpu_baseline(args.workload, args.cpu_seconds)
+    out = {
+        "metric": METRIC,
+        "value": main_res["value"],
+        "unit": "DOF*residual-evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_res["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "elements": main_res["elements"], "degree": main_res["degree"],
+                   "dof": main_res["dof"],
+                   "step": "one classical RK4 step (4 residual evaluations + stage combinations)"},
+        "flux_pairs_per_s": main_res["flux_pairs_per_s"],
+        "flux_pairs_distinct_per_s": main_res["flux_pairs_distinct_per_s"],
+        "ms_per_residual_k1_k2": main_res["ms_per_residual_k1_k2"],
+        "roofline": main_res["roofline"],
+        "cpu_baseline": cpu,
+        "extra": extra,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

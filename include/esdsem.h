@@ -1,0 +1,170 @@
+/*
+ * esdsem.h -- C ABI of the MI355X (gfx950) library for the entropy-stable
+ * modal discontinuous spectral-element method on curved triangles and
+ * tetrahedra with tensor-product SBP operators in collapsed coordinates
+ * (Montoya & Zingg, "Efficient entropy-stable discontinuous spectral-element
+ * methods using tensor-product summation-by-parts operators on triangles and
+ * tetrahedra").
+ *
+ * Conventions for every call
+ *   - All floating point is IEEE binary64.
+ *   - Pointers named *_dev are device (HBM) pointers on the plan's device;
+ *     all other pointers are host pointers.
+ *   - The caller owns every state, output, workspace and checkpoint buffer;
+ *     the plan owns operator tables, geometry, connectivity and a status flag.
+ *   - Compute calls are asynchronous on the given HIP stream (pass 0 for the
+ *     null stream).  esd_plan_create, esd_plan_query, esd_plan_host_array and
+ *     esd_sync_status synchronise with the host.
+ *   - A non-zero status comes with a message from esd_last_error(); output
+ *     buffers are then unspecified.  No C++ exception crosses the ABI.
+ *
+ * Data layout (element-major, SoA inside an element)
+ *   modal state u~ : [element][variable][mode], N_c = dim+2 variables ordered
+ *                    (rho, rho v_1..rho v_dim, E); modes of the orthonormal PKD
+ *                    basis (Sec. 4.3) ordered by multi-index (a1, a2[, a3]) with
+ *                    a1 outermost and the last index innermost.
+ *   volume nodes   : tensor-product collapsed-coordinate nodes (Sec. 3),
+ *                    index a1 + Q a2 [+ Q^2 a3], Q = p+1.
+ *   Elements keep the order of the mesh description.  Each element's local
+ *   vertex order is normalised by the library: the largest global vertex id
+ *   becomes local vertex dim+1, in 3D the second largest becomes local vertex 3,
+ *   the other two follow in increasing id order, swapped if the affine map
+ *   would be orientation-reversing (Remark on connectivity, Sec. 6).
+ */
+#ifndef ESDSEM_H
+#define ESDSEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct esd_plan esd_plan;          /* opaque, owned by the library */
+
+typedef enum {
+  ESD_OK = 0,
+  ESD_EINVAL = -1,          /* bad argument (null pointer, size, enum)          */
+  ESD_EJACOBIAN = -2,       /* mapping Jacobian <= 0 at a node (eq. jacobian_positive) */
+  ESD_EADMISSIBLE = -3,     /* rho <= 0, p <= 0 or non-finite state seen by a kernel (sticky) */
+  ESD_EUNSUPPORTED = -4,    /* degree or dimension not built into the library   */
+  ESD_ENONCONFORMING = -5,  /* facet nodes of neighbours do not coincide (Assumption conformal) */
+  ESD_EHIP = -6,            /* a HIP runtime call failed                        */
+  ESD_ENOMEM = -7           /* device allocation failed                         */
+} esd_status;
+
+/* Entropy-conservative two-point flux used in the volume and facet terms. */
+typedef enum {
+  ESD_FLUX_RANOCHA = 0,       /* eq. (ranocha_flux), Sec. 7.2                    */
+  ESD_FLUX_CHANDRASHEKAR = 1  /* Chandrashekar's EC flux (cited in Sec. 4.6)     */
+} esd_ecflux;
+
+/* Interface dissipation of eq. (num_flux). */
+typedef enum {
+  ESD_DISS_NONE = 0,          /* entropy-conservative interface flux (Sec. 7.2)  */
+  ESD_DISS_LLF_DAVIS = 1      /* local Lax-Friedrichs with eq. (wave_speed)      */
+} esd_dissipation;
+
+/* Maps n points x_in [n][dim] (physical, unwarped) to x_out [n][dim].  Called
+ * on the host during esd_plan_create with the affine images of the mapping
+ * nodes of eq. (poly_mapping); NULL means no warp (affine elements). */
+typedef void (*esd_warp_fn)(int64_t n, const double* x_in, double* x_out, void* ctx);
+
+typedef struct {
+  int32_t dim;                         /* 2 (triangles) or 3 (tetrahedra)          */
+  int32_t degree;                      /* p = q = p_g for every element (Sec. 7.3) */
+  int64_t n_elements;
+  const int64_t* elem_vertex_ids;      /* host [n_elements][dim+1] global ids; periodic
+                                          images of a vertex share one id           */
+  const double* elem_vertex_coords;    /* host [n_elements][dim+1][dim] physical coords */
+  esd_warp_fn warp;                    /* may be NULL                               */
+  void* warp_ctx;
+} esd_mesh_desc;
+
+typedef struct {
+  double gamma;                        /* ratio of specific heats, > 1 (Sec. 7.1)  */
+  int32_t ecflux;                      /* esd_ecflux                               */
+  int32_t dissipation;                 /* esd_dissipation                          */
+} esd_scheme_desc;
+
+typedef struct {
+  int32_t dim, degree, n_vars, n_modes;   /* N_c, N_p* per element                  */
+  int32_t n_vol_nodes, n_facets, n_facet_nodes;   /* per element; n_facet_nodes per facet */
+  int64_t n_elements;
+  int64_t n_dof;                          /* n_elements * n_vars * n_modes          */
+  int64_t flux_pairs_paper;               /* per residual, count of eq. (num_fluxes) */
+  int64_t flux_pairs_distinct;            /* per residual, pairs evaluated by the line loops */
+  size_t workspace_bytes;                 /* esd_residual / esd_residual_vjp workspace */
+  size_t rk4_workspace_bytes;             /* esd_rk4 workspace                      */
+} esd_plan_info;
+
+/* Builds operators (Sec. 3, 4.3), geometry (Sec. 4.1-4.2, 4.5) and facet
+ * connectivity (Assumption conformal) on the host and uploads them to the
+ * current HIP device.  Synchronous.  Errors: ESD_EINVAL, ESD_EUNSUPPORTED,
+ * ESD_EJACOBIAN, ESD_ENONCONFORMING, ESD_ENOMEM, ESD_EHIP.  flags: bit 0 set =
+ * host-only plan (no device allocation; only esd_plan_query and
+ * esd_plan_host_array may be used with it). */
+esd_status esd_plan_create(const esd_mesh_desc* mesh, const esd_scheme_desc* scheme,
+                           uint32_t flags, esd_plan** out);
+void esd_plan_destroy(esd_plan* plan);
+esd_status esd_plan_query(const esd_plan* plan, esd_plan_info* out);
+
+/* Copies a host-side setup array of the plan into out (count doubles).  Names:
+ * "x_vol" [e][node][dim] physical volume-node coordinates, "J" [e][node]
+ * interpolated Jacobian (eq. jacobian_approx), "G" [e][node][l][m] metric terms
+ * (Sec. 4.2), "nJ" [e][facet][node][dim] = G^T nhat (eq. nanson), "Jf"
+ * [e][facet][node], "x_fac" [e][facet][node][dim], "nbr" [e][facet][node]
+ * neighbour element*facets*nodes + facet*nodes + node (as doubles).  Returns
+ * ESD_EINVAL for an unknown name or wrong count. */
+esd_status esd_plan_host_array(const esd_plan* plan, const char* name, double* out, int64_t count);
+
+/* Physical coordinates of the volume quadrature nodes, [element][node][dim]. */
+esd_status esd_node_coords(const esd_plan* plan, double* x_dev, void* stream);
+
+/* Weight-adjusted L2 projection of nodal values given at the volume quadrature
+ * nodes, u~ = Mt^{-1} V^T W J u (eqs. weight_adjusted_inverse, dudt_modal with
+ * M = I): u_nodal_dev [element][node][variable] -> u_dev [element][variable][mode]. */
+esd_status esd_project(const esd_plan* plan, const double* u_nodal_dev, double* u_dev, void* stream);
+
+/* Semi-discrete right-hand side du~/dt = Mt^{-1} V^T r(u~) of eq. (dudt_modal)
+ * with r of eq. (entropy_stable): entropy projection (eq. entropy_expansion),
+ * line-by-line flux differencing (eq. flux_differencing, Remark on lines),
+ * facet correction (eq. facet_correction), interface flux (eq. num_flux) and the
+ * weight-adjusted inverse (eq. matvec_dudt).  u_dev and dudt_dev are
+ * [element][variable][mode] and must not overlap; ws_dev holds
+ * info.workspace_bytes (256-byte aligned).  Admissibility violations set the
+ * sticky flag read by esd_sync_status. */
+esd_status esd_residual(const esd_plan* plan, const double* u_dev, double* dudt_dev,
+                        void* ws_dev, void* stream);
+
+/* nsteps steps of classical four-stage Runge-Kutta with step dt, in place on
+ * u_dev.  ws_dev holds info.rk4_workspace_bytes.  If stage_ckpt_dev is not NULL
+ * it receives the four stage inputs U1..U4 of every step, [4*nsteps][n_dof]. */
+esd_status esd_rk4(const esd_plan* plan, double* u_dev, double dt, int32_t nsteps,
+                   void* ws_dev, double* stage_ckpt_dev, void* stream);
+
+/* Vector-Jacobian product of the residual: grad_dev = (d du~/dt / d u~)^T vbar_dev,
+ * all [element][variable][mode].  ws_dev holds info.workspace_bytes. */
+esd_status esd_residual_vjp(const esd_plan* plan, const double* u_dev, const double* vbar_dev,
+                            double* grad_dev, void* ws_dev, void* stream);
+
+/* Synchronises the stream and returns ESD_EADMISSIBLE if any kernel since the
+ * last call saw an inadmissible state (the flag is cleared), else ESD_OK. */
+esd_status esd_sync_status(const esd_plan* plan, void* stream);
+
+/* Kernel timing for measurement: when enabled, every K1 (entropy projection)
+ * and K2 (right-hand side) launch of esd_residual / esd_rk4 is bracketed by
+ * HIP events on the stream it is launched on.  esd_plan_get_timing
+ * synchronises, returns the summed milliseconds and launch counts since the
+ * last reset, and resets them.  Timing is off by default. */
+esd_status esd_plan_set_timing(esd_plan* plan, int32_t enable);
+esd_status esd_plan_get_timing(esd_plan* plan, double* k1_ms, double* k2_ms, int64_t* launches);
+
+/* Thread-local message describing the last failure. */
+const char* esd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ESDSEM_H */

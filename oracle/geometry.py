@@ -13,10 +13,12 @@ Test infrastructure (see the package docstring).  Written from:
   * Assumption (conformal): matching facet nodes across every interface.
 
 Readings (listed in the design notes): mapping and curl-interpolation nodes are
-equispaced simplex nodes; the curl-form columns give G_{l m} for m = 1, 2, 3
+equispaced simplex nodes, whose Lagrange basis has a closed product form in
+barycentric coordinates; the curl-form columns give G_{l m} for m = 1, 2, 3
 (so that G equals the adjugate for affine maps); element-local coordinates
-(physical minus the element's first vertex) are used, which leaves G and J
-unchanged; orientation puts the largest global vertex id at local vertex d+1
+(physical minus the element's first vertex) are used and only the warp
+displacement is interpolated (interpolation reproduces the affine part), which
+leaves G and J unchanged; orientation puts the largest global vertex id at local vertex d+1
 and (in 3D) the second largest at local vertex 3, the other two in increasing
 id order, swapped if the affine Jacobian is negative.
 """
@@ -48,15 +50,46 @@ def equispaced(dim: int, N: int) -> torch.Tensor:
     return torch.tensor(pts, dtype=DT)
 
 
+def lattice_multi_indices(dim: int, N: int) -> torch.Tensor:
+    """Barycentric integer coordinates alpha (sum N) of the equispaced nodes, in
+    the order of equispaced(): alpha_k = N lambda_k, lambda_{k>=1} = (1+xi_k)/2."""
+    X = equispaced(dim, N)
+    lam = 0.5 * (1 + X)
+    lam0 = 1 - lam.sum(-1, keepdim=True)
+    return torch.round(N * torch.cat([lam0, lam], -1)).to(torch.int64)
+
+
 def lagrange_matrices(dim: int, N: int, X: torch.Tensor):
     """Interpolation matrix L[k, i] = l_i(X_k) and gradients dL[m][k, i] for the
-    degree-N Lagrange basis on equispaced nodes (through the PKD Vandermonde)."""
-    nodes = equispaced(dim, N)
-    Vn = pkd(dim, N, nodes)
-    VX = pkd(dim, N, X)
-    GX = pkd_grad(dim, N, X)
-    L = torch.linalg.solve(Vn.T, VX.T).T
-    dL = [torch.linalg.solve(Vn.T, GX[m].T).T for m in range(dim)]
+    degree-N Lagrange basis on equispaced nodes, from the closed-form product
+    formula l_a(lambda) = prod_k prod_{j<a_k} (N lambda_k - j)/(a_k - j)
+    (barycentric coordinates; no linear solve)."""
+    X = torch.as_tensor(X, dtype=DT)
+    A = lattice_multi_indices(dim, N)                       # [Nn, d+1]
+    lam = 0.5 * (1 + X)
+    lam = torch.cat([1 - lam.sum(-1, keepdim=True), lam], -1)   # [npts, d+1]
+    npts, nn = X.shape[0], A.shape[0]
+    fac = torch.ones((dim + 1, npts, nn), dtype=DT)          # per barycentric coordinate factor
+    dfac = torch.zeros((dim + 1, npts, nn), dtype=DT)        # its derivative w.r.t. lambda_k
+    for k in range(dim + 1):
+        ak = A[:, k]
+        t = N * lam[:, k:k + 1]                               # [npts, 1]
+        for j in range(N):
+            on = (ak > j)[None, :]                            # factor present for this node
+            f = torch.where(on, (t - j) / torch.where(on, (ak - j).to(DT), torch.ones(1, dtype=DT)), torch.ones(1, dtype=DT))
+            df = torch.where(on, N / torch.where(on, (ak - j).to(DT), torch.ones(1, dtype=DT)), torch.zeros(1, dtype=DT))
+            dfac[k] = dfac[k] * f + fac[k] * df
+            fac[k] = fac[k] * f
+    L = torch.prod(fac, 0)
+    dl = []                                                  # d l / d lambda_k
+    for k in range(dim + 1):
+        others = torch.ones((npts, nn), dtype=DT)
+        for kk in range(dim + 1):
+            if kk != k:
+                others = others * fac[kk]
+        dl.append(dfac[k] * others)
+    # lambda_0 = 1 - sum lambda_m, lambda_m = (1+xi_m)/2  ->  d/dxi_m = (dl_m - dl_0)/2
+    dL = [0.5 * (dl[m + 1] - dl[0]) for m in range(dim)]
     return L, dL
 
 
@@ -110,29 +143,42 @@ def build_geometry(ref: RefElement, elem_ids: np.ndarray, elem_x: np.ndarray, wa
     dim, p, q = ref.dim, ref.p, ref.q
     vids, vx = orient(np.asarray(elem_ids), np.asarray(elem_x, dtype=np.float64))
     ne = vids.shape[0]
-    # affine image of the mapping nodes, warped, then element-local coordinates
+    # affine image of the mapping nodes and the warp displacement delta there.
+    # x_h = X_aff + I[delta]: interpolation reproduces the affine part exactly,
+    # so only the displacement is interpolated; coordinates are element-local
+    # (relative to the first vertex), which leaves G and J unchanged.
     Xm = equispaced(dim, p)                             # mapping nodes (degree p_g = p)
     lam = _barycentric(dim, Xm)                         # [Ng, d+1]
     x_aff = np.einsum("gk,ekd->egd", lam.numpy(), vx)   # [Ne, Ng, d]
     x_map = warp(x_aff.reshape(-1, dim)).reshape(ne, -1, dim)
+    dlt = torch.tensor(x_map - x_aff, dtype=DT)         # [Ne, Ng, d]
     origin = vx[:, 0, :]
-    xl = torch.tensor(x_map - origin[:, None, :], dtype=DT)   # local coords [Ne, Ng, d]
     org = torch.tensor(origin, dtype=DT)
+    Aff = torch.tensor(0.5 * (vx[:, 1:, :] - vx[:, :1, :]).transpose(0, 2, 1), dtype=DT)   # [Ne, c, m] = dX_c/dxi_m
+
+    def X_aff(X):                                       # local affine coordinates at reference points
+        return torch.einsum("ecm,km->ekc", Aff, 1 + X)
 
     def grad_x(X):
         L, dL = lagrange_matrices(dim, p, X)
-        xv = torch.einsum("ki,eid->ekd", L, xl)
-        gx = torch.stack([torch.einsum("ki,eic->ekc", dL[m], xl) for m in range(dim)], -1)  # [Ne,k,c,m] = dx_c/dxi_m
-        return xv, gx
+        xv = X_aff(X) + torch.einsum("ki,eid->ekd", L, dlt)
+        gd = torch.stack([torch.einsum("ki,eic->ekc", dL[m], dlt) for m in range(dim)], -1)  # [Ne,k,c,m]
+        return xv, gd                                   # gradient of the displacement only
 
     # interpolated Jacobian (eq. jacobian_approx)
-    _, gx_map = grad_x(Xm)
-    Jmap = torch.linalg.det(gx_map)
+    _, gd_map = grad_x(Xm)
+    Jmap = torch.linalg.det(Aff[:, None] + gd_map)
     Lvol, _ = lagrange_matrices(dim, p, ref.xi)
     J = torch.einsum("ki,ei->ek", Lvol, Jmap)
 
+    def cross(a, b):
+        return torch.stack([a[..., 1] * b[..., 2] - a[..., 2] * b[..., 1],
+                            a[..., 2] * b[..., 0] - a[..., 0] * b[..., 2],
+                            a[..., 0] * b[..., 1] - a[..., 1] * b[..., 0]], -1)
+
     def metrics(X):
-        xv, gx = grad_x(X)
+        xv, gd = grad_x(X)
+        gx = Aff[:, None] + gd
         if dim == 2:
             G = torch.empty(gx.shape, dtype=DT)
             G[..., 0, 0] = gx[..., 1, 1]
@@ -140,12 +186,20 @@ def build_geometry(ref: RefElement, elem_ids: np.ndarray, elem_x: np.ndarray, wa
             G[..., 1, 0] = -gx[..., 1, 0]
             G[..., 1, 1] = gx[..., 0, 0]
             return xv, G
-        # conservative curl form with degree q+1 interpolants
+        # conservative curl form with degree q+1 interpolants, x = X + delta:
+        # x3 grad x2 = X3 grad X2 + (X3 grad d2 + d3 grad X2 + d3 grad d2); the
+        # first term is linear (interpolated exactly) with curl grad X3 x grad X2
         Xc = equispaced(3, q + 1)
-        xc, gc = grad_x(Xc)                  # [Ne, Nc, 3], [Ne, Nc, 3(comp), 3(ref)]
-        r1 = xc[..., 2:3] * gc[..., 1, :]    # x3 grad x2
-        r2 = xc[..., 2:3] * gc[..., 0, :]    # x3 grad x1
-        r3 = xc[..., 0:1] * gc[..., 1, :]    # x1 grad x2
+        Lc, dLc_ = lagrange_matrices(3, p, Xc)
+        Xa = X_aff(Xc)                                                    # [Ne, Nc, 3]
+        dc = torch.einsum("ki,eid->ekd", Lc, dlt)                         # delta at curl nodes
+        gdc = torch.stack([torch.einsum("ki,eic->ekc", dLc_[m], dlt) for m in range(3)], -1)  # [Ne,Nc,c,m]
+        a = [Aff[:, None, c, :] for c in range(3)]                        # grad X_c (constant rows)
+
+        def rvec(c1, c2):     # x_c1 grad x_c2 minus its affine-affine part
+            return Xa[..., c1:c1 + 1] * gdc[..., c2, :] + dc[..., c1:c1 + 1] * a[c2] + dc[..., c1:c1 + 1] * gdc[..., c2, :]
+
+        r1, r2, r3 = rvec(2, 1), rvec(2, 0), rvec(0, 1)
         _, dLc = lagrange_matrices(3, q + 1, X)
 
         def curl(r):
@@ -154,14 +208,17 @@ def build_geometry(ref: RefElement, elem_ids: np.ndarray, elem_x: np.ndarray, wa
                                 dr[2][..., 0] - dr[0][..., 2],
                                 dr[0][..., 1] - dr[1][..., 0]], -1)
 
-        c1, c2, c3 = -curl(r1), curl(r2), curl(r3)
+        npt = X.shape[0]
+        c1 = -(cross(a[2], a[1]).expand(-1, npt, -1) + curl(r1))
+        c2 = cross(a[2], a[0]).expand(-1, npt, -1) + curl(r2)
+        c3 = cross(a[0], a[1]).expand(-1, npt, -1) + curl(r3)
         G = torch.stack([c1, c2, c3], -1)    # G[..., l, m]: column m from the m-th curl
         return xv, G
 
     xv, G = metrics(ref.xi)
     x_vol = xv + org[:, None, :]
-    _, gx_vol = grad_x(ref.xi)
-    J_exact = torch.linalg.det(gx_vol)
+    _, gd_vol = grad_x(ref.xi)
+    J_exact = torch.linalg.det(Aff[:, None] + gd_vol)
     Gf, nJ, Jf, nn, xf = [], [], [], [], []
     for z in range(ref.Nf):
         xfz, Gz = metrics(ref.xi_f[z])

@@ -69,11 +69,16 @@ def project(prob: Problem, u_nodal: torch.Tensor, elems=None) -> torch.Tensor:
     nodes: u~ = Mt^{-1} V^T W J u -> [nE, Nc, Np]."""
     if elems is None:
         elems = torch.arange(prob.ne)
+    elems = torch.as_tensor(elems)
     V, w = prob.ref.V, prob.ref.w
-    J = prob.geo.J[elems]
-    b = torch.einsum("ki,ek,ekc->eci", V, w[None, :] * J, u_nodal)
-    A = wadj_inverse(prob, elems)
-    return torch.einsum("eij,ecj->eci", A, b)
+    out = []
+    for i in range(0, len(elems), 2048):
+        el = elems[i:i + 2048]
+        J = prob.geo.J[el]
+        b = torch.einsum("ki,ek,ekc->eci", V, w[None, :] * J, u_nodal[i:i + 2048])
+        A = wadj_inverse(prob, el)
+        out.append(torch.einsum("eij,ecj->eci", A, b))
+    return torch.cat(out, 0)
 
 
 def entropy_projection(prob: Problem, ut: torch.Tensor, elems) -> torch.Tensor:
@@ -288,3 +293,40 @@ def entropy_rate(prob: Problem, ut: torch.Tensor, dudt: torch.Tensor) -> torch.T
     Wu = ph.entropy_vars(u, prob.gamma)
     du = torch.einsum("ki,eci->ekc", V, dudt)
     return torch.einsum("k,ek,ekc,ekc->", w, prob.geo.J, Wu, du)
+
+
+def residual_magnitude(prob: Problem, ut: torch.Tensor, elems=None) -> torch.Tensor:
+    """The residual of eq. (entropy_stable) + eq. (dudt_modal) evaluated with the
+    absolute value of every term (|S|, |{G}|, |F|, |R^T B|, |R|, |Mt^{-1}|, |V|):
+    the scale of the summands, against which rounding differences between two
+    correct evaluations are measured when the residual itself cancels (e.g. a
+    large uniform pressure background).  -> [nE, Nc, Np]"""
+    ref, geo = prob.ref, prob.geo
+    d, g = ref.dim, prob.gamma
+    if elems is None:
+        elems = np.arange(prob.ne)
+    elems, need = _neighbourhood(prob, elems)
+    wt_need = entropy_projection(prob, ut, torch.as_tensor(need))
+    idx_of = {int(e): i for i, e in enumerate(need)}
+    wt = wt_need[[idx_of[int(e)] for e in elems]]
+    ubar = ph.cons_from_entropy(torch.einsum("ki,eci->ekc", ref.V, wt), g)
+    G = geo.G[elems]
+    F = _pair_fluxes(prob, ubar, ubar).abs()
+    r = torch.zeros_like(ubar)
+    for l in range(d):
+        Gavg = 0.5 * (G[:, :, None, l, :] + G[:, None, :, l, :]).abs()
+        r = r + torch.einsum("ij,eijc->eic", 2.0 * ref.S[l].abs(), torch.einsum("eijm,eijcm->eijc", Gavg, F))
+    del F
+    own, ext = _facet_states(prob, wt_need, idx_of, elems)
+    for z in range(ref.Nf):
+        Fz = _pair_fluxes(prob, ubar, own[z]).abs()
+        GnV = torch.einsum("l,eilm->eim", ref.nhat[z], G)
+        avg = 0.5 * (GnV[:, :, None, :] + geo.nJ[z][elems][:, None, :, :]).abs()
+        RtB = (ref.R[z].T @ torch.diag(ref.w_f[z])).abs()
+        C = RtB[None, :, :, None] * torch.einsum("eijm,eijcm->eijc", avg, Fz)
+        fstar = ph.interface_flux(own[z], ext[z], geo.n[z][elems], g, prob.ecflux, prob.dissipation).abs()
+        s = (ref.w_f[z][None, :, None] * geo.Jf[z][elems][..., None]) * fstar + C.sum(1)
+        r = r + C.sum(2) + torch.einsum("ji,ejc->eic", ref.R[z].abs(), s)
+    A = wadj_inverse(prob, torch.as_tensor(elems)).abs()
+    b = torch.einsum("ki,ekc->eci", ref.V.abs(), r)
+    return torch.einsum("eij,ecj->eci", A, b)

@@ -1,0 +1,247 @@
+"""Python binding of the esdsem C ABI (include/esdsem.h).
+
+Argument marshalling only: every step of the residual, RK4 and VJP runs in the
+HIP library libesdsem.so built in this directory (``python
+paper_2312_07874_amd/build.py``).  Device buffers are torch CUDA (HIP) tensors;
+streams are torch's current stream.  Importing this module fails loudly if the
+library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Callable, Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libesdsem.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_2312_07874_amd/build.py`")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+ESD_OK = 0
+STATUS = {0: "ESD_OK", -1: "ESD_EINVAL", -2: "ESD_EJACOBIAN", -3: "ESD_EADMISSIBLE", -4: "ESD_EUNSUPPORTED",
+          -5: "ESD_ENONCONFORMING", -6: "ESD_EHIP", -7: "ESD_ENOMEM"}
+
+FLUX_RANOCHA, FLUX_CHANDRASHEKAR = 0, 1
+DISS_NONE, DISS_LLF_DAVIS = 0, 1
+
+WARP_FN = ctypes.CFUNCTYPE(None, ctypes.c_int64, ctypes.POINTER(ctypes.c_double),
+                           ctypes.POINTER(ctypes.c_double), ctypes.c_void_p)
+
+
+class _MeshDesc(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("degree", ctypes.c_int32), ("n_elements", ctypes.c_int64),
+                ("elem_vertex_ids", ctypes.POINTER(ctypes.c_int64)),
+                ("elem_vertex_coords", ctypes.POINTER(ctypes.c_double)),
+                ("warp", WARP_FN), ("warp_ctx", ctypes.c_void_p)]
+
+
+class _SchemeDesc(ctypes.Structure):
+    _fields_ = [("gamma", ctypes.c_double), ("ecflux", ctypes.c_int32), ("dissipation", ctypes.c_int32)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("degree", ctypes.c_int32), ("n_vars", ctypes.c_int32),
+                ("n_modes", ctypes.c_int32), ("n_vol_nodes", ctypes.c_int32), ("n_facets", ctypes.c_int32),
+                ("n_facet_nodes", ctypes.c_int32), ("n_elements", ctypes.c_int64), ("n_dof", ctypes.c_int64),
+                ("flux_pairs_paper", ctypes.c_int64), ("flux_pairs_distinct", ctypes.c_int64),
+                ("workspace_bytes", ctypes.c_size_t), ("rk4_workspace_bytes", ctypes.c_size_t)]
+
+
+_vp = ctypes.c_void_p
+_c = ctypes.c_int
+EXPORTS = {
+    "esd_plan_create": (_c, [ctypes.POINTER(_MeshDesc), ctypes.POINTER(_SchemeDesc), ctypes.c_uint32,
+                             ctypes.POINTER(_vp)]),
+    "esd_plan_destroy": (None, [_vp]),
+    "esd_plan_query": (_c, [_vp, ctypes.POINTER(PlanInfo)]),
+    "esd_plan_host_array": (_c, [_vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int64]),
+    "esd_node_coords": (_c, [_vp, _vp, _vp]),
+    "esd_project": (_c, [_vp, _vp, _vp, _vp]),
+    "esd_residual": (_c, [_vp, _vp, _vp, _vp, _vp]),
+    "esd_rk4": (_c, [_vp, _vp, ctypes.c_double, ctypes.c_int32, _vp, _vp, _vp]),
+    "esd_residual_vjp": (_c, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "esd_sync_status": (_c, [_vp, _vp]),
+    "esd_plan_set_timing": (_c, [_vp, ctypes.c_int32]),
+    "esd_plan_get_timing": (_c, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                 ctypes.POINTER(ctypes.c_int64)]),
+    "esd_last_error": (ctypes.c_char_p, []),
+}
+for _name, (_res, _args) in EXPORTS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+class EsdError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        msg = _lib.esd_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _check(rc: int, where: str):
+    if rc != ESD_OK:
+        raise EsdError(rc, where)
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _stream():
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+class Plan:
+    """A mesh + scheme set up on the device (esd_plan_create)."""
+
+    def __init__(self, dim: int, degree: int, elem_vertex_ids, elem_vertex_coords,
+                 warp: Optional[Callable[[np.ndarray], np.ndarray]] = None, gamma: float = 1.4,
+                 ecflux: int = FLUX_RANOCHA, dissipation: int = DISS_LLF_DAVIS, host_only: bool = False):
+        self._ids = np.ascontiguousarray(elem_vertex_ids, dtype=np.int64)
+        self._xy = np.ascontiguousarray(elem_vertex_coords, dtype=np.float64)
+        ne = self._ids.shape[0]
+        if warp is not None:
+            def _cb(n, xin, xout, ctx, _dim=dim, _warp=warp):
+                a = np.ctypeslib.as_array(xin, shape=(n * _dim,)).reshape(n, _dim)
+                b = np.ctypeslib.as_array(xout, shape=(n * _dim,)).reshape(n, _dim)
+                b[...] = _warp(a.copy())
+            self._cb = WARP_FN(_cb)
+        else:
+            self._cb = WARP_FN()
+        desc = _MeshDesc(dim, degree, ne, self._ids.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                         self._xy.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), self._cb, None)
+        sch = _SchemeDesc(gamma, ecflux, dissipation)
+        h = _vp()
+        _check(_lib.esd_plan_create(ctypes.byref(desc), ctypes.byref(sch), 1 if host_only else 0, ctypes.byref(h)),
+               "esd_plan_create")
+        self._h = h
+        self.info = PlanInfo()
+        _check(_lib.esd_plan_query(self._h, ctypes.byref(self.info)), "esd_plan_query")
+        self.dim, self.degree, self.gamma = dim, degree, gamma
+        self._ws = None
+
+    @classmethod
+    def from_workload(cls, wl, degree=None, host_only=False, **kw):
+        mesh = wl.mesh()
+        return cls(mesh.dim, degree or wl.degree, mesh.elem_vertex_ids, mesh.elem_vertex_coords,
+                   None if wl.warp.__name__ == "warp_none" else wl.warp, wl.gamma,
+                   kw.get("ecflux", wl.ecflux), kw.get("dissipation", wl.dissipation), host_only)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _lib.esd_plan_destroy(h)
+            self._h = None
+
+    # ---- shapes
+    @property
+    def state_shape(self):
+        return (self.info.n_elements, self.info.n_vars, self.info.n_modes)
+
+    @property
+    def nodal_shape(self):
+        return (self.info.n_elements, self.info.n_vol_nodes, self.info.n_vars)
+
+    def host_array(self, name: str) -> np.ndarray:
+        i = self.info
+        nf, nq, d = i.n_facets * i.n_facet_nodes, i.n_vol_nodes, i.dim
+        shapes = {"x_vol": (i.n_elements, nq, d), "J": (i.n_elements, nq), "G": (i.n_elements, nq, d, d),
+                  "nJ": (i.n_elements, nf, d), "Jf": (i.n_elements, nf), "x_fac": (i.n_elements, nf, d),
+                  "nbr": (i.n_elements, nf)}
+        out = np.empty(shapes[name], dtype=np.float64)
+        _check(_lib.esd_plan_host_array(self._h, name.encode(), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                        out.size), "esd_plan_host_array")
+        return out
+
+    # ---- device calls
+    def workspace(self, rk4: bool = False):
+        import torch
+        nbytes = self.info.rk4_workspace_bytes if rk4 else self.info.workspace_bytes
+        if self._ws is None or self._ws.numel() * 8 < nbytes:
+            self._ws = torch.empty((nbytes + 7) // 8, dtype=torch.float64, device="cuda")
+        return self._ws
+
+    def node_coords(self):
+        import torch
+        x = torch.empty((self.info.n_elements, self.info.n_vol_nodes, self.dim), dtype=torch.float64, device="cuda")
+        _check(_lib.esd_node_coords(self._h, _ptr(x), _stream()), "esd_node_coords")
+        return x
+
+    def project(self, u_nodal):
+        import torch
+        assert u_nodal.is_cuda and u_nodal.dtype == torch.float64 and u_nodal.is_contiguous()
+        assert tuple(u_nodal.shape) == self.nodal_shape
+        out = torch.empty(self.state_shape, dtype=torch.float64, device=u_nodal.device)
+        _check(_lib.esd_project(self._h, _ptr(u_nodal), _ptr(out), _stream()), "esd_project")
+        return out
+
+    def residual(self, u, out=None):
+        import torch
+        assert u.is_cuda and u.dtype == torch.float64 and u.is_contiguous()
+        assert tuple(u.shape) == self.state_shape
+        if out is None:
+            out = torch.empty_like(u)
+        _check(_lib.esd_residual(self._h, _ptr(u), _ptr(out), _ptr(self.workspace()), _stream()), "esd_residual")
+        return out
+
+    def rk4(self, u, dt: float, nsteps: int, ckpt=None):
+        """In place on u; ckpt (optional) receives the stage inputs [4*nsteps, *state]."""
+        assert u.is_contiguous() and tuple(u.shape) == self.state_shape
+        _check(_lib.esd_rk4(self._h, _ptr(u), float(dt), int(nsteps), _ptr(self.workspace(rk4=True)),
+                            _ptr(ckpt), _stream()), "esd_rk4")
+        return u
+
+    def vjp(self, u, vbar, out=None):
+        import torch
+        assert u.is_contiguous() and vbar.is_contiguous()
+        if out is None:
+            out = torch.empty_like(u)
+        _check(_lib.esd_residual_vjp(self._h, _ptr(u), _ptr(vbar), _ptr(out), _ptr(self.workspace()), _stream()),
+               "esd_residual_vjp")
+        return out
+
+    def set_timing(self, enable: bool):
+        _check(_lib.esd_plan_set_timing(self._h, 1 if enable else 0), "esd_plan_set_timing")
+
+    def get_timing(self):
+        """(k1_ms, k2_ms, launches) summed since the last call (HIP events)."""
+        a, b, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+        _check(_lib.esd_plan_get_timing(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(n)),
+               "esd_plan_get_timing")
+        return a.value, b.value, n.value
+
+    def sync_status(self):
+        _check(_lib.esd_sync_status(self._h, _stream()), "esd_sync_status")
+
+
+def _autograd_residual():
+    import torch
+
+    class Residual(torch.autograd.Function):
+        """du~/dt = R(u~) with the hand-written adjoint kernel as backward."""
+
+        @staticmethod
+        def forward(ctx, u, plan):
+            ctx.plan = plan
+            ctx.save_for_backward(u)
+            return plan.residual(u.contiguous())
+
+        @staticmethod
+        def backward(ctx, g):
+            (u,) = ctx.saved_tensors
+            return ctx.plan.vjp(u.contiguous(), g.contiguous()), None
+
+    return Residual
+
+
+def residual(u, plan: Plan):
+    """Differentiable residual (torch.autograd)."""
+    return _autograd_residual().apply(u, plan)

@@ -1,0 +1,389 @@
+// C ABI of the library (declared in include/esdsem.h).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <exception>
+#include <limits>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "esdsem.h"
+#include "plan.hpp"
+
+namespace {
+thread_local std::string g_err;
+
+esd_status fail(esd_status s, const std::string& m) {
+  g_err = m;
+  return s;
+}
+
+size_t align256(size_t n) { return (n + 255) / 256 * 256; }
+
+#define HIP_TRY(x)                                                                   \
+  do {                                                                               \
+    hipError_t e_ = (x);                                                             \
+    if (e_ != hipSuccess) return fail(ESD_EHIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+template <typename T>
+esd_status upload(T** dst, const std::vector<T>& src) {
+  if (hipMalloc((void**)dst, src.size() * sizeof(T)) != hipSuccess) return fail(ESD_ENOMEM, "hipMalloc failed");
+  HIP_TRY(hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+  return ESD_OK;
+}
+
+void free_device(esd_plan* p) {
+  if (p->d_tables) (void)hipFree(p->d_tables);
+  if (p->d_gvol) (void)hipFree(p->d_gvol);
+  if (p->d_gfac) (void)hipFree(p->d_gfac);
+  if (p->d_conn) (void)hipFree(p->d_conn);
+  if (p->d_xvol) (void)hipFree(p->d_xvol);
+  if (p->d_flag) (void)hipFree(p->d_flag);
+  p->d_tables = p->d_gvol = p->d_gfac = p->d_xvol = nullptr;
+  p->d_conn = nullptr;
+  p->d_flag = nullptr;
+}
+
+// Scaled metric rows for the line families (see plan.hpp), w J and w / J.
+std::vector<double> pack_gvol(const esd_plan& P) {
+  const esd::RefTables& R = P.ref;
+  const int dim = P.dim, NQ = R.NQ, Q = R.Q, NGV = esd::ngv(dim);
+  std::vector<double> g((size_t)P.ne * NGV * NQ);
+  for (int64_t e = 0; e < P.ne; ++e)
+    for (int k = 0; k < NQ; ++k) {
+      const double* G = &P.geo.G[((size_t)e * NQ + k) * dim * dim];   // G[l*dim + m]
+      double* o = &g[(size_t)e * NGV * NQ];
+      const double J = P.geo.J[(size_t)e * NQ + k];
+      if (dim == 2) {
+        const int a1 = k % Q, a2 = k / Q;
+        const double w1 = R.wl[a1], w2 = R.wl[a2];
+        for (int m = 0; m < 2; ++m) {
+          o[(0 + m) * NQ + k] = w2 * G[0 * 2 + m];
+          o[(2 + m) * NQ + k] = 0.5 * w2 * G[1 * 2 + m];
+          o[(4 + m) * NQ + k] = 0.5 * w1 * G[1 * 2 + m];
+        }
+      } else {
+        const int a1 = k % Q, a2 = (k / Q) % Q, a3 = k / (Q * Q);
+        const double w1 = R.wl[a1], w2 = R.wl[a2], w3 = R.wj[a3], e2 = R.xl[a2];
+        for (int m = 0; m < 3; ++m) {
+          o[(0 + m) * NQ + k] = 0.5 * w2 * w3 * G[0 * 3 + m];
+          o[(3 + m) * NQ + k] = 0.25 * w2 * w3 * (G[1 * 3 + m] + G[2 * 3 + m]);
+          o[(6 + m) * NQ + k] = 0.25 * w1 * w3 * G[1 * 3 + m];
+          o[(9 + m) * NQ + k] = 0.125 * w1 * w3 * G[2 * 3 + m];
+          o[(12 + m) * NQ + k] = 0.125 * w1 * w2 * (1.0 - e2) * G[2 * 3 + m];
+        }
+      }
+      o[(NGV - 2) * NQ + k] = R.w[k] * J;
+      o[(NGV - 1) * NQ + k] = R.w[k] / J;
+    }
+  return g;
+}
+}  // namespace
+
+extern "C" {
+
+const char* esd_last_error(void) { return g_err.c_str(); }
+
+esd_status esd_plan_create(const esd_mesh_desc* mesh, const esd_scheme_desc* scheme, uint32_t flags,
+                           esd_plan** out) {
+  if (!out) return fail(ESD_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!mesh || !scheme) return fail(ESD_EINVAL, "mesh or scheme is NULL");
+  if (mesh->dim != 2 && mesh->dim != 3) return fail(ESD_EUNSUPPORTED, "dim must be 2 or 3");
+  if (!esd::degree_supported(mesh->dim, mesh->degree))
+    return fail(ESD_EUNSUPPORTED, "degree " + std::to_string(mesh->degree) + " not built for dim " +
+                                      std::to_string(mesh->dim));
+  if (mesh->n_elements <= 0 || !mesh->elem_vertex_ids || !mesh->elem_vertex_coords)
+    return fail(ESD_EINVAL, "empty mesh");
+  if (!(scheme->gamma > 1.0) || scheme->ecflux < 0 || scheme->ecflux > 1 || scheme->dissipation < 0 ||
+      scheme->dissipation > 1)
+    return fail(ESD_EINVAL, "bad scheme parameters");
+  esd_plan* P = new (std::nothrow) esd_plan();
+  if (!P) return fail(ESD_ENOMEM, "host allocation failed");
+  try {
+    P->dim = mesh->dim;
+    P->p = mesh->degree;
+    P->nc = mesh->dim + 2;
+    P->ne = mesh->n_elements;
+    P->scheme.gamma = scheme->gamma;
+    P->scheme.gm1_inv = 1.0 / (scheme->gamma - 1.0);
+    P->scheme.ecflux = scheme->ecflux;
+    P->scheme.dissipation = scheme->dissipation;
+    P->host_only = (flags & 1u) != 0;
+    P->ref = esd::build_ref_tables(P->dim, P->p);
+    std::string msg;
+    const int rc = esd::build_geometry(P->ref, P->ne, mesh->elem_vertex_ids, mesh->elem_vertex_coords,
+                                       (esd::warp_fn)mesh->warp, mesh->warp_ctx, P->geo, msg);
+    if (rc != 0) {
+      delete P;
+      return fail((esd_status)rc, msg);
+    }
+    const esd::RefTables& R = P->ref;
+    const size_t ndof = (size_t)P->ne * P->nc * R.NP;
+    P->ws_bytes = align256(ndof * sizeof(double)) + align256((size_t)P->ne * P->nc * R.NFQ * sizeof(double));
+    P->rk_ws_bytes = P->ws_bytes + 3 * align256(ndof * sizeof(double));
+    if (P->host_only) {
+      *out = P;
+      return ESD_OK;
+    }
+    if (hipGetDevice(&P->device) != hipSuccess) {
+      delete P;
+      return fail(ESD_EHIP, "no HIP device");
+    }
+    // reference tables, packed
+    std::vector<double> tb;
+    std::vector<size_t> off;
+    auto add = [&](const std::vector<double>& v) {
+      off.push_back(tb.size());
+      tb.insert(tb.end(), v.begin(), v.end());
+    };
+    add(R.psi1);
+    add(R.psi2);
+    add(R.psi3);
+    add(R.lgm1);
+    add(R.lgp1);
+    add(R.gjm1);
+    add(R.I42);
+    add(R.A);
+    add(R.wf);
+    add(R.wl);
+    add(R.wj);
+    add(R.xl);
+    esd_status st = upload(&P->d_tables, tb);
+    if (st != ESD_OK) {
+      free_device(P);
+      delete P;
+      return st;
+    }
+    const double* b = P->d_tables;
+    P->tab = {b + off[0], b + off[1], b + off[2], b + off[3], b + off[4],  b + off[5],
+              b + off[6], b + off[7], b + off[8], b + off[9], b + off[10], b + off[11]};
+    // geometry
+    st = upload(&P->d_gvol, pack_gvol(*P));
+    const int NFQ = R.NFQ, NQF = R.NQF, dim = P->dim, NF = R.NF;
+    std::vector<double> gf((size_t)P->ne * (dim + 1) * NFQ);
+    std::vector<int32_t> conn((size_t)P->ne * NFQ);
+    const int64_t stride = (int64_t)P->nc * NFQ;
+    if ((int64_t)P->ne * stride >= std::numeric_limits<int32_t>::max()) {
+      free_device(P);
+      delete P;
+      return fail(ESD_EUNSUPPORTED, "mesh too large for 32-bit facet addressing");
+    }
+    for (int64_t e = 0; e < P->ne; ++e)
+      for (int j = 0; j < NFQ; ++j) {
+        for (int m = 0; m < dim; ++m) gf[((size_t)e * (dim + 1) + m) * NFQ + j] = P->geo.nJ[((size_t)e * NFQ + j) * dim + m];
+        gf[((size_t)e * (dim + 1) + dim) * NFQ + j] = P->geo.Jf[(size_t)e * NFQ + j];
+        const int64_t nb = P->geo.nbr[(size_t)e * NFQ + j];
+        const int64_t ne_ = nb / NFQ, rem = nb % NFQ;
+        const int64_t nf = rem / NQF, nn = rem % NQF;
+        (void)NF;
+        conn[(size_t)e * NFQ + j] = (int32_t)(ne_ * stride + nf * NQF + nn);
+      }
+    if (st == ESD_OK) st = upload(&P->d_gfac, gf);
+    if (st == ESD_OK) st = upload(&P->d_conn, conn);
+    if (st == ESD_OK) st = upload(&P->d_xvol, P->geo.x_vol);
+    if (st == ESD_OK) st = upload(&P->d_flag, std::vector<int>(1, 0));
+    if (st != ESD_OK) {
+      free_device(P);
+      delete P;
+      return st;
+    }
+  } catch (const std::exception& ex) {
+    free_device(P);
+    delete P;
+    return fail(ESD_ENOMEM, std::string("setup failed: ") + ex.what());
+  }
+  *out = P;
+  return ESD_OK;
+}
+
+void esd_plan_destroy(esd_plan* plan) {
+  if (!plan) return;
+  for (hipEvent_t e : plan->ev) (void)hipEventDestroy(e);
+  for (hipEvent_t e : plan->ev_pool) (void)hipEventDestroy(e);
+  free_device(plan);
+  delete plan;
+}
+
+esd_status esd_plan_set_timing(esd_plan* P, int32_t enable) {
+  if (!P) return fail(ESD_EINVAL, "plan is NULL");
+  P->timing = enable != 0;
+  return ESD_OK;
+}
+
+esd_status esd_plan_get_timing(esd_plan* P, double* k1_ms, double* k2_ms, int64_t* launches) {
+  if (!P || !k1_ms || !k2_ms || !launches) return fail(ESD_EINVAL, "NULL argument");
+  *k1_ms = *k2_ms = 0.0;
+  *launches = 0;
+  if (P->ev.size() % 3 != 0) return fail(ESD_EHIP, "incomplete timing record");
+  for (size_t i = 0; i < P->ev.size(); i += 3) {
+    HIP_TRY(hipEventSynchronize(P->ev[i + 2]));
+    float a = 0.f, b = 0.f;
+    HIP_TRY(hipEventElapsedTime(&a, P->ev[i], P->ev[i + 1]));
+    HIP_TRY(hipEventElapsedTime(&b, P->ev[i + 1], P->ev[i + 2]));
+    *k1_ms += a;
+    *k2_ms += b;
+    *launches += 1;
+  }
+  P->ev_pool.insert(P->ev_pool.end(), P->ev.begin(), P->ev.end());
+  P->ev.clear();
+  return ESD_OK;
+}
+
+esd_status esd_plan_query(const esd_plan* P, esd_plan_info* out) {
+  if (!P || !out) return fail(ESD_EINVAL, "NULL argument");
+  const esd::RefTables& R = P->ref;
+  std::memset(out, 0, sizeof(*out));
+  out->dim = P->dim;
+  out->degree = P->p;
+  out->n_vars = P->nc;
+  out->n_modes = R.NP;
+  out->n_vol_nodes = R.NQ;
+  out->n_facets = R.NF;
+  out->n_facet_nodes = R.NQF;
+  out->n_elements = P->ne;
+  out->n_dof = P->ne * P->nc * R.NP;
+  const int64_t Q = R.Q;
+  int64_t paper, distinct;
+  if (P->dim == 2) {
+    paper = 3 * Q * Q * (Q + 1) / 2;          // 1.5 (q+1)^2 (q+2)
+    distinct = Q * Q * (Q + 2);
+  } else {
+    paper = 4 * Q * Q * Q * Q;
+    distinct = Q * Q * Q * (5 * Q + 3) / 2;   // (q+1)^3 (2.5 q + 4)
+  }
+  out->flux_pairs_paper = paper * P->ne;
+  out->flux_pairs_distinct = distinct * P->ne;
+  out->workspace_bytes = P->ws_bytes;
+  out->rk4_workspace_bytes = P->rk_ws_bytes;
+  return ESD_OK;
+}
+
+esd_status esd_plan_host_array(const esd_plan* P, const char* name, double* out, int64_t count) {
+  if (!P || !name || !out) return fail(ESD_EINVAL, "NULL argument");
+  const std::string n(name);
+  if (n == "nbr") {
+    if ((int64_t)P->geo.nbr.size() != count) return fail(ESD_EINVAL, "count mismatch for nbr");
+    for (int64_t i = 0; i < count; ++i) out[i] = (double)P->geo.nbr[i];
+    return ESD_OK;
+  }
+  const std::vector<double>* v = nullptr;
+  if (n == "x_vol") v = &P->geo.x_vol;
+  else if (n == "J") v = &P->geo.J;
+  else if (n == "G") v = &P->geo.G;
+  else if (n == "nJ") v = &P->geo.nJ;
+  else if (n == "Jf") v = &P->geo.Jf;
+  else if (n == "x_fac") v = &P->geo.x_fac;
+  if (!v) return fail(ESD_EINVAL, "unknown array " + n);
+  if ((int64_t)v->size() != count) return fail(ESD_EINVAL, "count mismatch for " + n);
+  std::memcpy(out, v->data(), v->size() * sizeof(double));
+  return ESD_OK;
+}
+
+static esd_status check_device(const esd_plan* P) {
+  if (!P) return fail(ESD_EINVAL, "plan is NULL");
+  if (P->host_only) return fail(ESD_EINVAL, "host-only plan");
+  return ESD_OK;
+}
+
+esd_status esd_node_coords(const esd_plan* P, double* x_dev, void* stream) {
+  esd_status st = check_device(P);
+  if (st != ESD_OK) return st;
+  if (!x_dev) return fail(ESD_EINVAL, "x_dev is NULL");
+  HIP_TRY(hipMemcpyAsync(x_dev, P->d_xvol, P->geo.x_vol.size() * sizeof(double), hipMemcpyDeviceToDevice,
+                         (hipStream_t)stream));
+  return ESD_OK;
+}
+
+esd_status esd_project(const esd_plan* P, const double* u_nodal_dev, double* u_dev, void* stream) {
+  esd_status st = check_device(P);
+  if (st != ESD_OK) return st;
+  if (!u_nodal_dev || !u_dev) return fail(ESD_EINVAL, "NULL buffer");
+  const int rc = esd::launch_project(P, u_nodal_dev, u_dev, (hipStream_t)stream);
+  if (rc < 0) return fail(ESD_EUNSUPPORTED, "degree not built");
+  if (rc != 0) return fail(ESD_EHIP, std::string("launch failed: ") + hipGetErrorString((hipError_t)rc));
+  return ESD_OK;
+}
+
+static esd::Workspace split_ws(const esd_plan* P, void* ws) {
+  const size_t ndof = (size_t)P->ne * P->nc * P->ref.NP;
+  esd::Workspace w;
+  w.wt = (double*)ws;
+  w.wf = (double*)((char*)ws + align256(ndof * sizeof(double)));
+  return w;
+}
+
+esd_status esd_residual(const esd_plan* P, const double* u_dev, double* dudt_dev, void* ws_dev, void* stream) {
+  esd_status st = check_device(P);
+  if (st != ESD_OK) return st;
+  if (!u_dev || !dudt_dev || !ws_dev) return fail(ESD_EINVAL, "NULL buffer");
+  if ((const void*)u_dev == (const void*)dudt_dev) return fail(ESD_EINVAL, "u and dudt overlap");
+  if (((uintptr_t)ws_dev) % 256 != 0) return fail(ESD_EINVAL, "workspace not 256-byte aligned");
+  const int rc = esd::launch_residual(P, u_dev, dudt_dev, split_ws(P, ws_dev), (hipStream_t)stream);
+  if (rc < 0) return fail(ESD_EUNSUPPORTED, "degree not built");
+  if (rc != 0) return fail(ESD_EHIP, std::string("launch failed: ") + hipGetErrorString((hipError_t)rc));
+  return ESD_OK;
+}
+
+esd_status esd_rk4(const esd_plan* P, double* u_dev, double dt, int32_t nsteps, void* ws_dev,
+                   double* stage_ckpt_dev, void* stream) {
+  esd_status st = check_device(P);
+  if (st != ESD_OK) return st;
+  if (!u_dev || !ws_dev || nsteps < 0 || !std::isfinite(dt)) return fail(ESD_EINVAL, "bad argument");
+  if (((uintptr_t)ws_dev) % 256 != 0) return fail(ESD_EINVAL, "workspace not 256-byte aligned");
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t n = P->ne * P->nc * P->ref.NP;
+  const size_t nb = align256((size_t)n * sizeof(double));
+  esd::Workspace w = split_ws(P, ws_dev);
+  double* k = (double*)((char*)ws_dev + P->ws_bytes);
+  double* U = (double*)((char*)ws_dev + P->ws_bytes + nb);
+  double* acc = (double*)((char*)ws_dev + P->ws_bytes + 2 * nb);
+  const double ca[4] = {dt / 6.0, dt / 3.0, dt / 3.0, dt / 6.0};
+  const double cu[4] = {0.5 * dt, 0.5 * dt, dt, 0.0};
+  for (int step = 0; step < nsteps; ++step) {
+    for (int stg = 0; stg < 4; ++stg) {
+      const double* in = (stg == 0) ? u_dev : U;
+      if (stage_ckpt_dev)
+        HIP_TRY(hipMemcpyAsync(stage_ckpt_dev + ((int64_t)4 * step + stg) * n, in, n * sizeof(double),
+                               hipMemcpyDeviceToDevice, s));
+      int rc = esd::launch_residual(P, in, k, w, s);
+      if (rc != 0) return fail(ESD_EHIP, "residual launch failed");
+      if (stg < 3)
+        rc = esd::launch_rk_stage(acc, U, u_dev, k, ca[stg], cu[stg], stg == 0, n, s);
+      else
+        rc = esd::launch_axpy(u_dev, acc, ca[3], k, n, s);
+      if (rc != 0) return fail(ESD_EHIP, "stage launch failed");
+    }
+  }
+  return ESD_OK;
+}
+
+esd_status esd_residual_vjp(const esd_plan* P, const double* u_dev, const double* vbar_dev, double* grad_dev,
+                            void* ws_dev, void* stream) {
+  esd_status st = check_device(P);
+  if (st != ESD_OK) return st;
+  if (!u_dev || !vbar_dev || !grad_dev || !ws_dev) return fail(ESD_EINVAL, "NULL buffer");
+  const int rc = esd::launch_vjp(P, u_dev, vbar_dev, grad_dev, split_ws(P, ws_dev), (hipStream_t)stream);
+  if (rc < 0) return fail(ESD_EUNSUPPORTED, "VJP not built for this degree");
+  if (rc != 0) return fail(ESD_EHIP, "VJP launch failed");
+  return ESD_OK;
+}
+
+esd_status esd_sync_status(const esd_plan* P, void* stream) {
+  esd_status st = check_device(P);
+  if (st != ESD_OK) return st;
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  int flag = 0;
+  HIP_TRY(hipMemcpy(&flag, P->d_flag, sizeof(int), hipMemcpyDeviceToHost));
+  if (flag) {
+    const int zero = 0;
+    HIP_TRY(hipMemcpy(P->d_flag, &zero, sizeof(int), hipMemcpyHostToDevice));
+    return fail(ESD_EADMISSIBLE, "inadmissible state (rho <= 0, p <= 0 or non-finite) seen by a kernel");
+  }
+  return ESD_OK;
+}
+
+}  // extern "C"

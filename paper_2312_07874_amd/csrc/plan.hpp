@@ -1,0 +1,93 @@
+// Plan object shared by the C ABI (api.cpp) and the kernels (kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "host_setup.hpp"
+
+namespace esd {
+
+constexpr int FLUX_RANOCHA = 0;
+constexpr int FLUX_CHANDRASHEKAR = 1;
+
+// Device pointers to the per-degree reference tables (all FP64, see RefTables).
+struct DevTables {
+  const double* psi1;   // [P+1][Q]
+  const double* psi2;   // [P+1][P+1][Q]
+  const double* psi3;   // [P+1][P+1][Q]
+  const double* lgm1;   // [Q]
+  const double* lgp1;   // [Q]
+  const double* gjm1;   // [Q]
+  const double* I42;    // [Q][Q]
+  const double* A;      // [5][Q][Q]
+  const double* wf;     // [NF][NQF]
+  const double* wl;     // [Q]
+  const double* wj;     // [Q]
+  const double* xl;     // [Q]
+};
+
+// Scheme constants passed to kernels.
+struct Scheme {
+  double gamma;
+  double gm1_inv;       // 1/(gamma-1)
+  int ecflux;
+  int dissipation;
+};
+
+// Per-element geometric data on the device (element-major):
+//   gvol [e][NGV][NQ]  scaled metric rows for the line families, then w*J, w/J
+//     tri : h1(2) = w2 g1, h2(2) = (w2/2) g2, h2'(2) = (w1/2) g2           NGV = 8
+//     tet : h1(3) = (w2 w3/2) g1, h23(3) = (w2 w3/4)(g2+g3),
+//           h2(3) = (w1 w3/4) g2, h3(3) = (w1 w3/8) g3,
+//           hz(3) = (w1 w2 (1-eta2)/8) g3                                    NGV = 17
+//   gfac [e][dim+1][NFQ]  G^T nhat (dim rows), J_f
+//   conn [e][NFQ]         neighbour address in the facet-state buffer:
+//                          nbr_e*NC*NFQ + nbr_facet*NQF + nbr_node
+inline int ngv(int dim) { return dim == 2 ? 8 : 17; }
+
+struct Workspace {
+  double* wt;   // [ne][NC][NP]  projected entropy variables (modal)
+  double* wf;   // [ne][NC][NFQ] projected entropy variables at facet nodes
+};
+
+}  // namespace esd
+
+struct esd_plan {
+  int dim = 0, p = 0, nc = 0;
+  int64_t ne = 0;
+  esd::Scheme scheme{};
+  esd::RefTables ref;
+  esd::HostGeometry geo;
+  bool host_only = false;
+  int device = 0;
+  double* d_tables = nullptr;
+  esd::DevTables tab{};
+  double* d_gvol = nullptr;
+  double* d_gfac = nullptr;
+  int32_t* d_conn = nullptr;
+  double* d_xvol = nullptr;
+  int* d_flag = nullptr;
+  size_t ws_bytes = 0;
+  size_t rk_ws_bytes = 0;
+  // measurement: events bracketing each K1 / K2 launch (mutable: recorded by const calls)
+  bool timing = false;
+  mutable std::vector<hipEvent_t> ev;       // triples: before K1, between, after K2
+  mutable std::vector<hipEvent_t> ev_pool;
+};
+
+namespace esd {
+// kernel launchers (kernels.hip); return hipError_t as int, or -1 for an
+// unsupported degree
+int launch_residual(const esd_plan* P, const double* u, double* dudt, Workspace ws, hipStream_t s);
+int launch_project(const esd_plan* P, const double* u_nodal, double* u, hipStream_t s);
+int launch_axpy(double* y, const double* x, double a, const double* z, int64_t n, hipStream_t s);
+int launch_rk_stage(double* acc, double* U, const double* u, const double* k, double ca, double cu,
+                    int first, int64_t n, hipStream_t s);
+int launch_vjp(const esd_plan* P, const double* u, const double* vbar, double* grad, Workspace ws,
+               hipStream_t s);
+bool degree_supported(int dim, int p);
+}  // namespace esd
