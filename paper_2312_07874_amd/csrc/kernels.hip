@@ -106,55 +106,108 @@ __device__ __forceinline__ void decode_tri_mode(int P, int m, int& a1, int& a2) 
 
 // ------------------------------------------------------------------ sum-factorised PKD transforms
 // in/out arrays are [nel*NC][...] contiguous per (element, variable); all
-// threads of the block participate; each call ends with a barrier.
+// threads of the block participate; each call ends with a barrier.  Every
+// thread produces a whole line of outputs from one set of LDS loads
+// (register blocking along the contracted direction).
 template <int DIM, int P>
 __device__ void xform_V(const double* uh, double* T1, double* T2, double* out, const DevTables& T, int nec) {
   using S = Shape<DIM, P>;
   constexpr int Q = S::Q;
   const int tid = threadIdx.x, nth = blockDim.x;
   if constexpr (DIM == 2) {
-    for (int o = tid; o < nec * (P + 1) * Q; o += nth) {
-      const int i2 = o % Q, a1 = (o / Q) % (P + 1), ec = o / (Q * (P + 1));
+    // T1[ec][a1][i2] = sum_a2 psi2[a1][a2][i2] u~[ec][(a1,a2)]
+    for (int o = tid; o < nec * (P + 1); o += nth) {
+      const int a1 = o % (P + 1), ec = o / (P + 1);
       const int mb = a1 * (P + 1) - a1 * (a1 - 1) / 2;
-      double acc = 0.0;
-      for (int a2 = 0; a2 <= P - a1; ++a2) acc += T.psi2[(a1 * (P + 1) + a2) * Q + i2] * uh[ec * S::NP + mb + a2];
-      T1[o] = acc;
+      double acc[Q];
+#pragma unroll
+      for (int i = 0; i < Q; ++i) acc[i] = 0.0;
+#pragma unroll
+      for (int a2 = 0; a2 <= P; ++a2) {
+        if (a2 <= P - a1) {
+          const double x = uh[ec * S::NP + mb + a2];
+          const double* ps = T.psi2 + (a1 * (P + 1) + a2) * Q;
+#pragma unroll
+          for (int i = 0; i < Q; ++i) acc[i] += ps[i] * x;
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < Q; ++i) T1[(ec * (P + 1) + a1) * Q + i] = acc[i];
     }
     __syncthreads();
-    for (int o = tid; o < nec * S::NQ; o += nth) {
-      const int i1 = o % Q, i2 = (o / Q) % Q, ec = o / S::NQ;
-      double acc = 0.0;
+    // out[ec][i1 + Q i2] = sum_a1 psi1[a1][i1] T1[ec][a1][i2]
+    for (int o = tid; o < nec * Q; o += nth) {
+      const int i2 = o % Q, ec = o / Q;
+      double acc[Q];
 #pragma unroll
-      for (int a1 = 0; a1 <= P; ++a1) acc += T.psi1[a1 * Q + i1] * T1[(ec * (P + 1) + a1) * Q + i2];
-      out[o] = acc;
+      for (int i = 0; i < Q; ++i) acc[i] = 0.0;
+#pragma unroll
+      for (int a1 = 0; a1 <= P; ++a1) {
+        const double x = T1[(ec * (P + 1) + a1) * Q + i2];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) acc[i] += T.psi1[a1 * Q + i] * x;
+      }
+#pragma unroll
+      for (int i = 0; i < Q; ++i) out[ec * S::NQ + i + Q * i2] = acc[i];
     }
     __syncthreads();
   } else {
-    for (int o = tid; o < nec * S::NPAIR * Q; o += nth) {
-      const int i3 = o % Q, r = o / Q, pr = r % S::NPAIR, ec = r / S::NPAIR;
+    // T1[ec][pr][i3] = sum_a3 psi3[s][a3][i3] u~[ec][(a1,a2,a3)]
+    for (int o = tid; o < nec * S::NPAIR; o += nth) {
+      const int pr = o % S::NPAIR, ec = o / S::NPAIR;
       int a1, a2;
       decode_pair(P, pr, a1, a2);
       const int s = a1 + a2, mb = tet_mode_base(P, a1, a2);
-      double acc = 0.0;
-      for (int a3 = 0; a3 <= P - s; ++a3) acc += T.psi3[(s * (P + 1) + a3) * Q + i3] * uh[ec * S::NP + mb + a3];
-      T1[o] = acc;
-    }
-    __syncthreads();
-    for (int o = tid; o < nec * (P + 1) * Q * Q; o += nth) {
-      const int i3 = o % Q, i2 = (o / Q) % Q, a1 = (o / (Q * Q)) % (P + 1), ec = o / (Q * Q * (P + 1));
-      const int pb = pair_index(P, a1, 0);
-      double acc = 0.0;
-      for (int a2 = 0; a2 <= P - a1; ++a2)
-        acc += T.psi2[(a1 * (P + 1) + a2) * Q + i2] * T1[(ec * S::NPAIR + pb + a2) * Q + i3];
-      T2[o] = acc;
-    }
-    __syncthreads();
-    for (int o = tid; o < nec * S::NQ; o += nth) {
-      const int i1 = o % Q, i2 = (o / Q) % Q, i3 = (o / (Q * Q)) % Q, ec = o / S::NQ;
-      double acc = 0.0;
+      double acc[Q];
 #pragma unroll
-      for (int a1 = 0; a1 <= P; ++a1) acc += T.psi1[a1 * Q + i1] * T2[((ec * (P + 1) + a1) * Q + i2) * Q + i3];
-      out[o] = acc;
+      for (int i = 0; i < Q; ++i) acc[i] = 0.0;
+#pragma unroll
+      for (int a3 = 0; a3 <= P; ++a3) {
+        if (a3 <= P - s) {
+          const double x = uh[ec * S::NP + mb + a3];
+          const double* ps = T.psi3 + (s * (P + 1) + a3) * Q;
+#pragma unroll
+          for (int i = 0; i < Q; ++i) acc[i] += ps[i] * x;
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < Q; ++i) T1[(ec * S::NPAIR + pr) * Q + i] = acc[i];
+    }
+    __syncthreads();
+    // T2[ec][a1][i2 + Q i3] = sum_a2 psi2[a1][a2][i2] T1[ec][(a1,a2)][i3]
+    for (int o = tid; o < nec * (P + 1) * Q; o += nth) {
+      const int i3 = o % Q, a1 = (o / Q) % (P + 1), ec = o / (Q * (P + 1));
+      const int pb = pair_index(P, a1, 0);
+      double acc[Q];
+#pragma unroll
+      for (int i = 0; i < Q; ++i) acc[i] = 0.0;
+#pragma unroll
+      for (int a2 = 0; a2 <= P; ++a2) {
+        if (a2 <= P - a1) {
+          const double x = T1[(ec * S::NPAIR + pb + a2) * Q + i3];
+          const double* ps = T.psi2 + (a1 * (P + 1) + a2) * Q;
+#pragma unroll
+          for (int i = 0; i < Q; ++i) acc[i] += ps[i] * x;
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < Q; ++i) T2[(ec * (P + 1) + a1) * Q * Q + i + Q * i3] = acc[i];
+    }
+    __syncthreads();
+    // out[ec][i1 + Q i2 + Q^2 i3] = sum_a1 psi1[a1][i1] T2[ec][a1][i2 + Q i3]
+    for (int o = tid; o < nec * Q * Q; o += nth) {
+      const int i23 = o % (Q * Q), ec = o / (Q * Q);
+      double acc[Q];
+#pragma unroll
+      for (int i = 0; i < Q; ++i) acc[i] = 0.0;
+#pragma unroll
+      for (int a1 = 0; a1 <= P; ++a1) {
+        const double x = T2[(ec * (P + 1) + a1) * Q * Q + i23];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) acc[i] += T.psi1[a1 * Q + i] * x;
+      }
+#pragma unroll
+      for (int i = 0; i < Q; ++i) out[ec * S::NQ + i + Q * i23] = acc[i];
     }
     __syncthreads();
   }
@@ -166,53 +219,93 @@ __device__ void xform_Vt(const double* in, double* T1, double* T2, double* out, 
   constexpr int Q = S::Q;
   const int tid = threadIdx.x, nth = blockDim.x;
   if constexpr (DIM == 2) {
-    for (int o = tid; o < nec * (P + 1) * Q; o += nth) {
-      const int i2 = o % Q, a1 = (o / Q) % (P + 1), ec = o / (Q * (P + 1));
-      double acc = 0.0;
+    // T1[ec][a1][i2] = sum_i1 psi1[a1][i1] in[ec][i1 + Q i2]
+    for (int o = tid; o < nec * Q; o += nth) {
+      const int i2 = o % Q, ec = o / Q;
+      double acc[P + 1];
 #pragma unroll
-      for (int i1 = 0; i1 < Q; ++i1) acc += T.psi1[a1 * Q + i1] * in[ec * S::NQ + i1 + Q * i2];
-      T1[o] = acc;
+      for (int a = 0; a <= P; ++a) acc[a] = 0.0;
+#pragma unroll
+      for (int i1 = 0; i1 < Q; ++i1) {
+        const double x = in[ec * S::NQ + i1 + Q * i2];
+#pragma unroll
+        for (int a = 0; a <= P; ++a) acc[a] += T.psi1[a * Q + i1] * x;
+      }
+#pragma unroll
+      for (int a = 0; a <= P; ++a) T1[(ec * (P + 1) + a) * Q + i2] = acc[a];
     }
     __syncthreads();
-    for (int o = tid; o < nec * S::NP; o += nth) {
-      const int m = o % S::NP, ec = o / S::NP;
-      int a1, a2;
-      decode_tri_mode(P, m, a1, a2);
-      double acc = 0.0;
+    // out[ec][(a1,a2)] = sum_i2 psi2[a1][a2][i2] T1[ec][a1][i2]
+    for (int o = tid; o < nec * (P + 1); o += nth) {
+      const int a1 = o % (P + 1), ec = o / (P + 1);
+      const int mb = a1 * (P + 1) - a1 * (a1 - 1) / 2;
+      double acc[P + 1];
 #pragma unroll
-      for (int i2 = 0; i2 < Q; ++i2) acc += T.psi2[(a1 * (P + 1) + a2) * Q + i2] * T1[(ec * (P + 1) + a1) * Q + i2];
-      out[o] = acc;
+      for (int a = 0; a <= P; ++a) acc[a] = 0.0;
+#pragma unroll
+      for (int i2 = 0; i2 < Q; ++i2) {
+        const double x = T1[(ec * (P + 1) + a1) * Q + i2];
+#pragma unroll
+        for (int a = 0; a <= P; ++a) acc[a] += T.psi2[(a1 * (P + 1) + a) * Q + i2] * x;
+      }
+#pragma unroll
+      for (int a = 0; a <= P; ++a)
+        if (a <= P - a1) out[ec * S::NP + mb + a] = acc[a];
     }
     __syncthreads();
   } else {
-    for (int o = tid; o < nec * (P + 1) * Q * Q; o += nth) {
-      const int i3 = o % Q, i2 = (o / Q) % Q, a1 = (o / (Q * Q)) % (P + 1), ec = o / (Q * Q * (P + 1));
-      double acc = 0.0;
+    // T2[ec][a1][i2 + Q i3] = sum_i1 psi1[a1][i1] in[ec][i1 + Q i2 + Q^2 i3]
+    for (int o = tid; o < nec * Q * Q; o += nth) {
+      const int i23 = o % (Q * Q), ec = o / (Q * Q);
+      double acc[P + 1];
 #pragma unroll
-      for (int i1 = 0; i1 < Q; ++i1) acc += T.psi1[a1 * Q + i1] * in[ec * S::NQ + i1 + Q * (i2 + Q * i3)];
-      T2[o] = acc;
+      for (int a = 0; a <= P; ++a) acc[a] = 0.0;
+#pragma unroll
+      for (int i1 = 0; i1 < Q; ++i1) {
+        const double x = in[ec * S::NQ + i1 + Q * i23];
+#pragma unroll
+        for (int a = 0; a <= P; ++a) acc[a] += T.psi1[a * Q + i1] * x;
+      }
+#pragma unroll
+      for (int a = 0; a <= P; ++a) T2[(ec * (P + 1) + a) * Q * Q + i23] = acc[a];
     }
     __syncthreads();
-    for (int o = tid; o < nec * S::NPAIR * Q; o += nth) {
-      const int i3 = o % Q, r = o / Q, pr = r % S::NPAIR, ec = r / S::NPAIR;
+    // T1[ec][(a1,a2)][i3] = sum_i2 psi2[a1][a2][i2] T2[ec][a1][i2 + Q i3]
+    for (int o = tid; o < nec * (P + 1) * Q; o += nth) {
+      const int i3 = o % Q, a1 = (o / Q) % (P + 1), ec = o / (Q * (P + 1));
+      const int pb = pair_index(P, a1, 0);
+      double acc[P + 1];
+#pragma unroll
+      for (int a = 0; a <= P; ++a) acc[a] = 0.0;
+#pragma unroll
+      for (int i2 = 0; i2 < Q; ++i2) {
+        const double x = T2[(ec * (P + 1) + a1) * Q * Q + i2 + Q * i3];
+#pragma unroll
+        for (int a = 0; a <= P; ++a) acc[a] += T.psi2[(a1 * (P + 1) + a) * Q + i2] * x;
+      }
+#pragma unroll
+      for (int a = 0; a <= P; ++a)
+        if (a <= P - a1) T1[(ec * S::NPAIR + pb + a) * Q + i3] = acc[a];
+    }
+    __syncthreads();
+    // out[ec][(a1,a2,a3)] = sum_i3 psi3[s][a3][i3] T1[ec][(a1,a2)][i3]
+    for (int o = tid; o < nec * S::NPAIR; o += nth) {
+      const int pr = o % S::NPAIR, ec = o / S::NPAIR;
       int a1, a2;
       decode_pair(P, pr, a1, a2);
-      double acc = 0.0;
+      const int s = a1 + a2, mb = tet_mode_base(P, a1, a2);
+      double acc[P + 1];
 #pragma unroll
-      for (int i2 = 0; i2 < Q; ++i2)
-        acc += T.psi2[(a1 * (P + 1) + a2) * Q + i2] * T2[((ec * (P + 1) + a1) * Q + i2) * Q + i3];
-      T1[o] = acc;
-    }
-    __syncthreads();
-    for (int o = tid; o < nec * S::NP; o += nth) {
-      const int m = o % S::NP, ec = o / S::NP;
-      int a1, a2, a3;
-      decode_tet_mode(P, m, a1, a2, a3);
-      const int s = a1 + a2, pr = pair_index(P, a1, a2);
-      double acc = 0.0;
+      for (int a = 0; a <= P; ++a) acc[a] = 0.0;
 #pragma unroll
-      for (int i3 = 0; i3 < Q; ++i3) acc += T.psi3[(s * (P + 1) + a3) * Q + i3] * T1[(ec * S::NPAIR + pr) * Q + i3];
-      out[o] = acc;
+      for (int i3 = 0; i3 < Q; ++i3) {
+        const double x = T1[(ec * S::NPAIR + pr) * Q + i3];
+#pragma unroll
+        for (int a = 0; a <= P; ++a) acc[a] += T.psi3[(s * (P + 1) + a) * Q + i3] * x;
+      }
+#pragma unroll
+      for (int a = 0; a <= P; ++a)
+        if (a <= P - s) out[ec * S::NP + mb + a] = acc[a];
     }
     __syncthreads();
   }
@@ -427,64 +520,78 @@ k_entropy_projection(const double* __restrict__ u, double* __restrict__ wt, doub
   }
 }
 
-// ------------------------------------------------------------------ K2 helpers: one collapsed line
-// Pairs (a < b) of the line with nodes base + stride*k: F = f#(u_a, u_b, n_ab),
-// n_ab = A0_ab (h0_a + h0_b) [+ A1_ab (h1_a + h1_b)], r_a -= F, r_b += F.
+// ------------------------------------------------------------------ K2 helpers
+// One volume task: node a of the line base + stride*k; pairs (a, b) with
+// F = f#(u_a, u_b, n_ab), n_ab = A0_ab (h0_a + h0_b) [+ A1_ab (h1_a + h1_b)],
+// r_a -= F, r_b += F.
 template <int DIM, int P, int FLUX, int NA>
-__device__ __forceinline__ void line_pairs(const double* sN, const double* __restrict__ g, int base, int stride,
-                                           const double* __restrict__ A0, const double* __restrict__ A1, int hc0,
-                                           int hc1, const Scheme& S, double (&acc)[P + 1][DIM + 2]) {
+__device__ __forceinline__ void vol_task(const double* sN, const double* __restrict__ g, double* sR, int base,
+                                         int stride, int a, const double* __restrict__ A0,
+                                         const double* __restrict__ A1, int hc0, int hc1, const Scheme& S) {
   using Sh = Shape<DIM, P>;
   constexpr int Q = Sh::Q, NQ = Sh::NQ, NC = Sh::NC;
+  const int na = base + stride * a;
+  const Node<DIM> Na = load_node<DIM>(sN, NQ, na);
+  double h0a[DIM], h1a[DIM];
 #pragma unroll
-  for (int a = 0; a < Q; ++a) {
-    const int na = base + stride * a;
-    const Node<DIM> NAa = load_node<DIM>(sN, NQ, na);
-    double h0a[DIM], h1a[DIM];
-#pragma unroll
-    for (int i = 0; i < DIM; ++i) {
-      h0a[i] = g[(hc0 + i) * NQ + na];
-      if constexpr (NA == 2) h1a[i] = g[(hc1 + i) * NQ + na];
-    }
-#pragma unroll
-    for (int b = a + 1; b < Q; ++b) {
-      const int nb = base + stride * b;
-      const Node<DIM> NBb = load_node<DIM>(sN, NQ, nb);
-      double n[DIM];
-      const double c0 = A0[a * Q + b];
-#pragma unroll
-      for (int i = 0; i < DIM; ++i) n[i] = c0 * (h0a[i] + g[(hc0 + i) * NQ + nb]);
-      if constexpr (NA == 2) {
-        const double c1 = A1[a * Q + b];
-#pragma unroll
-        for (int i = 0; i < DIM; ++i) n[i] += c1 * (h1a[i] + g[(hc1 + i) * NQ + nb]);
-      }
-      double F[NC];
-      ec_flux<DIM, FLUX>(NAa, NBb, n, S, F);
-#pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        acc[a][c] -= F[c];
-        acc[b][c] += F[c];
-      }
-    }
+  for (int i = 0; i < DIM; ++i) {
+    h0a[i] = g[(hc0 + i) * NQ + na];
+    if constexpr (NA == 2) h1a[i] = g[(hc1 + i) * NQ + na];
   }
+  double racc[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) racc[c] = 0.0;
+  auto pair = [&](int b) {
+    const int nb = base + stride * b;
+    const Node<DIM> Nb = load_node<DIM>(sN, NQ, nb);
+    double n[DIM];
+    const double c0 = A0[a * Q + b];
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) n[i] = c0 * (h0a[i] + g[(hc0 + i) * NQ + nb]);
+    if constexpr (NA == 2) {
+      const double c1 = A1[a * Q + b];
+#pragma unroll
+      for (int i = 0; i < DIM; ++i) n[i] += c1 * (h1a[i] + g[(hc1 + i) * NQ + nb]);
+    }
+    double F[NC];
+    ec_flux<DIM, FLUX>(Na, Nb, n, S, F);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      racc[c] -= F[c];
+      atomicAdd(&sR[c * NQ + nb], F[c]);
+    }
+  };
+#pragma unroll
+  for (int k = 1; k <= (Q - 1) / 2; ++k) {
+    int b = a + k;
+    b = (b >= Q) ? b - Q : b;
+    pair(b);
+  }
+  if constexpr (Q % 2 == 0) {
+    if (a < Q / 2) pair(a + Q / 2);
+  }
+#pragma unroll
+  for (int c = 0; c < NC; ++c) atomicAdd(&sR[c * NQ + na], racc[c]);
 }
 
-// facet-correction pair: C = coef * f#(u_i, u^z_j, (gn_i + nJ_j)/2); r_i -= C, t_j += C
-template <int DIM, int FLUX>
-__device__ __forceinline__ void facet_pair(const Node<DIM>& Vi, const double* gn_i, const Node<DIM>& Fj,
-                                           const double* nJ_j, double coef, const Scheme& S, double* racc,
-                                           double* tacc) {
+// One facet-correction pair (eq. facet_correction): C = coef f#(u_i, u^z_j, (gn_i + nJ_j)/2);
+// r_i -= C (registers), t_j += C (LDS atomics).
+template <int DIM, int P, int FLUX>
+__device__ __forceinline__ void facet_task(const Node<DIM>& Vi, const double* gn_i, const double* sF, double* sT,
+                                           const double* __restrict__ gf, int j, double coef, const Scheme& S,
+                                           double* racc) {
+  constexpr int NC = DIM + 2, NFQ = Shape<DIM, P>::NFQ;
+  const Node<DIM> Fj = load_node<DIM>(sF, NFQ, j);
   double n[DIM];
 #pragma unroll
-  for (int i = 0; i < DIM; ++i) n[i] = 0.5 * (gn_i[i] + nJ_j[i]);
-  double F[DIM + 2];
+  for (int i = 0; i < DIM; ++i) n[i] = 0.5 * (gn_i[i] + gf[i * NFQ + j]);
+  double F[NC];
   ec_flux<DIM, FLUX>(Vi, Fj, n, S, F);
 #pragma unroll
-  for (int c = 0; c < DIM + 2; ++c) {
+  for (int c = 0; c < NC; ++c) {
     const double C = coef * F[c];
     racc[c] -= C;
-    tacc[c] += C;
+    atomicAdd(&sT[c * NFQ + j], C);
   }
 }
 
@@ -538,197 +645,107 @@ k_rhs(const double* __restrict__ wt, const double* __restrict__ wfb, double* __r
   if (bad) atomicOr(flag, 1);
   __syncthreads();
 
-  // ---- flux differencing along lines + facet corrections
-  const int el = tid / Sh::NLINES;
-  const int lt = tid % Sh::NLINES;
-  const int fam = lt / LPF, L = lt % LPF;
-  const bool active = el < nel;
-  double acc[Q][NC];
-#pragma unroll
-  for (int k = 0; k < Q; ++k)
-#pragma unroll
-    for (int c = 0; c < NC; ++c) acc[k][c] = 0.0;
-  int base = 0, stride = 1;
-  if (active) {
+  // ---- volume flux differencing: one task per (line family, line, node a);
+  //      task a evaluates the pairs (a, a+k mod Q), k = 1..(Q-1)/2 (and k = Q/2
+  //      for a < Q/2 when Q is even), so every unordered pair of a line is
+  //      evaluated once and every task does the same work.  r_a accumulates in
+  //      registers, r_b through LDS atomics.
+  for (int o = tid; o < nec * NQ; o += nth) sR[o] = 0.0;
+  for (int o = tid; o < nec * NFQ; o += nth) sT[o] = 0.0;
+  __syncthreads();
+  {
+    constexpr int TPE = DIM * NQ;           // volume tasks per element
+    for (int task = tid; task < nel * TPE; task += nth) {
+      const int el = task / TPE, lt = task % TPE;
+      const int fam = lt / NQ, rem = lt % NQ, L = rem / Q, a = rem % Q;
+      const double* sNe = sN + el * Sh::SCR;
+      double* sRe = sR + el * NC * NQ;
+      const double* g = gvol + (e0 + el) * NGV * NQ;
+      if constexpr (DIM == 2) {
+        if (fam == 0)
+          vol_task<DIM, P, FLUX, 2>(sNe, g, sRe, Q * L, 1, a, T.A + 0 * Q * Q, T.A + 1 * Q * Q, 0, 2, S);
+        else
+          vol_task<DIM, P, FLUX, 1>(sNe, g, sRe, L, Q, a, T.A + 2 * Q * Q, nullptr, 4, 0, S);
+      } else {
+        if (fam == 0)
+          vol_task<DIM, P, FLUX, 2>(sNe, g, sRe, Q * L, 1, a, T.A + 0 * Q * Q, T.A + 1 * Q * Q, 0, 3, S);
+        else if (fam == 1)
+          vol_task<DIM, P, FLUX, 2>(sNe, g, sRe, (L % Q) + Q * Q * (L / Q), Q, a, T.A + 2 * Q * Q, T.A + 3 * Q * Q,
+                                    6, 9, S);
+        else
+          vol_task<DIM, P, FLUX, 1>(sNe, g, sRe, L, Q * Q, a, T.A + 4 * Q * Q, nullptr, 12, 0, S);
+      }
+    }
+  }
+  __syncthreads();
+  // ---- facet correction (eq. facet_correction): one task per volume node i
+  //      with its partners on faces 1-3 (one each, along i's lines) and, in
+  //      3D, the Q face-4 nodes of its eta2-eta3 plane.  r_i is owned by the
+  //      task; C^T 1 accumulates through LDS atomics.
+  for (int task = tid; task < nel * NQ; task += nth) {
+    const int el = task / NQ, t = task % NQ;
     const double* sNe = sN + el * Sh::SCR;
     const double* sFe = sF + el * 8 * NFQ;
     double* sTe = sT + el * NC * NFQ;
     const double* g = gvol + (e0 + el) * NGV * NQ;
     const double* gf = gfac + (e0 + el) * (DIM + 1) * NFQ;
+    double racc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) racc[c] = 0.0;
+    int i;
     if constexpr (DIM == 2) {
-      if (fam == 0) {
-        base = Q * L;
-        stride = 1;
-        line_pairs<DIM, P, FLUX, 2>(sNe, g, base, stride, T.A + 0 * Q * Q, T.A + 1 * Q * Q, 0, 2, S, acc);
-        // facets 1 (eta1 = +1) and 2 (eta1 = -1) on this eta1-line
-        const double w2 = T.wl[L];
-        const Node<DIM> F1 = load_node<DIM>(sFe, NFQ, 1 * NQF + L);
-        const Node<DIM> F2 = load_node<DIM>(sFe, NFQ, 2 * NQF + L);
-        double nJ1[2], nJ2[2];
+      const int b2 = t % Q, b1 = t / Q;     // b2 fastest: neighbouring lanes hit different facet nodes
+      i = b1 + Q * b2;
+      const Node<DIM> Vi = load_node<DIM>(sNe, NQ, i);
+      const double w1 = T.wl[b1], w2 = T.wl[b2];
+      double gA[2], gB[2], gC[2];
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-          nJ1[i] = gf[i * NFQ + 1 * NQF + L];
-          nJ2[i] = gf[i * NFQ + 2 * NQF + L];
-        }
-        double t1[NC] = {0}, t2[NC] = {0};
-        const double cw1 = T.wf[1 * NQF + L], cw2 = T.wf[2 * NQF + L];
-#pragma unroll
-        for (int k = 0; k < Q; ++k) {
-          const int nk = base + k;
-          const Node<DIM> Vk = load_node<DIM>(sNe, NQ, nk);
-          double gA[2], gB[2];
-#pragma unroll
-          for (int i = 0; i < 2; ++i) {
-            const double g1 = g[(0 + i) * NQ + nk] / w2;
-            const double g2 = 2.0 * g[(2 + i) * NQ + nk] / w2;
-            gA[i] = (g1 + g2) * 0.70710678118654752440;
-            gB[i] = -g1;
-          }
-          facet_pair<DIM, FLUX>(Vk, gA, F1, nJ1, T.lgp1[k] * cw1, S, acc[k], t1);
-          facet_pair<DIM, FLUX>(Vk, gB, F2, nJ2, T.lgm1[k] * cw2, S, acc[k], t2);
-        }
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-          sTe[c * NFQ + 1 * NQF + L] += t1[c];
-          sTe[c * NFQ + 2 * NQF + L] += t2[c];
-        }
-      } else {
-        base = L;
-        stride = Q;
-        line_pairs<DIM, P, FLUX, 1>(sNe, g, base, stride, T.A + 2 * Q * Q, nullptr, 4, 0, S, acc);
-        // facet 0 (eta2 = -1) on this eta2-line
-        const double w1 = T.wl[L];
-        const Node<DIM> F0 = load_node<DIM>(sFe, NFQ, 0 * NQF + L);
-        double nJ0[2];
-#pragma unroll
-        for (int i = 0; i < 2; ++i) nJ0[i] = gf[i * NFQ + 0 * NQF + L];
-        double t0[NC] = {0};
-        const double cw0 = T.wf[0 * NQF + L];
-#pragma unroll
-        for (int k = 0; k < Q; ++k) {
-          const int nk = base + stride * k;
-          const Node<DIM> Vk = load_node<DIM>(sNe, NQ, nk);
-          double gA[2];
-#pragma unroll
-          for (int i = 0; i < 2; ++i) gA[i] = -2.0 * g[(4 + i) * NQ + nk] / w1;
-          facet_pair<DIM, FLUX>(Vk, gA, F0, nJ0, T.lgm1[k] * cw0, S, acc[k], t0);
-        }
-#pragma unroll
-        for (int c = 0; c < NC; ++c) sTe[c * NFQ + 0 * NQF + L] += t0[c];
+      for (int m = 0; m < 2; ++m) {
+        const double g1 = g[(0 + m) * NQ + i] / w2;
+        const double g2 = 2.0 * g[(2 + m) * NQ + i] / w2;
+        gA[m] = (g1 + g2) * 0.70710678118654752440;     // facet 2: G^T nhat, nhat = (1,1)/sqrt 2
+        gB[m] = -g1;                                     // facet 3: nhat = (-1, 0)
+        gC[m] = -2.0 * g[(4 + m) * NQ + i] / w1;         // facet 1: nhat = (0, -1)
       }
+      facet_task<DIM, P, FLUX>(Vi, gA, sFe, sTe, gf, 1 * NQF + b2, T.lgp1[b1] * T.wf[1 * NQF + b2], S, racc);
+      facet_task<DIM, P, FLUX>(Vi, gB, sFe, sTe, gf, 2 * NQF + b2, T.lgm1[b1] * T.wf[2 * NQF + b2], S, racc);
+      facet_task<DIM, P, FLUX>(Vi, gC, sFe, sTe, gf, 0 * NQF + b1, T.lgm1[b2] * T.wf[0 * NQF + b1], S, racc);
     } else {
-      if (fam == 0) {
-        // eta1-line (a2, a3)
-        const int a2 = L % Q, a3 = L / Q;
-        base = Q * L;
-        stride = 1;
-        line_pairs<DIM, P, FLUX, 2>(sNe, g, base, stride, T.A + 0 * Q * Q, T.A + 1 * Q * Q, 0, 3, S, acc);
-        const double inv23 = 1.0 / (T.wl[a2] * T.wj[a3]);
-        const Node<DIM> F1 = load_node<DIM>(sFe, NFQ, 1 * NQF + L);
-        const Node<DIM> F2 = load_node<DIM>(sFe, NFQ, 2 * NQF + L);
-        double nJ1[3], nJ2[3];
+      const int b3 = t % Q, b2 = (t / Q) % Q, b1 = t / (Q * Q);
+      i = b1 + Q * (b2 + Q * b3);
+      const Node<DIM> Vi = load_node<DIM>(sNe, NQ, i);
+      const double inv23 = 1.0 / (T.wl[b2] * T.wj[b3]);
+      const double inv13 = 1.0 / (T.wl[b1] * T.wj[b3]);
+      const double inv12 = 1.0 / (T.wl[b1] * T.wl[b2] * (1.0 - T.xl[b2]));
+      double gA[3], gB[3], gC[3], gD[3];
 #pragma unroll
-        for (int i = 0; i < 3; ++i) {
-          nJ1[i] = gf[i * NFQ + 1 * NQF + L];
-          nJ2[i] = gf[i * NFQ + 2 * NQF + L];
-        }
-        double t1[NC] = {0}, t2[NC] = {0};
-        const double cw1 = T.wf[1 * NQF + L], cw2 = T.wf[2 * NQF + L];
+      for (int m = 0; m < 3; ++m) {
+        const double g1 = 2.0 * g[(0 + m) * NQ + i] * inv23;
+        const double g23 = 4.0 * g[(3 + m) * NQ + i] * inv23;
+        gA[m] = (g1 + g23) * 0.57735026918962576451;    // facet 2: nhat = (1,1,1)/sqrt 3
+        gB[m] = -g1;                                     // facet 3: nhat = (-1,0,0)
+        gC[m] = -4.0 * g[(6 + m) * NQ + i] * inv13;      // facet 1: nhat = (0,-1,0)
+        gD[m] = -8.0 * g[(12 + m) * NQ + i] * inv12;     // facet 4: nhat = (0,0,-1)
+      }
+      const int j23 = b2 + Q * b3;
+      facet_task<DIM, P, FLUX>(Vi, gA, sFe, sTe, gf, 1 * NQF + j23, T.lgp1[b1] * T.wf[1 * NQF + j23], S, racc);
+      facet_task<DIM, P, FLUX>(Vi, gB, sFe, sTe, gf, 2 * NQF + j23, T.lgm1[b1] * T.wf[2 * NQF + j23], S, racc);
+      const int j13 = b1 + Q * b3;
+      facet_task<DIM, P, FLUX>(Vi, gC, sFe, sTe, gf, 0 * NQF + j13, T.lgm1[b2] * T.wf[0 * NQF + j13], S, racc);
+      const double cz = T.gjm1[b3];
 #pragma unroll
-        for (int k = 0; k < Q; ++k) {
-          const int nk = base + k;
-          const Node<DIM> Vk = load_node<DIM>(sNe, NQ, nk);
-          double gA[3], gB[3];
-#pragma unroll
-          for (int i = 0; i < 3; ++i) {
-            const double g1 = 2.0 * g[(0 + i) * NQ + nk] * inv23;
-            const double g23 = 4.0 * g[(3 + i) * NQ + nk] * inv23;
-            gA[i] = (g1 + g23) * 0.57735026918962576451;
-            gB[i] = -g1;
-          }
-          facet_pair<DIM, FLUX>(Vk, gA, F1, nJ1, T.lgp1[k] * cw1, S, acc[k], t1);
-          facet_pair<DIM, FLUX>(Vk, gB, F2, nJ2, T.lgm1[k] * cw2, S, acc[k], t2);
-        }
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-          sTe[c * NFQ + 1 * NQF + L] += t1[c];
-          sTe[c * NFQ + 2 * NQF + L] += t2[c];
-        }
-      } else if (fam == 1) {
-        // eta2-line (a1, a3)
-        const int a1 = L % Q, a3 = L / Q;
-        base = a1 + Q * Q * a3;
-        stride = Q;
-        line_pairs<DIM, P, FLUX, 2>(sNe, g, base, stride, T.A + 2 * Q * Q, T.A + 3 * Q * Q, 6, 9, S, acc);
-        const double inv13 = 1.0 / (T.wl[a1] * T.wj[a3]);
-        const Node<DIM> F0 = load_node<DIM>(sFe, NFQ, 0 * NQF + L);
-        double nJ0[3];
-#pragma unroll
-        for (int i = 0; i < 3; ++i) nJ0[i] = gf[i * NFQ + 0 * NQF + L];
-        double t0[NC] = {0};
-        const double cw0 = T.wf[0 * NQF + L];
-#pragma unroll
-        for (int k = 0; k < Q; ++k) {
-          const int nk = base + stride * k;
-          const Node<DIM> Vk = load_node<DIM>(sNe, NQ, nk);
-          double gA[3];
-#pragma unroll
-          for (int i = 0; i < 3; ++i) gA[i] = -4.0 * g[(6 + i) * NQ + nk] * inv13;
-          facet_pair<DIM, FLUX>(Vk, gA, F0, nJ0, T.lgm1[k] * cw0, S, acc[k], t0);
-        }
-#pragma unroll
-        for (int c = 0; c < NC; ++c) sTe[c * NFQ + 0 * NQF + L] += t0[c];
-      } else {
-        // eta3-line (a1, a2)
-        const int a1 = L % Q, a2 = L / Q;
-        base = L;
-        stride = Q * Q;
-        line_pairs<DIM, P, FLUX, 1>(sNe, g, base, stride, T.A + 4 * Q * Q, nullptr, 12, 0, S, acc);
-        // face 4 (xi3 = -1): facet nodes (a1, b) for every b, volume nodes of this line
-        const double inv12 = 1.0 / (T.wl[a1] * T.wl[a2] * (1.0 - T.xl[a2]));
-        double gA[Q][3];
-#pragma unroll
-        for (int k = 0; k < Q; ++k)
-#pragma unroll
-          for (int i = 0; i < 3; ++i) gA[k][i] = -8.0 * g[(12 + i) * NQ + base + stride * k] * inv12;
-        for (int bq = 0; bq < Q; ++bq) {
-          const int j = 3 * NQF + a1 + Q * bq;
-          const Node<DIM> Fj = load_node<DIM>(sFe, NFQ, j);
-          double nJ[3];
-#pragma unroll
-          for (int i = 0; i < 3; ++i) nJ[i] = gf[i * NFQ + j];
-          const double cw = T.wf[j] * T.I42[bq * Q + a2];
-          double tj[NC] = {0};
-#pragma unroll
-          for (int k = 0; k < Q; ++k) {
-            const Node<DIM> Vk = load_node<DIM>(sNe, NQ, base + stride * k);
-            facet_pair<DIM, FLUX>(Vk, gA[k], Fj, nJ, cw * T.gjm1[k], S, acc[k], tj);
-          }
-#pragma unroll
-          for (int c = 0; c < NC; ++c) atomicAdd(&sTe[c * NFQ + j], tj[c]);
-        }
+      for (int m = 0; m < Q; ++m) {
+        int a2 = m + b2 + b3;                 // rotated so that neighbouring lanes hit different facet nodes
+        a2 = a2 % Q;
+        const int j = 3 * NQF + b1 + Q * a2;
+        facet_task<DIM, P, FLUX>(Vi, gD, sFe, sTe, gf, j, cz * T.I42[a2 * Q + b2] * T.wf[j], S, racc);
       }
     }
+    double* r = sR + el * NC * NQ;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) r[c * NQ + i] += racc[c];
   }
-  // ordered accumulation of the line families into r (deterministic)
-#pragma unroll
-  for (int ph = 0; ph < DIM; ++ph) {
-    if (active && fam == ph) {
-      double* r = sR + el * NC * NQ;
-#pragma unroll
-      for (int k = 0; k < Q; ++k) {
-        const int nk = base + stride * k;
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-          if (ph == 0)
-            r[c * NQ + nk] = acc[k][c];
-          else
-            r[c * NQ + nk] += acc[k][c];
-        }
-      }
-    }
-    __syncthreads();
-  }
+  __syncthreads();
 
   // ---- interface flux and s = B J_f f* - C^T 1
   bad = false;
