@@ -50,14 +50,16 @@ template <int DIM, int P>
 struct Launch;  // block size and elements per block
 template <int P>
 struct Launch<3, P> {
+  // one element per workgroup; small workgroups keep several elements in
+  // flight per CU, which hides the latency of the barrier-separated phases
   static constexpr int EPB = 1;
-  static constexpr int BS = (3 * (P + 1) * (P + 1) <= 128) ? 128 : ((3 * (P + 1) * (P + 1) + 63) / 64) * 64;
+  static constexpr int BS = P <= 3 ? 64 : (P == 4 ? 128 : (P <= 6 ? 192 : 256));
 };
 template <int P>
 struct Launch<2, P> {
-  static constexpr int LINES = 2 * (P + 1);
   static constexpr int EPB = (P <= 4) ? 12 : ((P <= 7) ? 8 : 6);
-  static constexpr int BS = ((EPB * LINES + 63) / 64) * 64 < 128 ? 128 : ((EPB * LINES + 63) / 64) * 64;
+  static constexpr int NQ = (P + 1) * (P + 1);
+  static constexpr int BS = ((EPB * NQ + 63) / 64) * 64;
 };
 
 __device__ __forceinline__ int pair_index(int P, int a1, int a2) { return a1 * (P + 1) - a1 * (a1 - 1) / 2 + a2; }
@@ -113,6 +115,7 @@ template <int DIM, int P>
 __device__ void xform_V(const double* uh, double* T1, double* T2, double* out, const DevTables& T, int nec) {
   using S = Shape<DIM, P>;
   constexpr int Q = S::Q;
+  constexpr int XU = Q <= 7 ? Q : 1;   // unroll the contraction while its table fits scalar registers
   const int tid = threadIdx.x, nth = blockDim.x;
   if constexpr (DIM == 2) {
     // T1[ec][a1][i2] = sum_a2 psi2[a1][a2][i2] u~[ec][(a1,a2)]
@@ -122,7 +125,7 @@ __device__ void xform_V(const double* uh, double* T1, double* T2, double* out, c
       double acc[Q];
 #pragma unroll
       for (int i = 0; i < Q; ++i) acc[i] = 0.0;
-#pragma unroll
+#pragma unroll XU
       for (int a2 = 0; a2 <= P; ++a2) {
         if (a2 <= P - a1) {
           const double x = uh[ec * S::NP + mb + a2];
@@ -141,7 +144,7 @@ __device__ void xform_V(const double* uh, double* T1, double* T2, double* out, c
       double acc[Q];
 #pragma unroll
       for (int i = 0; i < Q; ++i) acc[i] = 0.0;
-#pragma unroll
+#pragma unroll XU
       for (int a1 = 0; a1 <= P; ++a1) {
         const double x = T1[(ec * (P + 1) + a1) * Q + i2];
 #pragma unroll
@@ -161,7 +164,7 @@ __device__ void xform_V(const double* uh, double* T1, double* T2, double* out, c
       double acc[Q];
 #pragma unroll
       for (int i = 0; i < Q; ++i) acc[i] = 0.0;
-#pragma unroll
+#pragma unroll XU
       for (int a3 = 0; a3 <= P; ++a3) {
         if (a3 <= P - s) {
           const double x = uh[ec * S::NP + mb + a3];
@@ -181,7 +184,7 @@ __device__ void xform_V(const double* uh, double* T1, double* T2, double* out, c
       double acc[Q];
 #pragma unroll
       for (int i = 0; i < Q; ++i) acc[i] = 0.0;
-#pragma unroll
+#pragma unroll XU
       for (int a2 = 0; a2 <= P; ++a2) {
         if (a2 <= P - a1) {
           const double x = T1[(ec * S::NPAIR + pb + a2) * Q + i3];
@@ -200,7 +203,7 @@ __device__ void xform_V(const double* uh, double* T1, double* T2, double* out, c
       double acc[Q];
 #pragma unroll
       for (int i = 0; i < Q; ++i) acc[i] = 0.0;
-#pragma unroll
+#pragma unroll XU
       for (int a1 = 0; a1 <= P; ++a1) {
         const double x = T2[(ec * (P + 1) + a1) * Q * Q + i23];
 #pragma unroll
@@ -217,6 +220,7 @@ template <int DIM, int P>
 __device__ void xform_Vt(const double* in, double* T1, double* T2, double* out, const DevTables& T, int nec) {
   using S = Shape<DIM, P>;
   constexpr int Q = S::Q;
+  constexpr int XU = Q <= 7 ? Q : 1;   // unroll the contraction while its table fits scalar registers
   const int tid = threadIdx.x, nth = blockDim.x;
   if constexpr (DIM == 2) {
     // T1[ec][a1][i2] = sum_i1 psi1[a1][i1] in[ec][i1 + Q i2]
@@ -225,7 +229,7 @@ __device__ void xform_Vt(const double* in, double* T1, double* T2, double* out, 
       double acc[P + 1];
 #pragma unroll
       for (int a = 0; a <= P; ++a) acc[a] = 0.0;
-#pragma unroll
+#pragma unroll XU
       for (int i1 = 0; i1 < Q; ++i1) {
         const double x = in[ec * S::NQ + i1 + Q * i2];
 #pragma unroll
@@ -242,7 +246,7 @@ __device__ void xform_Vt(const double* in, double* T1, double* T2, double* out, 
       double acc[P + 1];
 #pragma unroll
       for (int a = 0; a <= P; ++a) acc[a] = 0.0;
-#pragma unroll
+#pragma unroll XU
       for (int i2 = 0; i2 < Q; ++i2) {
         const double x = T1[(ec * (P + 1) + a1) * Q + i2];
 #pragma unroll
@@ -260,7 +264,7 @@ __device__ void xform_Vt(const double* in, double* T1, double* T2, double* out, 
       double acc[P + 1];
 #pragma unroll
       for (int a = 0; a <= P; ++a) acc[a] = 0.0;
-#pragma unroll
+#pragma unroll XU
       for (int i1 = 0; i1 < Q; ++i1) {
         const double x = in[ec * S::NQ + i1 + Q * i23];
 #pragma unroll
@@ -277,7 +281,7 @@ __device__ void xform_Vt(const double* in, double* T1, double* T2, double* out, 
       double acc[P + 1];
 #pragma unroll
       for (int a = 0; a <= P; ++a) acc[a] = 0.0;
-#pragma unroll
+#pragma unroll XU
       for (int i2 = 0; i2 < Q; ++i2) {
         const double x = T2[(ec * (P + 1) + a1) * Q * Q + i2 + Q * i3];
 #pragma unroll
@@ -297,7 +301,7 @@ __device__ void xform_Vt(const double* in, double* T1, double* T2, double* out, 
       double acc[P + 1];
 #pragma unroll
       for (int a = 0; a <= P; ++a) acc[a] = 0.0;
-#pragma unroll
+#pragma unroll XU
       for (int i3 = 0; i3 < Q; ++i3) {
         const double x = T1[(ec * S::NPAIR + pr) * Q + i3];
 #pragma unroll
@@ -309,6 +313,15 @@ __device__ void xform_Vt(const double* in, double* T1, double* T2, double* out, 
     }
     __syncthreads();
   }
+}
+
+// 1/x: hardware reciprocal estimate refined by two Newton-Raphson steps
+// (each squares the relative error), correctly rounded to within an ulp
+__device__ __forceinline__ double frcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(fma(-x, r, 1.0), r, r);
+  r = fma(fma(-x, r, 1.0), r, r);
+  return r;
 }
 
 // ------------------------------------------------------------------ physics
@@ -345,10 +358,11 @@ __device__ __forceinline__ void store_node(double* s, int stride, int k, const N
 template <int DIM>
 __device__ __forceinline__ bool from_entropy(const double* w, const Scheme& S, Node<DIM>& n) {
   const double b = -w[DIM + 1];
+  const double ib = frcp(b);
   double v2 = 0.0;
 #pragma unroll
   for (int i = 0; i < DIM; ++i) {
-    n.v[i] = w[1 + i] / b;
+    n.v[i] = w[1 + i] * ib;
     v2 += n.v[i] * n.v[i];
   }
   const double s = S.gamma - (S.gamma - 1.0) * (w[0] + 0.5 * b * v2);
@@ -356,28 +370,29 @@ __device__ __forceinline__ bool from_entropy(const double* w, const Scheme& S, N
   n.lnb = log(b);
   n.lnrho = -(s + n.lnb) * S.gm1_inv;
   n.rho = exp(n.lnrho);
-  n.p = n.rho / b;
+  n.p = n.rho * ib;
   return (b > 0.0) && isfinite(n.rho) && isfinite(n.p) && (n.rho > 0.0);
 }
 
 constexpr double LOG_SERIES_THRESHOLD = 1.0e-4;
 
-// logarithmic mean (a+ - a-)/(ln a+ - ln a-) from precomputed logs; series in
-// f = (a+ - a-)/(a+ + a-) through f^6/7 when f^2 < 1e-4
-__device__ __forceinline__ double log_mean(double a, double b, double la, double lb) {
-  const double d = b - a, s = a + b;
-  if (d * d < LOG_SERIES_THRESHOLD * s * s) {
-    const double u = (d * d) / (s * s);
-    return s / (2.0 * (1.0 + u * (1.0 / 3.0 + u * (1.0 / 5.0 + u * (1.0 / 7.0)))));
-  }
+// The logarithmic mean (a+ - a-)/(ln a+ - ln a-) and the reciprocal of the
+// logarithmic mean, from precomputed logs.  With f = (a+ - a-)/(a+ + a-) and
+// ln(a+/a-) = 2 atanh f, nearly equal arguments (f^2 < 1e-4) use the series
+//   {a}_ln     = (a- + a+)/2 * f/atanh f,  f/atanh f = 1 - u/3 - 4u^2/45 - 44u^3/945 + O(u^4)
+//   1/{a}_ln   = 2 (1 + u/3 + u^2/5 + u^3/7) / (a- + a+) + O(u^4),   u = f^2,
+// whose truncation is below 3e-18 relative.  inv_s = 1/(a- + a+) is passed in.
+__device__ __forceinline__ double log_mean(double a, double b, double la, double lb, double inv_s) {
+  const double d = b - a;
+  const double f = d * inv_s, u = f * f;
+  if (u < LOG_SERIES_THRESHOLD)
+    return 0.5 * (a + b) * (1.0 - u * (1.0 / 3.0 + u * (4.0 / 45.0 + u * (44.0 / 945.0))));
   return d / (lb - la);
 }
-__device__ __forceinline__ double inv_log_mean(double a, double b, double la, double lb) {
-  const double d = b - a, s = a + b;
-  if (d * d < LOG_SERIES_THRESHOLD * s * s) {
-    const double u = (d * d) / (s * s);
-    return 2.0 * (1.0 + u * (1.0 / 3.0 + u * (1.0 / 5.0 + u * (1.0 / 7.0)))) / s;
-  }
+__device__ __forceinline__ double inv_log_mean(double a, double b, double la, double lb, double inv_s) {
+  const double d = b - a;
+  const double f = d * inv_s, u = f * f;
+  if (u < LOG_SERIES_THRESHOLD) return 2.0 * (1.0 + u * (1.0 / 3.0 + u * (1.0 / 5.0 + u * (1.0 / 7.0)))) * inv_s;
   return (lb - la) / d;
 }
 
@@ -385,8 +400,11 @@ __device__ __forceinline__ double inv_log_mean(double a, double b, double la, do
 template <int DIM, int FLUX>
 __device__ __forceinline__ void ec_flux(const Node<DIM>& A, const Node<DIM>& B, const double* n, const Scheme& S,
                                         double* F) {
-  const double rho_ln = log_mean(A.rho, B.rho, A.lnrho, B.lnrho);
-  const double ib_ln = inv_log_mean(A.b, B.b, A.lnb, B.lnb);   // 1 / {rho/p}_ln
+  // one reciprocal serves both means: 1/(sr sb) -> 1/sr = sb/(sr sb), 1/sb = sr/(sr sb)
+  const double sr = A.rho + B.rho, sb = A.b + B.b;
+  const double rr = frcp(sr * sb);
+  const double rho_ln = log_mean(A.rho, B.rho, A.lnrho, B.lnrho, sb * rr);
+  const double ib_ln = inv_log_mean(A.b, B.b, A.lnb, B.lnb, sr * rr);   // 1 / {rho/p}_ln
   double vavg[DIM];
   double vn = 0.0, vab = 0.0, van = 0.0, vbn = 0.0;
 #pragma unroll
@@ -405,7 +423,7 @@ __device__ __forceinline__ void ec_flux(const Node<DIM>& A, const Node<DIM>& B, 
     for (int i = 0; i < DIM; ++i) F[1 + i] = frho * vavg[i] + pavg * n[i];
     F[DIM + 1] = frho * (0.5 * vab + ib_ln * S.gm1_inv) + 0.5 * (A.p * vbn + B.p * van);
   } else {
-    const double phat = (A.rho + B.rho) / (A.b + B.b);      // {rho} / (2 {beta}), beta = b/2
+    const double phat = sr * sr * rr;                        // {rho} / (2 {beta}) = sr/sb, beta = b/2
 #pragma unroll
     for (int i = 0; i < DIM; ++i) F[1 + i] = frho * vavg[i] + phat * n[i];
     F[DIM + 1] = frho * (0.5 * vab + ib_ln * S.gm1_inv) + phat * vn;
