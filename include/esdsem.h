@@ -95,8 +95,10 @@ typedef struct {
   int64_t n_dof;                          /* n_elements * n_vars * n_modes          */
   int64_t flux_pairs_paper;               /* per residual, count of eq. (num_fluxes) */
   int64_t flux_pairs_distinct;            /* per residual, pairs evaluated by the line loops */
-  size_t workspace_bytes;                 /* esd_residual / esd_residual_vjp workspace */
+  size_t workspace_bytes;                 /* esd_residual workspace                 */
   size_t rk4_workspace_bytes;             /* esd_rk4 workspace                      */
+  size_t vjp_workspace_bytes;             /* esd_residual_vjp workspace             */
+  size_t rk4_vjp_workspace_bytes;         /* esd_rk4_vjp workspace                  */
 } esd_plan_info;
 
 /* Builds operators (Sec. 3, 4.3), geometry (Sec. 4.1-4.2, 4.5) and facet
@@ -144,10 +146,26 @@ esd_status esd_residual(const esd_plan* plan, const double* u_dev, double* dudt_
 esd_status esd_rk4(const esd_plan* plan, double* u_dev, double dt, int32_t nsteps,
                    void* ws_dev, double* stage_ckpt_dev, void* stream);
 
-/* Vector-Jacobian product of the residual: grad_dev = (d du~/dt / d u~)^T vbar_dev,
- * all [element][variable][mode].  ws_dev holds info.workspace_bytes. */
+/* Vector-Jacobian product of the semi-discrete right-hand side (the adjoint of
+ * esd_residual, differentiating eqs. entropy_expansion, entropy_stable,
+ * facet_correction, num_flux and dudt_modal exactly, including the interface
+ * coupling to the neighbours):
+ *   grad_dev = (d du~/dt / d u~)^T vbar_dev,  all [element][variable][mode].
+ * The derivative of the wave speed takes the branch the forward takes (ties go
+ * to the interior side; |x| has derivative 0 at 0).  grad_dev must not overlap
+ * u_dev or vbar_dev; ws_dev holds info.vjp_workspace_bytes (256-byte aligned).
+ * Errors: ESD_EINVAL, ESD_EUNSUPPORTED (degree not built, or facet nodes not
+ * paired both ways), ESD_EHIP; inadmissible states set the sticky flag. */
 esd_status esd_residual_vjp(const esd_plan* plan, const double* u_dev, const double* vbar_dev,
                             double* grad_dev, void* ws_dev, void* stream);
+
+/* Discrete adjoint of nsteps steps of esd_rk4 (classical four-stage
+ * Runge-Kutta) with step dt.  stage_ckpt_dev holds the stage inputs written by
+ * esd_rk4, [4*nsteps][n_dof].  On entry ubar_dev is the cotangent of the final
+ * state, on exit that of the initial state (in place).  ws_dev holds
+ * info.rk4_vjp_workspace_bytes (256-byte aligned). */
+esd_status esd_rk4_vjp(const esd_plan* plan, const double* stage_ckpt_dev, double dt, int32_t nsteps,
+                       double* ubar_dev, void* ws_dev, void* stream);
 
 /* Synchronises the stream and returns ESD_EADMISSIBLE if any kernel since the
  * last call saw an inadmissible state (the flag is cleared), else ESD_OK. */

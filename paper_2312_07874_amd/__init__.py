@@ -50,7 +50,8 @@ class PlanInfo(ctypes.Structure):
                 ("n_modes", ctypes.c_int32), ("n_vol_nodes", ctypes.c_int32), ("n_facets", ctypes.c_int32),
                 ("n_facet_nodes", ctypes.c_int32), ("n_elements", ctypes.c_int64), ("n_dof", ctypes.c_int64),
                 ("flux_pairs_paper", ctypes.c_int64), ("flux_pairs_distinct", ctypes.c_int64),
-                ("workspace_bytes", ctypes.c_size_t), ("rk4_workspace_bytes", ctypes.c_size_t)]
+                ("workspace_bytes", ctypes.c_size_t), ("rk4_workspace_bytes", ctypes.c_size_t),
+                ("vjp_workspace_bytes", ctypes.c_size_t), ("rk4_vjp_workspace_bytes", ctypes.c_size_t)]
 
 
 _vp = ctypes.c_void_p
@@ -66,6 +67,7 @@ EXPORTS = {
     "esd_residual": (_c, [_vp, _vp, _vp, _vp, _vp]),
     "esd_rk4": (_c, [_vp, _vp, ctypes.c_double, ctypes.c_int32, _vp, _vp, _vp]),
     "esd_residual_vjp": (_c, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "esd_rk4_vjp": (_c, [_vp, _vp, ctypes.c_double, ctypes.c_int32, _vp, _vp, _vp]),
     "esd_sync_status": (_c, [_vp, _vp]),
     "esd_plan_set_timing": (_c, [_vp, ctypes.c_int32]),
     "esd_plan_get_timing": (_c, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
@@ -162,9 +164,12 @@ class Plan:
         return out
 
     # ---- device calls
-    def workspace(self, rk4: bool = False):
+    def workspace(self, kind: str = "residual"):
+        """Device workspace (one buffer per plan, grown on demand) for
+        kind = "residual", "rk4", "vjp" or "rk4_vjp"."""
         import torch
-        nbytes = self.info.rk4_workspace_bytes if rk4 else self.info.workspace_bytes
+        nbytes = {"residual": self.info.workspace_bytes, "rk4": self.info.rk4_workspace_bytes,
+                  "vjp": self.info.vjp_workspace_bytes, "rk4_vjp": self.info.rk4_vjp_workspace_bytes}[kind]
         if self._ws is None or self._ws.numel() * 8 < nbytes:
             self._ws = torch.empty((nbytes + 7) // 8, dtype=torch.float64, device="cuda")
         return self._ws
@@ -195,18 +200,30 @@ class Plan:
     def rk4(self, u, dt: float, nsteps: int, ckpt=None):
         """In place on u; ckpt (optional) receives the stage inputs [4*nsteps, *state]."""
         assert u.is_contiguous() and tuple(u.shape) == self.state_shape
-        _check(_lib.esd_rk4(self._h, _ptr(u), float(dt), int(nsteps), _ptr(self.workspace(rk4=True)),
+        _check(_lib.esd_rk4(self._h, _ptr(u), float(dt), int(nsteps), _ptr(self.workspace("rk4")),
                             _ptr(ckpt), _stream()), "esd_rk4")
         return u
 
     def vjp(self, u, vbar, out=None):
+        """(d du~/dt / d u~)^T vbar (esd_residual_vjp)."""
         import torch
         assert u.is_contiguous() and vbar.is_contiguous()
+        assert tuple(u.shape) == self.state_shape and tuple(vbar.shape) == self.state_shape
         if out is None:
             out = torch.empty_like(u)
-        _check(_lib.esd_residual_vjp(self._h, _ptr(u), _ptr(vbar), _ptr(out), _ptr(self.workspace()), _stream()),
-               "esd_residual_vjp")
+        _check(_lib.esd_residual_vjp(self._h, _ptr(u), _ptr(vbar), _ptr(out), _ptr(self.workspace("vjp")),
+                                     _stream()), "esd_residual_vjp")
         return out
+
+    def rk4_vjp(self, ckpt, dt: float, nsteps: int, ubar):
+        """Discrete adjoint of rk4: ubar (cotangent of the final state) is
+        replaced in place by the cotangent of the initial state; ckpt holds the
+        stage inputs written by rk4(..., ckpt=...)."""
+        assert ckpt.is_contiguous() and ubar.is_contiguous() and tuple(ubar.shape) == self.state_shape
+        assert ckpt.numel() == 4 * nsteps * ubar.numel()
+        _check(_lib.esd_rk4_vjp(self._h, _ptr(ckpt), float(dt), int(nsteps), _ptr(ubar),
+                                _ptr(self.workspace("rk4_vjp")), _stream()), "esd_rk4_vjp")
+        return ubar
 
     def set_timing(self, enable: bool):
         _check(_lib.esd_plan_set_timing(self._h, 1 if enable else 0), "esd_plan_set_timing")
@@ -245,3 +262,34 @@ def _autograd_residual():
 def residual(u, plan: Plan):
     """Differentiable residual (torch.autograd)."""
     return _autograd_residual().apply(u, plan)
+
+
+def _autograd_rk4():
+    import torch
+
+    class RK4(torch.autograd.Function):
+        """nsteps of classical RK4; backward is the discrete adjoint from the
+        stored stage inputs."""
+
+        @staticmethod
+        def forward(ctx, u, plan, dt, nsteps):
+            out = u.detach().clone().contiguous()
+            ckpt = torch.empty((4 * nsteps,) + tuple(u.shape), dtype=u.dtype, device=u.device)
+            plan.rk4(out, dt, nsteps, ckpt)
+            ctx.plan, ctx.dt, ctx.nsteps = plan, dt, nsteps
+            ctx.save_for_backward(ckpt)
+            return out
+
+        @staticmethod
+        def backward(ctx, g):
+            (ckpt,) = ctx.saved_tensors
+            ub = g.detach().clone().contiguous()
+            ctx.plan.rk4_vjp(ckpt, ctx.dt, ctx.nsteps, ub)
+            return ub, None, None, None
+
+    return RK4
+
+
+def rk4(u, plan: Plan, dt: float, nsteps: int):
+    """Differentiable RK4 solve (torch.autograd); keeps 4*nsteps stage states."""
+    return _autograd_rk4().apply(u, plan, dt, nsteps)

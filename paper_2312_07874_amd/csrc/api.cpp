@@ -123,8 +123,11 @@ esd_status esd_plan_create(const esd_mesh_desc* mesh, const esd_scheme_desc* sch
     }
     const esd::RefTables& R = P->ref;
     const size_t ndof = (size_t)P->ne * P->nc * R.NP;
-    P->ws_bytes = align256(ndof * sizeof(double)) + align256((size_t)P->ne * P->nc * R.NFQ * sizeof(double));
+    const size_t fbytes = align256((size_t)P->ne * P->nc * R.NFQ * sizeof(double));
+    P->ws_bytes = align256(ndof * sizeof(double)) + fbytes;
     P->rk_ws_bytes = P->ws_bytes + 3 * align256(ndof * sizeof(double));
+    P->vjp_ws_bytes = P->ws_bytes + fbytes;
+    P->rk_vjp_ws_bytes = P->vjp_ws_bytes + 3 * align256(ndof * sizeof(double));
     if (P->host_only) {
       *out = P;
       return ESD_OK;
@@ -181,6 +184,18 @@ esd_status esd_plan_create(const esd_mesh_desc* mesh, const esd_scheme_desc* sch
         const int64_t nf = rem / NQF, nn = rem % NQF;
         (void)NF;
         conn[(size_t)e * NFQ + j] = (int32_t)(ne_ * stride + nf * NQF + nn);
+      }
+    // the VJP gathers exterior cotangents through the same permutation, which
+    // needs it to pair facet nodes both ways
+    P->conn_involutive = true;
+    for (int64_t e = 0; e < P->ne && P->conn_involutive; ++e)
+      for (int j = 0; j < NFQ; ++j) {
+        const int64_t a = conn[(size_t)e * NFQ + j];
+        const int64_t e2 = a / stride, j2 = a % stride;
+        if (j2 >= NFQ || conn[(size_t)e2 * NFQ + j2] != (int32_t)(e * stride + j)) {
+          P->conn_involutive = false;
+          break;
+        }
       }
     if (st == ESD_OK) st = upload(&P->d_gfac, gf);
     if (st == ESD_OK) st = upload(&P->d_conn, conn);
@@ -259,6 +274,8 @@ esd_status esd_plan_query(const esd_plan* P, esd_plan_info* out) {
   out->flux_pairs_distinct = distinct * P->ne;
   out->workspace_bytes = P->ws_bytes;
   out->rk4_workspace_bytes = P->rk_ws_bytes;
+  out->vjp_workspace_bytes = P->vjp_ws_bytes;
+  out->rk4_vjp_workspace_bytes = P->rk_vjp_ws_bytes;
   return ESD_OK;
 }
 
@@ -313,6 +330,7 @@ static esd::Workspace split_ws(const esd_plan* P, void* ws) {
   esd::Workspace w;
   w.wt = (double*)ws;
   w.wf = (double*)((char*)ws + align256(ndof * sizeof(double)));
+  w.xbar = (double*)((char*)ws + P->ws_bytes);   // inside the workspace only for the VJP entry points
   return w;
 }
 
@@ -366,9 +384,48 @@ esd_status esd_residual_vjp(const esd_plan* P, const double* u_dev, const double
   esd_status st = check_device(P);
   if (st != ESD_OK) return st;
   if (!u_dev || !vbar_dev || !grad_dev || !ws_dev) return fail(ESD_EINVAL, "NULL buffer");
+  if ((const void*)grad_dev == (const void*)u_dev || (const void*)grad_dev == (const void*)vbar_dev)
+    return fail(ESD_EINVAL, "grad overlaps u or vbar");
+  if (((uintptr_t)ws_dev) % 256 != 0) return fail(ESD_EINVAL, "workspace not 256-byte aligned");
+  if (!P->conn_involutive) return fail(ESD_EUNSUPPORTED, "facet permutation is not an involution");
   const int rc = esd::launch_vjp(P, u_dev, vbar_dev, grad_dev, split_ws(P, ws_dev), (hipStream_t)stream);
-  if (rc < 0) return fail(ESD_EUNSUPPORTED, "VJP not built for this degree");
-  if (rc != 0) return fail(ESD_EHIP, "VJP launch failed");
+  if (rc < 0) return fail(ESD_EUNSUPPORTED, "degree not built");
+  if (rc != 0) return fail(ESD_EHIP, std::string("VJP launch failed: ") + hipGetErrorString((hipError_t)rc));
+  return ESD_OK;
+}
+
+esd_status esd_rk4_vjp(const esd_plan* P, const double* stage_ckpt_dev, double dt, int32_t nsteps, double* ubar_dev,
+                       void* ws_dev, void* stream) {
+  esd_status st = check_device(P);
+  if (st != ESD_OK) return st;
+  if (!stage_ckpt_dev || !ubar_dev || !ws_dev || nsteps < 0 || !std::isfinite(dt))
+    return fail(ESD_EINVAL, "bad argument");
+  if (((uintptr_t)ws_dev) % 256 != 0) return fail(ESD_EINVAL, "workspace not 256-byte aligned");
+  if (!P->conn_involutive) return fail(ESD_EUNSUPPORTED, "facet permutation is not an involution");
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t n = P->ne * P->nc * P->ref.NP;
+  const size_t nb = align256((size_t)n * sizeof(double));
+  esd::Workspace w = split_ws(P, ws_dev);
+  double* kb = (double*)((char*)ws_dev + P->vjp_ws_bytes);
+  double* G = (double*)((char*)ws_dev + P->vjp_ws_bytes + nb);
+  double* acc = (double*)((char*)ws_dev + P->vjp_ws_bytes + 2 * nb);
+  // reverse of U_k = u + c_k dt k_{k-1}, u+ = u + dt/6 (k1 + 2 k2 + 2 k3 + k4)
+  const double cu[4] = {dt / 6.0, dt / 3.0, dt / 3.0, dt / 6.0};   // weight of stage k in u+
+  const double cs[4] = {0.5 * dt, 0.5 * dt, dt, 0.0};               // weight of k_k in U_{k+1}
+  for (int step = nsteps - 1; step >= 0; --step) {
+    int rc = esd::launch_scale(kb, ubar_dev, cu[3], n, s);
+    for (int stg = 3; stg >= 0 && rc == 0; --stg) {
+      const double* U = stage_ckpt_dev + ((int64_t)4 * step + stg) * n;
+      rc = esd::launch_vjp(P, U, kb, G, w, s);
+      if (rc != 0) break;
+      if (stg > 0)
+        rc = esd::launch_adj_stage(acc, kb, ubar_dev, G, cu[stg - 1], cs[stg - 1], stg == 3, n, s);
+      else
+        rc = esd::launch_axpy(ubar_dev, acc, 1.0, G, n, s);
+    }
+    if (rc < 0) return fail(ESD_EUNSUPPORTED, "degree not built");
+    if (rc != 0) return fail(ESD_EHIP, std::string("adjoint launch failed: ") + hipGetErrorString((hipError_t)rc));
+  }
   return ESD_OK;
 }
 

@@ -1,0 +1,420 @@
+// Device building blocks shared by the forward and adjoint kernels (gfx950):
+// element shapes and launch shapes per degree, PKD mode indexing, the
+// sum-factorised transforms V and V^T (Sec. 5.2), facet extrapolation R and its
+// transpose (eqs. r_2d, r_3d), and node records in LDS.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "physics.hpp"
+#include "plan.hpp"
+
+namespace esd {
+
+// degrees built into the library, per dimension
+#define ESD_TRI_DEGREES(X) X(2, 1) X(2, 2) X(2, 3) X(2, 4) X(2, 5) X(2, 6) X(2, 7) X(2, 8) X(2, 9) X(2, 10)
+#define ESD_TET_DEGREES(X) X(3, 1) X(3, 2) X(3, 3) X(3, 4) X(3, 5) X(3, 6) X(3, 7) X(3, 8)
+
+// ------------------------------------------------------------------ shapes
+template <int DIM, int P>
+struct Shape {
+  static constexpr int Q = P + 1;
+  static constexpr int NC = DIM + 2;
+  static constexpr int NQ = DIM == 2 ? Q * Q : Q * Q * Q;
+  static constexpr int NP = DIM == 2 ? (P + 1) * (P + 2) / 2 : (P + 1) * (P + 2) * (P + 3) / 6;
+  static constexpr int NF = DIM + 1;
+  static constexpr int NQF = DIM == 2 ? Q : Q * Q;
+  static constexpr int NFQ = NF * NQF;
+  static constexpr int NPAIR = (P + 1) * (P + 2) / 2;
+  static constexpr int NGV = DIM == 2 ? 8 : 17;
+  static constexpr int LPF = DIM == 2 ? Q : Q * Q;           // lines per family
+  static constexpr int NLINES = DIM * LPF;
+  static constexpr int T1 = DIM == 2 ? NC * (P + 1) * Q : NC * NPAIR * Q;
+  static constexpr int T2 = DIM == 2 ? 0 : NC * (P + 1) * Q * Q;
+  static constexpr int SCR = (T1 + T2 > 8 * NQ) ? (T1 + T2) : 8 * NQ;   // per element
+};
+
+template <int DIM, int P>
+struct Launch;  // block size and elements per block
+template <int P>
+struct Launch<3, P> {
+  // one element per workgroup; small workgroups keep several elements in
+  // flight per CU, which hides the latency of the barrier-separated phases
+  static constexpr int EPB = 1;
+  static constexpr int BS = P <= 3 ? 64 : (P == 4 ? 128 : (P <= 6 ? 192 : 256));
+};
+template <int P>
+struct Launch<2, P> {
+  static constexpr int EPB = (P <= 4) ? 12 : ((P <= 7) ? 8 : 6);
+  static constexpr int NQ = (P + 1) * (P + 1);
+  static constexpr int BS = ((EPB * NQ + 63) / 64) * 64;
+};
+
+__device__ __forceinline__ int pair_index(int P, int a1, int a2) { return a1 * (P + 1) - a1 * (a1 - 1) / 2 + a2; }
+__device__ __forceinline__ void decode_pair(int P, int pr, int& a1, int& a2) {
+  a1 = 0;
+  int cnt = P + 1;
+  while (pr >= cnt) {
+    pr -= cnt;
+    ++a1;
+    --cnt;
+  }
+  a2 = pr;
+}
+__device__ __forceinline__ int tet_mode_base(int P, int a1, int a2) {
+  int b = 0;
+  for (int i = 0; i < a1; ++i) b += (P + 1 - i) * (P + 2 - i) / 2;
+  return b + a2 * (P + 1 - a1) - a2 * (a2 - 1) / 2;
+}
+__device__ __forceinline__ void decode_tet_mode(int P, int m, int& a1, int& a2, int& a3) {
+  a1 = 0;
+  int cnt = (P + 1) * (P + 2) / 2;
+  while (m >= cnt) {
+    m -= cnt;
+    ++a1;
+    cnt = (P + 1 - a1) * (P + 2 - a1) / 2;
+  }
+  a2 = 0;
+  cnt = P + 1 - a1;
+  while (m >= cnt) {
+    m -= cnt;
+    ++a2;
+    --cnt;
+  }
+  a3 = m;
+}
+__device__ __forceinline__ void decode_tri_mode(int P, int m, int& a1, int& a2) {
+  a1 = 0;
+  int cnt = P + 1;
+  while (m >= cnt) {
+    m -= cnt;
+    ++a1;
+    --cnt;
+  }
+  a2 = m;
+}
+
+// ------------------------------------------------------------------ sum-factorised PKD transforms
+// in/out arrays are [nel*NC][...] contiguous per (element, variable); all
+// threads of the block participate; each call ends with a barrier.  Every
+// thread produces a whole line of outputs from one set of LDS loads
+// (register blocking along the contracted direction).
+template <int DIM, int P>
+__device__ void xform_V(const double* uh, double* T1, double* T2, double* out, const DevTables& T, int nec) {
+  using S = Shape<DIM, P>;
+  constexpr int Q = S::Q;
+  constexpr int XU = Q <= 7 ? Q : 1;   // unroll the contraction while its table fits scalar registers
+  const int tid = threadIdx.x, nth = blockDim.x;
+  if constexpr (DIM == 2) {
+    // T1[ec][a1][i2] = sum_a2 psi2[a1][a2][i2] u~[ec][(a1,a2)]
+    for (int o = tid; o < nec * (P + 1); o += nth) {
+      const int a1 = o % (P + 1), ec = o / (P + 1);
+      const int mb = a1 * (P + 1) - a1 * (a1 - 1) / 2;
+      double acc[Q];
+#pragma unroll
+      for (int i = 0; i < Q; ++i) acc[i] = 0.0;
+#pragma unroll XU
+      for (int a2 = 0; a2 <= P; ++a2) {
+        if (a2 <= P - a1) {
+          const double x = uh[ec * S::NP + mb + a2];
+          const double* ps = T.psi2 + (a1 * (P + 1) + a2) * Q;
+#pragma unroll
+          for (int i = 0; i < Q; ++i) acc[i] += ps[i] * x;
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < Q; ++i) T1[(ec * (P + 1) + a1) * Q + i] = acc[i];
+    }
+    __syncthreads();
+    // out[ec][i1 + Q i2] = sum_a1 psi1[a1][i1] T1[ec][a1][i2]
+    for (int o = tid; o < nec * Q; o += nth) {
+      const int i2 = o % Q, ec = o / Q;
+      double acc[Q];
+#pragma unroll
+      for (int i = 0; i < Q; ++i) acc[i] = 0.0;
+#pragma unroll XU
+      for (int a1 = 0; a1 <= P; ++a1) {
+        const double x = T1[(ec * (P + 1) + a1) * Q + i2];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) acc[i] += T.psi1[a1 * Q + i] * x;
+      }
+#pragma unroll
+      for (int i = 0; i < Q; ++i) out[ec * S::NQ + i + Q * i2] = acc[i];
+    }
+    __syncthreads();
+  } else {
+    // T1[ec][pr][i3] = sum_a3 psi3[s][a3][i3] u~[ec][(a1,a2,a3)]
+    for (int o = tid; o < nec * S::NPAIR; o += nth) {
+      const int pr = o % S::NPAIR, ec = o / S::NPAIR;
+      int a1, a2;
+      decode_pair(P, pr, a1, a2);
+      const int s = a1 + a2, mb = tet_mode_base(P, a1, a2);
+      double acc[Q];
+#pragma unroll
+      for (int i = 0; i < Q; ++i) acc[i] = 0.0;
+#pragma unroll XU
+      for (int a3 = 0; a3 <= P; ++a3) {
+        if (a3 <= P - s) {
+          const double x = uh[ec * S::NP + mb + a3];
+          const double* ps = T.psi3 + (s * (P + 1) + a3) * Q;
+#pragma unroll
+          for (int i = 0; i < Q; ++i) acc[i] += ps[i] * x;
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < Q; ++i) T1[(ec * S::NPAIR + pr) * Q + i] = acc[i];
+    }
+    __syncthreads();
+    // T2[ec][a1][i2 + Q i3] = sum_a2 psi2[a1][a2][i2] T1[ec][(a1,a2)][i3]
+    for (int o = tid; o < nec * (P + 1) * Q; o += nth) {
+      const int i3 = o % Q, a1 = (o / Q) % (P + 1), ec = o / (Q * (P + 1));
+      const int pb = pair_index(P, a1, 0);
+      double acc[Q];
+#pragma unroll
+      for (int i = 0; i < Q; ++i) acc[i] = 0.0;
+#pragma unroll XU
+      for (int a2 = 0; a2 <= P; ++a2) {
+        if (a2 <= P - a1) {
+          const double x = T1[(ec * S::NPAIR + pb + a2) * Q + i3];
+          const double* ps = T.psi2 + (a1 * (P + 1) + a2) * Q;
+#pragma unroll
+          for (int i = 0; i < Q; ++i) acc[i] += ps[i] * x;
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < Q; ++i) T2[(ec * (P + 1) + a1) * Q * Q + i + Q * i3] = acc[i];
+    }
+    __syncthreads();
+    // out[ec][i1 + Q i2 + Q^2 i3] = sum_a1 psi1[a1][i1] T2[ec][a1][i2 + Q i3]
+    for (int o = tid; o < nec * Q * Q; o += nth) {
+      const int i23 = o % (Q * Q), ec = o / (Q * Q);
+      double acc[Q];
+#pragma unroll
+      for (int i = 0; i < Q; ++i) acc[i] = 0.0;
+#pragma unroll XU
+      for (int a1 = 0; a1 <= P; ++a1) {
+        const double x = T2[(ec * (P + 1) + a1) * Q * Q + i23];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) acc[i] += T.psi1[a1 * Q + i] * x;
+      }
+#pragma unroll
+      for (int i = 0; i < Q; ++i) out[ec * S::NQ + i + Q * i23] = acc[i];
+    }
+    __syncthreads();
+  }
+}
+
+template <int DIM, int P>
+__device__ void xform_Vt(const double* in, double* T1, double* T2, double* out, const DevTables& T, int nec) {
+  using S = Shape<DIM, P>;
+  constexpr int Q = S::Q;
+  constexpr int XU = Q <= 7 ? Q : 1;   // unroll the contraction while its table fits scalar registers
+  const int tid = threadIdx.x, nth = blockDim.x;
+  if constexpr (DIM == 2) {
+    // T1[ec][a1][i2] = sum_i1 psi1[a1][i1] in[ec][i1 + Q i2]
+    for (int o = tid; o < nec * Q; o += nth) {
+      const int i2 = o % Q, ec = o / Q;
+      double acc[P + 1];
+#pragma unroll
+      for (int a = 0; a <= P; ++a) acc[a] = 0.0;
+#pragma unroll XU
+      for (int i1 = 0; i1 < Q; ++i1) {
+        const double x = in[ec * S::NQ + i1 + Q * i2];
+#pragma unroll
+        for (int a = 0; a <= P; ++a) acc[a] += T.psi1[a * Q + i1] * x;
+      }
+#pragma unroll
+      for (int a = 0; a <= P; ++a) T1[(ec * (P + 1) + a) * Q + i2] = acc[a];
+    }
+    __syncthreads();
+    // out[ec][(a1,a2)] = sum_i2 psi2[a1][a2][i2] T1[ec][a1][i2]
+    for (int o = tid; o < nec * (P + 1); o += nth) {
+      const int a1 = o % (P + 1), ec = o / (P + 1);
+      const int mb = a1 * (P + 1) - a1 * (a1 - 1) / 2;
+      double acc[P + 1];
+#pragma unroll
+      for (int a = 0; a <= P; ++a) acc[a] = 0.0;
+#pragma unroll XU
+      for (int i2 = 0; i2 < Q; ++i2) {
+        const double x = T1[(ec * (P + 1) + a1) * Q + i2];
+#pragma unroll
+        for (int a = 0; a <= P; ++a) acc[a] += T.psi2[(a1 * (P + 1) + a) * Q + i2] * x;
+      }
+#pragma unroll
+      for (int a = 0; a <= P; ++a)
+        if (a <= P - a1) out[ec * S::NP + mb + a] = acc[a];
+    }
+    __syncthreads();
+  } else {
+    // T2[ec][a1][i2 + Q i3] = sum_i1 psi1[a1][i1] in[ec][i1 + Q i2 + Q^2 i3]
+    for (int o = tid; o < nec * Q * Q; o += nth) {
+      const int i23 = o % (Q * Q), ec = o / (Q * Q);
+      double acc[P + 1];
+#pragma unroll
+      for (int a = 0; a <= P; ++a) acc[a] = 0.0;
+#pragma unroll XU
+      for (int i1 = 0; i1 < Q; ++i1) {
+        const double x = in[ec * S::NQ + i1 + Q * i23];
+#pragma unroll
+        for (int a = 0; a <= P; ++a) acc[a] += T.psi1[a * Q + i1] * x;
+      }
+#pragma unroll
+      for (int a = 0; a <= P; ++a) T2[(ec * (P + 1) + a) * Q * Q + i23] = acc[a];
+    }
+    __syncthreads();
+    // T1[ec][(a1,a2)][i3] = sum_i2 psi2[a1][a2][i2] T2[ec][a1][i2 + Q i3]
+    for (int o = tid; o < nec * (P + 1) * Q; o += nth) {
+      const int i3 = o % Q, a1 = (o / Q) % (P + 1), ec = o / (Q * (P + 1));
+      const int pb = pair_index(P, a1, 0);
+      double acc[P + 1];
+#pragma unroll
+      for (int a = 0; a <= P; ++a) acc[a] = 0.0;
+#pragma unroll XU
+      for (int i2 = 0; i2 < Q; ++i2) {
+        const double x = T2[(ec * (P + 1) + a1) * Q * Q + i2 + Q * i3];
+#pragma unroll
+        for (int a = 0; a <= P; ++a) acc[a] += T.psi2[(a1 * (P + 1) + a) * Q + i2] * x;
+      }
+#pragma unroll
+      for (int a = 0; a <= P; ++a)
+        if (a <= P - a1) T1[(ec * S::NPAIR + pb + a) * Q + i3] = acc[a];
+    }
+    __syncthreads();
+    // out[ec][(a1,a2,a3)] = sum_i3 psi3[s][a3][i3] T1[ec][(a1,a2)][i3]
+    for (int o = tid; o < nec * S::NPAIR; o += nth) {
+      const int pr = o % S::NPAIR, ec = o / S::NPAIR;
+      int a1, a2;
+      decode_pair(P, pr, a1, a2);
+      const int s = a1 + a2, mb = tet_mode_base(P, a1, a2);
+      double acc[P + 1];
+#pragma unroll
+      for (int a = 0; a <= P; ++a) acc[a] = 0.0;
+#pragma unroll XU
+      for (int i3 = 0; i3 < Q; ++i3) {
+        const double x = T1[(ec * S::NPAIR + pr) * Q + i3];
+#pragma unroll
+        for (int a = 0; a <= P; ++a) acc[a] += T.psi3[(s * (P + 1) + a) * Q + i3] * x;
+      }
+#pragma unroll
+      for (int a = 0; a <= P; ++a)
+        if (a <= P - s) out[ec * S::NP + mb + a] = acc[a];
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ node data in LDS
+// node data layout in LDS: [8][stride] = rho, ln rho, b = rho/p, ln b, p, v1, v2, v3
+template <int DIM>
+__device__ __forceinline__ Node<DIM> load_node(const double* s, int stride, int k) {
+  Node<DIM> n;
+  n.rho = s[0 * stride + k];
+  n.lnrho = s[1 * stride + k];
+  n.b = s[2 * stride + k];
+  n.lnb = s[3 * stride + k];
+  n.p = s[4 * stride + k];
+#pragma unroll
+  for (int i = 0; i < DIM; ++i) n.v[i] = s[(5 + i) * stride + k];
+  return n;
+}
+template <int DIM>
+__device__ __forceinline__ void store_node(double* s, int stride, int k, const Node<DIM>& n) {
+  s[0 * stride + k] = n.rho;
+  s[1 * stride + k] = n.lnrho;
+  s[2 * stride + k] = n.b;
+  s[3 * stride + k] = n.lnb;
+  s[4 * stride + k] = n.p;
+#pragma unroll
+  for (int i = 0; i < DIM; ++i) s[(5 + i) * stride + k] = n.v[i];
+}
+
+// ------------------------------------------------------------------ facet extrapolation and its transpose
+// Facet values (R w)[ec][facet*NQF + node] of nodal fields w [nec][NQ] (eqs.
+// r_2d, r_3d), passed to store(o, value) with o = ec*NFQ + facet*NQF + node.
+// Triangles: facet 1 interpolates along eta2 to -1, facets 2 and 3 along eta1
+// to +1 / -1.  Tetrahedra: faces 1-3 likewise along eta2 / eta1; face 4 first
+// contracts eta3 -> -1 into scr [nec][Q*Q], then maps the eta2 line to the
+// face's own Legendre nodes (I42).  No barrier at the end.
+template <int DIM, int P, typename Store>
+__device__ __forceinline__ void facet_values(const double* w_all, double* scr, const DevTables& T, int nec,
+                                             Store store) {
+  using S = Shape<DIM, P>;
+  constexpr int Q = S::Q, NQ = S::NQ, NQF = S::NQF, NFQ = S::NFQ;
+  const int tid = threadIdx.x, nth = blockDim.x;
+  if constexpr (DIM == 3) {
+    for (int o = tid; o < nec * Q * Q; o += nth) {
+      const int a1 = o % Q, k2 = (o / Q) % Q, ec = o / (Q * Q);
+      double acc = 0.0;
+#pragma unroll
+      for (int k3 = 0; k3 < Q; ++k3) acc += T.gjm1[k3] * w_all[ec * NQ + a1 + Q * k2 + Q * Q * k3];
+      scr[o] = acc;
+    }
+    __syncthreads();
+  }
+  for (int o = tid; o < nec * NFQ; o += nth) {
+    const int jj = o % NFQ, ec = o / NFQ, f = jj / NQF, j = jj % NQF;
+    const double* w = w_all + ec * NQ;
+    double acc = 0.0;
+    if constexpr (DIM == 2) {
+      if (f == 0) {
+#pragma unroll
+        for (int k = 0; k < Q; ++k) acc += T.lgm1[k] * w[j + Q * k];
+      } else {
+        const double* l = (f == 1) ? T.lgp1 : T.lgm1;
+#pragma unroll
+        for (int k = 0; k < Q; ++k) acc += l[k] * w[k + Q * j];
+      }
+    } else {
+      const int a1 = j % Q, a2 = j / Q;
+      if (f == 0) {
+#pragma unroll
+        for (int k = 0; k < Q; ++k) acc += T.lgm1[k] * w[a1 + Q * k + Q * Q * a2];
+      } else if (f == 3) {
+#pragma unroll
+        for (int k = 0; k < Q; ++k) acc += T.I42[a2 * Q + k] * scr[ec * Q * Q + a1 + Q * k];
+      } else {
+        const double* l = (f == 1) ? T.lgp1 : T.lgm1;
+#pragma unroll
+        for (int k = 0; k < Q; ++k) acc += l[k] * w[k + Q * a1 + Q * Q * a2];
+      }
+    }
+    store(o, acc);
+  }
+}
+
+// Transpose of facet_values: (R^T s)[ec][k] for facet fields s [nec][NFQ],
+// passed to apply(o, value) with o = ec*NQ + k.  Tet face 4 is first
+// contracted back over its eta2 index into scr [nec][Q*Q].  No barrier at the end.
+template <int DIM, int P, typename Apply>
+__device__ __forceinline__ void facet_lift(const double* s_all, double* scr, const DevTables& T, int nec,
+                                           Apply apply) {
+  using S = Shape<DIM, P>;
+  constexpr int Q = S::Q, NQ = S::NQ, NQF = S::NQF, NFQ = S::NFQ;
+  const int tid = threadIdx.x, nth = blockDim.x;
+  if constexpr (DIM == 3) {
+    for (int o = tid; o < nec * Q * Q; o += nth) {
+      const int b1 = o % Q, b2 = (o / Q) % Q, ec = o / (Q * Q);
+      double acc4 = 0.0;
+#pragma unroll
+      for (int a2 = 0; a2 < Q; ++a2) acc4 += T.I42[a2 * Q + b2] * s_all[ec * NFQ + 3 * NQF + b1 + Q * a2];
+      scr[o] = acc4;
+    }
+    __syncthreads();
+  }
+  for (int o = tid; o < nec * NQ; o += nth) {
+    const int k = o % NQ, ec = o / NQ;
+    const double* s = s_all + ec * NFQ;
+    double d;
+    if constexpr (DIM == 2) {
+      const int b1 = k % Q, b2 = k / Q;
+      d = T.lgm1[b2] * s[0 * NQF + b1] + T.lgp1[b1] * s[1 * NQF + b2] + T.lgm1[b1] * s[2 * NQF + b2];
+    } else {
+      const int b1 = k % Q, b2 = (k / Q) % Q, b3 = k / (Q * Q);
+      d = T.lgm1[b2] * s[0 * NQF + b1 + Q * b3] + T.lgp1[b1] * s[1 * NQF + b2 + Q * b3] +
+          T.lgm1[b1] * s[2 * NQF + b2 + Q * b3] + T.gjm1[b3] * scr[ec * Q * Q + b1 + Q * b2];
+    }
+    apply(o, d);
+  }
+}
+
+}  // namespace esd

@@ -1,0 +1,386 @@
+// Euler physics of the entropy-stable scheme, forward and vector-Jacobian
+// products, as pure functions usable from device and host code.
+//
+//  - entropy variables W = dS/dU of S = -rho s/(gamma-1), s = ln p - gamma ln rho
+//    (eq. euler_entropy) and their inverse U(W);
+//  - logarithmic mean (a+ - a-)/(ln a+ - ln a-) and its reciprocal, with a
+//    series for nearly equal arguments;
+//  - Ranocha's entropy-conservative flux (eq. ranocha_flux; the 1/2 of the
+//    energy component multiplies v-.v+ only) and Chandrashekar's;
+//  - the interface flux f# - lambda/2 [u] with Davis' wave speed (eqs.
+//    num_flux, wave_speed), scaled by the facet Jacobian.
+// Node states are cached as (rho, ln rho, b = rho/p, ln b, p, v).
+#pragma once
+
+#include <cmath>
+
+#if defined(__HIPCC__)
+#include <hip/hip_runtime.h>
+#define ESD_HD __host__ __device__ __forceinline__
+#else
+#define ESD_HD inline
+#endif
+
+namespace esd {
+
+constexpr int FLUX_RANOCHA = 0;
+constexpr int FLUX_CHANDRASHEKAR = 1;
+constexpr double LOG_SERIES_THRESHOLD = 1.0e-4;
+
+template <int DIM>
+struct Node {
+  double rho, lnrho, b, lnb, p, v[DIM];
+};
+
+// cotangent of a node state, same fields
+template <int DIM>
+struct NodeBar {
+  double rho, lnrho, b, lnb, p, v[DIM];
+};
+
+template <int DIM>
+ESD_HD void zero(NodeBar<DIM>& x) {
+  x.rho = x.lnrho = x.b = x.lnb = x.p = 0.0;
+  for (int i = 0; i < DIM; ++i) x.v[i] = 0.0;
+}
+
+// 1/x: hardware reciprocal estimate refined by two Newton-Raphson steps
+// (each squares the relative error), correct to within an ulp
+ESD_HD double frcp(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(fma(-x, r, 1.0), r, r);
+  r = fma(fma(-x, r, 1.0), r, r);
+  return r;
+#else
+  return 1.0 / x;
+#endif
+}
+
+// U(w): entropy-projected state from entropy variables w = (w1, w_v, w_last).
+// b = -w_last = rho/p, v = w_v/b, s = gamma - (gamma-1)(w1 + b|v|^2/2),
+// ln rho = -(s + ln b)/(gamma-1), p = rho/b.  Returns false if inadmissible.
+template <int DIM>
+ESD_HD bool from_entropy(const double* w, double gamma, double gm1_inv, Node<DIM>& n) {
+  const double b = -w[DIM + 1];
+  const double ib = frcp(b);
+  double v2 = 0.0;
+  for (int i = 0; i < DIM; ++i) {
+    n.v[i] = w[1 + i] * ib;
+    v2 += n.v[i] * n.v[i];
+  }
+  const double s = gamma - (gamma - 1.0) * (w[0] + 0.5 * b * v2);
+  n.b = b;
+  n.lnb = log(b);
+  n.lnrho = -(s + n.lnb) * gm1_inv;
+  n.rho = exp(n.lnrho);
+  n.p = n.rho * ib;
+  return (b > 0.0) && __builtin_isfinite(n.rho) && __builtin_isfinite(n.p) && (n.rho > 0.0);
+}
+
+// Node cotangents in the independent parameterisation x = (ln rho, ln b, v)
+// (rho = e^{ln rho}, b = e^{ln b}, p = e^{ln rho - ln b}): NC numbers per node
+template <int DIM>
+ESD_HD void reduce_bar(const Node<DIM>& n, const NodeBar<DIM>& nb, double* xb) {
+  xb[0] = nb.lnrho + n.rho * nb.rho + n.p * nb.p;
+  xb[1] = nb.lnb + n.b * nb.b - n.p * nb.p;
+  for (int i = 0; i < DIM; ++i) xb[2 + i] = nb.v[i];
+}
+
+// w_bar = (dx/dw)^T x_bar for the node n = U(w):
+//   ln b = ln(-w_last), v = w_v / b, ln rho = w1 - gamma/(gamma-1) + |w_v|^2/(2b) - ln b/(gamma-1)
+template <int DIM>
+ESD_HD void xbar_to_wbar(const Node<DIM>& n, const double* xb, double gm1_inv, double* wb) {
+  const double ib = frcp(n.b);
+  const double L = xb[0];
+  double v2 = 0.0, vx = 0.0;
+  for (int i = 0; i < DIM; ++i) {
+    v2 += n.v[i] * n.v[i];
+    vx += n.v[i] * xb[2 + i];
+    wb[1 + i] = L * n.v[i] + xb[2 + i] * ib;
+  }
+  wb[0] = L;
+  // cotangent of b as the independent variable, b = -w_last
+  wb[DIM + 1] = -((xb[1] - vx) * ib - L * (0.5 * v2 + gm1_inv * ib));
+}
+
+// entropy variables from conservative u = (rho, m, E)
+template <int DIM>
+ESD_HD void entropy_vars(const double* u, double gamma, double gm1_inv, double* w) {
+  const double rho = u[0];
+  double m2 = 0.0;
+  for (int i = 0; i < DIM; ++i) m2 += u[1 + i] * u[1 + i];
+  const double p = (gamma - 1.0) * (u[DIM + 1] - 0.5 * m2 / rho);
+  const double s = log(p) - gamma * log(rho);
+  w[0] = (gamma - s) * gm1_inv - 0.5 * m2 / (rho * p);
+  for (int i = 0; i < DIM; ++i) w[1 + i] = u[1 + i] / p;
+  w[DIM + 1] = -rho / p;
+}
+
+// u_bar += (dW/du)^T w_bar
+template <int DIM>
+ESD_HD void entropy_vars_vjp(const double* u, const double* wb, double gamma, double gm1_inv, double* ub) {
+  const double rho = u[0];
+  double m2 = 0.0;
+  for (int i = 0; i < DIM; ++i) m2 += u[1 + i] * u[1 + i];
+  const double p = (gamma - 1.0) * (u[DIM + 1] - 0.5 * m2 * frcp(rho));
+  const double ip = frcp(p), ir = frcp(rho);
+  // w1 = g(gamma - ln p + gamma ln rho) - m2/(2 rho p); w_v = m/p; w_last = -rho/p
+  double pb = wb[0] * (-gm1_inv * ip + 0.5 * m2 * ir * ip * ip) + wb[DIM + 1] * rho * ip * ip;
+  for (int i = 0; i < DIM; ++i) pb -= wb[1 + i] * u[1 + i] * ip * ip;
+  double rb = wb[0] * (gm1_inv * gamma * ir + 0.5 * m2 * ir * ir * ip) - wb[DIM + 1] * ip;
+  // p = (gamma-1)(E - m2/(2 rho))
+  rb += pb * (gamma - 1.0) * 0.5 * m2 * ir * ir;
+  ub[0] += rb;
+  for (int i = 0; i < DIM; ++i)
+    ub[1 + i] += -wb[0] * u[1 + i] * ir * ip + wb[1 + i] * ip - pb * (gamma - 1.0) * u[1 + i] * ir;
+  ub[DIM + 1] += pb * (gamma - 1.0);
+}
+
+// ---------------------------------------------------------------- logarithmic means
+// {a}_ln = (a- + a+)/2 * f/atanh f  (series: 1 - u/3 - 4u^2/45 - 44u^3/945, u = f^2),
+// 1/{a}_ln = 2 (1 + u/3 + u^2/5 + u^3/7)/(a- + a+); truncation below 3e-18.
+// inv_s = 1/(a- + a+).
+ESD_HD double log_mean(double a, double b, double la, double lb, double inv_s) {
+  const double d = b - a;
+  const double f = d * inv_s, u = f * f;
+  if (u < LOG_SERIES_THRESHOLD) return 0.5 * (a + b) * (1.0 - u * (1.0 / 3.0 + u * (4.0 / 45.0 + u * (44.0 / 945.0))));
+  return d / (lb - la);
+}
+ESD_HD double inv_log_mean(double a, double b, double la, double lb, double inv_s) {
+  const double d = b - a;
+  const double f = d * inv_s, u = f * f;
+  if (u < LOG_SERIES_THRESHOLD) return 2.0 * (1.0 + u * (1.0 / 3.0 + u * (1.0 / 5.0 + u * (1.0 / 7.0)))) * inv_s;
+  return (lb - la) / d;
+}
+
+// partial derivatives of the two means w.r.t. (a, b, la, lb) on the branch the
+// forward evaluation takes
+ESD_HD void log_mean_grad(double a, double b, double la, double lb, double* g) {
+  const double s = a + b, d = b - a, is = frcp(s);
+  const double f = d * is, u = f * f;
+  if (u < LOG_SERIES_THRESHOLD) {
+    const double t = 1.0 - u * (1.0 / 3.0 + u * (4.0 / 45.0 + u * (44.0 / 945.0)));
+    const double dt = -(1.0 / 3.0 + u * (8.0 / 45.0 + u * (132.0 / 945.0)));
+    // du/da = 2 f df/da, df/da = -2b/s^2, df/db = 2a/s^2
+    const double dua = 2.0 * f * (-2.0 * b * is * is), dub = 2.0 * f * (2.0 * a * is * is);
+    g[0] = 0.5 * t + 0.5 * s * dt * dua;
+    g[1] = 0.5 * t + 0.5 * s * dt * dub;
+    g[2] = g[3] = 0.0;
+    return;
+  }
+  const double il = frcp(lb - la), L = d * il;
+  g[0] = -il;
+  g[1] = il;
+  g[2] = L * il;
+  g[3] = -L * il;
+}
+ESD_HD void inv_log_mean_grad(double a, double b, double la, double lb, double* g) {
+  const double s = a + b, d = b - a, is = frcp(s);
+  const double f = d * is, u = f * f;
+  if (u < LOG_SERIES_THRESHOLD) {
+    const double S = 1.0 + u * (1.0 / 3.0 + u * (1.0 / 5.0 + u * (1.0 / 7.0)));
+    const double dS = 1.0 / 3.0 + u * (2.0 / 5.0 + u * (3.0 / 7.0));
+    const double dua = 2.0 * f * (-2.0 * b * is * is), dub = 2.0 * f * (2.0 * a * is * is);
+    g[0] = 2.0 * dS * dua * is - 2.0 * S * is * is;
+    g[1] = 2.0 * dS * dub * is - 2.0 * S * is * is;
+    g[2] = g[3] = 0.0;
+    return;
+  }
+  const double id = frcp(d), I = (lb - la) * id;
+  g[0] = I * id;
+  g[1] = -I * id;
+  g[2] = -id;
+  g[3] = id;
+}
+
+// ---------------------------------------------------------------- EC two-point flux
+// directional flux f#(A, B, n) = sum_m n_m f#_m(A, B)
+template <int DIM, int FLUX>
+ESD_HD void ec_flux(const Node<DIM>& A, const Node<DIM>& B, const double* n, double gm1_inv, double* F) {
+  // one reciprocal serves both means: 1/(sr sb) -> 1/sr = sb/(sr sb), 1/sb = sr/(sr sb)
+  const double sr = A.rho + B.rho, sb = A.b + B.b;
+  const double rr = frcp(sr * sb);
+  const double rho_ln = log_mean(A.rho, B.rho, A.lnrho, B.lnrho, sb * rr);
+  const double ib_ln = inv_log_mean(A.b, B.b, A.lnb, B.lnb, sr * rr);   // 1 / {rho/p}_ln
+  double vavg[DIM];
+  double vn = 0.0, vab = 0.0, van = 0.0, vbn = 0.0;
+  for (int i = 0; i < DIM; ++i) {
+    vavg[i] = 0.5 * (A.v[i] + B.v[i]);
+    vn += vavg[i] * n[i];
+    vab += A.v[i] * B.v[i];
+    van += A.v[i] * n[i];
+    vbn += B.v[i] * n[i];
+  }
+  const double frho = rho_ln * vn;
+  F[0] = frho;
+  if (FLUX == FLUX_RANOCHA) {
+    const double pavg = 0.5 * (A.p + B.p);
+    for (int i = 0; i < DIM; ++i) F[1 + i] = frho * vavg[i] + pavg * n[i];
+    F[DIM + 1] = frho * (0.5 * vab + ib_ln * gm1_inv) + 0.5 * (A.p * vbn + B.p * van);
+  } else {
+    const double phat = sr * sr * rr;   // {rho} / (2 {beta}) = sr/sb, beta = b/2
+    for (int i = 0; i < DIM; ++i) F[1 + i] = frho * vavg[i] + phat * n[i];
+    F[DIM + 1] = frho * (0.5 * vab + ib_ln * gm1_inv) + phat * vn;
+  }
+}
+
+// (dF/dA)^T Fb and (dF/dB)^T Fb, accumulated into Ab, Bb (n held fixed)
+template <int DIM, int FLUX>
+ESD_HD void ec_flux_vjp(const Node<DIM>& A, const Node<DIM>& B, const double* n, double gm1_inv, const double* Fb,
+                        NodeBar<DIM>& Ab, NodeBar<DIM>& Bb) {
+  const double sr = A.rho + B.rho, sb = A.b + B.b;
+  const double rr = frcp(sr * sb);
+  const double rho_ln = log_mean(A.rho, B.rho, A.lnrho, B.lnrho, sb * rr);
+  const double ib_ln = inv_log_mean(A.b, B.b, A.lnb, B.lnb, sr * rr);
+  double vavg[DIM];
+  double vn = 0.0, vab = 0.0, van = 0.0, vbn = 0.0;
+  for (int i = 0; i < DIM; ++i) {
+    vavg[i] = 0.5 * (A.v[i] + B.v[i]);
+    vn += vavg[i] * n[i];
+    vab += A.v[i] * B.v[i];
+    van += A.v[i] * n[i];
+    vbn += B.v[i] * n[i];
+  }
+  const double frho = rho_ln * vn;
+  // reverse sweep
+  double frho_b = Fb[0];
+  double vavg_b[DIM];
+  for (int i = 0; i < DIM; ++i) {
+    frho_b += Fb[1 + i] * vavg[i];
+    vavg_b[i] = Fb[1 + i] * frho;
+  }
+  frho_b += Fb[DIM + 1] * (0.5 * vab + ib_ln * gm1_inv);
+  const double vab_b = Fb[DIM + 1] * frho * 0.5;
+  const double ib_b = Fb[DIM + 1] * frho * gm1_inv;
+  double vn_b = 0.0, van_b = 0.0, vbn_b = 0.0;
+  if (FLUX == FLUX_RANOCHA) {
+    double pavg_b = 0.0;
+    for (int i = 0; i < DIM; ++i) pavg_b += Fb[1 + i] * n[i];
+    Ab.p += 0.5 * pavg_b + 0.5 * Fb[DIM + 1] * vbn;
+    Bb.p += 0.5 * pavg_b + 0.5 * Fb[DIM + 1] * van;
+    vbn_b = 0.5 * Fb[DIM + 1] * A.p;
+    van_b = 0.5 * Fb[DIM + 1] * B.p;
+  } else {
+    const double isb = sr * rr, phat = sr * isb;
+    double phat_b = Fb[DIM + 1] * vn;
+    for (int i = 0; i < DIM; ++i) phat_b += Fb[1 + i] * n[i];
+    vn_b += Fb[DIM + 1] * phat;
+    // phat = sr / sb
+    Ab.rho += phat_b * isb;
+    Bb.rho += phat_b * isb;
+    Ab.b -= phat_b * phat * isb;
+    Bb.b -= phat_b * phat * isb;
+  }
+  const double rho_ln_b = frho_b * vn;
+  vn_b += frho_b * rho_ln;
+  for (int i = 0; i < DIM; ++i) {
+    vavg_b[i] += vn_b * n[i];
+    Ab.v[i] += 0.5 * vavg_b[i] + vab_b * B.v[i] + van_b * n[i];
+    Bb.v[i] += 0.5 * vavg_b[i] + vab_b * A.v[i] + vbn_b * n[i];
+  }
+  double g[4];
+  log_mean_grad(A.rho, B.rho, A.lnrho, B.lnrho, g);
+  Ab.rho += rho_ln_b * g[0];
+  Bb.rho += rho_ln_b * g[1];
+  Ab.lnrho += rho_ln_b * g[2];
+  Bb.lnrho += rho_ln_b * g[3];
+  inv_log_mean_grad(A.b, B.b, A.lnb, B.lnb, g);
+  Ab.b += ib_b * g[0];
+  Bb.b += ib_b * g[1];
+  Ab.lnb += ib_b * g[2];
+  Bb.lnb += ib_b * g[3];
+}
+
+// ---------------------------------------------------------------- interface flux
+// J_f f*(U-, U+, n) with nJ = J_f n:  f#(U-, U+, nJ) - (J_f lambda)/2 (U+ - U-),
+// J_f lambda = max(|v-.nJ|, |v+.nJ|) + J_f max(c-, c+) (ties take the interior branch)
+template <int DIM, int FLUX>
+ESD_HD void interface_flux(const Node<DIM>& Um, const Node<DIM>& Up, const double* nJ, double Jf, double gamma,
+                           double gm1_inv, int dissipation, double* F) {
+  ec_flux<DIM, FLUX>(Um, Up, nJ, gm1_inv, F);
+  if (!dissipation) return;
+  double vmn = 0.0, vpn = 0.0, vm2 = 0.0, vp2 = 0.0;
+  for (int i = 0; i < DIM; ++i) {
+    vmn += Um.v[i] * nJ[i];
+    vpn += Up.v[i] * nJ[i];
+    vm2 += Um.v[i] * Um.v[i];
+    vp2 += Up.v[i] * Up.v[i];
+  }
+  const double am = fabs(vmn), ap = fabs(vpn);
+  const double cm = sqrt(gamma * Um.p / Um.rho), cp = sqrt(gamma * Up.p / Up.rho);
+  const double lam = (am >= ap ? am : ap) + Jf * (cm >= cp ? cm : cp);
+  const double h = 0.5 * lam;
+  F[0] -= h * (Up.rho - Um.rho);
+  for (int i = 0; i < DIM; ++i) F[1 + i] -= h * (Up.rho * Up.v[i] - Um.rho * Um.v[i]);
+  const double Em = Um.p * gm1_inv + 0.5 * Um.rho * vm2;
+  const double Ep = Up.p * gm1_inv + 0.5 * Up.rho * vp2;
+  F[DIM + 1] -= h * (Ep - Em);
+}
+
+template <int DIM>
+ESD_HD void cons_vjp(const Node<DIM>& N, const double* Ub, double gm1_inv, NodeBar<DIM>& Nb) {
+  // U = (rho, rho v, p/(gamma-1) + rho |v|^2/2)
+  double v2 = 0.0;
+  for (int i = 0; i < DIM; ++i) v2 += N.v[i] * N.v[i];
+  Nb.rho += Ub[0] + 0.5 * v2 * Ub[DIM + 1];
+  for (int i = 0; i < DIM; ++i) {
+    Nb.rho += Ub[1 + i] * N.v[i];
+    Nb.v[i] += Ub[1 + i] * N.rho + Ub[DIM + 1] * N.rho * N.v[i];
+  }
+  Nb.p += gm1_inv * Ub[DIM + 1];
+}
+
+template <int DIM, int FLUX>
+ESD_HD void interface_flux_vjp(const Node<DIM>& Um, const Node<DIM>& Up, const double* nJ, double Jf, double gamma,
+                               double gm1_inv, int dissipation, const double* Fb, NodeBar<DIM>& Umb,
+                               NodeBar<DIM>& Upb) {
+  ec_flux_vjp<DIM, FLUX>(Um, Up, nJ, gm1_inv, Fb, Umb, Upb);
+  if (!dissipation) return;
+  double vmn = 0.0, vpn = 0.0, vm2 = 0.0, vp2 = 0.0;
+  for (int i = 0; i < DIM; ++i) {
+    vmn += Um.v[i] * nJ[i];
+    vpn += Up.v[i] * nJ[i];
+    vm2 += Um.v[i] * Um.v[i];
+    vp2 += Up.v[i] * Up.v[i];
+  }
+  const double am = fabs(vmn), ap = fabs(vpn);
+  const double cm = sqrt(gamma * Um.p / Um.rho), cp = sqrt(gamma * Up.p / Up.rho);
+  const double lam = (am >= ap ? am : ap) + Jf * (cm >= cp ? cm : cp);
+  const double h = 0.5 * lam;
+  const double Em = Um.p * gm1_inv + 0.5 * Um.rho * vm2;
+  const double Ep = Up.p * gm1_inv + 0.5 * Up.rho * vp2;
+  double dU[DIM + 2];
+  dU[0] = Up.rho - Um.rho;
+  for (int i = 0; i < DIM; ++i) dU[1 + i] = Up.rho * Up.v[i] - Um.rho * Um.v[i];
+  dU[DIM + 1] = Ep - Em;
+  // F -= h dU
+  double h_b = 0.0;
+  double Ub[DIM + 2], Umb_c[DIM + 2];
+  for (int c = 0; c < DIM + 2; ++c) {
+    h_b -= Fb[c] * dU[c];
+    Ub[c] = -h * Fb[c];      // cotangent of U+ (and minus it for U-)
+    Umb_c[c] = h * Fb[c];
+  }
+  cons_vjp<DIM>(Up, Ub, gm1_inv, Upb);
+  cons_vjp<DIM>(Um, Umb_c, gm1_inv, Umb);
+  const double lam_b = 0.5 * h_b;
+  // lam = max(am, ap) + Jf max(cm, cp); d|x| = sign(x) (0 at 0)
+  if (am >= ap) {
+    const double sg = vmn > 0.0 ? 1.0 : (vmn < 0.0 ? -1.0 : 0.0);
+    for (int i = 0; i < DIM; ++i) Umb.v[i] += lam_b * sg * nJ[i];
+  } else {
+    const double sg = vpn > 0.0 ? 1.0 : (vpn < 0.0 ? -1.0 : 0.0);
+    for (int i = 0; i < DIM; ++i) Upb.v[i] += lam_b * sg * nJ[i];
+  }
+  // c = sqrt(gamma p/rho): dc/dp = c/(2p), dc/drho = -c/(2 rho)
+  if (cm >= cp) {
+    Umb.p += 0.5 * lam_b * Jf * cm * frcp(Um.p);
+    Umb.rho -= 0.5 * lam_b * Jf * cm * frcp(Um.rho);
+  } else {
+    Upb.p += 0.5 * lam_b * Jf * cp * frcp(Up.p);
+    Upb.rho -= 0.5 * lam_b * Jf * cp * frcp(Up.rho);
+  }
+}
+
+}  // namespace esd

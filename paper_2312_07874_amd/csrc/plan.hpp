@@ -8,11 +8,9 @@
 #include <vector>
 
 #include "host_setup.hpp"
+#include "physics.hpp"
 
 namespace esd {
-
-constexpr int FLUX_RANOCHA = 0;
-constexpr int FLUX_CHANDRASHEKAR = 1;
 
 // Device pointers to the per-degree reference tables (all FP64, see RefTables).
 struct DevTables {
@@ -50,8 +48,9 @@ struct Scheme {
 inline int ngv(int dim) { return dim == 2 ? 8 : 17; }
 
 struct Workspace {
-  double* wt;   // [ne][NC][NP]  projected entropy variables (modal)
-  double* wf;   // [ne][NC][NFQ] projected entropy variables at facet nodes
+  double* wt;     // [ne][NC][NP]  projected entropy variables (modal)
+  double* wf;     // [ne][NC][NFQ] projected entropy variables at facet nodes
+  double* xbar;   // [ne][NC][NFQ] VJP only: cotangent of the neighbour's facet value seen at each own facet node
 };
 
 }  // namespace esd
@@ -73,6 +72,9 @@ struct esd_plan {
   int* d_flag = nullptr;
   size_t ws_bytes = 0;
   size_t rk_ws_bytes = 0;
+  size_t vjp_ws_bytes = 0;
+  size_t rk_vjp_ws_bytes = 0;
+  bool conn_involutive = false;   // facet permutation pairs nodes both ways (needed by the VJP gather)
   // measurement: events bracketing each K1 / K2 launch (mutable: recorded by const calls)
   bool timing = false;
   mutable std::vector<hipEvent_t> ev;       // triples: before K1, between, after K2
@@ -87,7 +89,12 @@ int launch_project(const esd_plan* P, const double* u_nodal, double* u, hipStrea
 int launch_axpy(double* y, const double* x, double a, const double* z, int64_t n, hipStream_t s);
 int launch_rk_stage(double* acc, double* U, const double* u, const double* k, double ca, double cu,
                     int first, int64_t n, hipStream_t s);
+int launch_entropy_projection(const esd_plan* P, const double* u, Workspace ws, hipStream_t s);
+// adjoint.hip
 int launch_vjp(const esd_plan* P, const double* u, const double* vbar, double* grad, Workspace ws,
                hipStream_t s);
+int launch_adj_stage(double* acc, double* kb, const double* ubar, const double* G, double cu, double cg, int first,
+                     int64_t n, hipStream_t s);
+int launch_scale(double* y, const double* x, double a, int64_t n, hipStream_t s);
 bool degree_supported(int dim, int p);
 }  // namespace esd

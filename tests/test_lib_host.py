@@ -91,3 +91,26 @@ def test_plan_info_counts():
     assert i.flux_pairs_paper == 4 * 5 ** 4 * mesh.n_elements
     assert i.flux_pairs_distinct == 5 ** 3 * (2.5 * 4 + 4) * mesh.n_elements
     assert i.n_dof == mesh.n_elements * 5 * 35
+
+
+def test_workspace_sizes_and_host_only_rejection():
+    """Workspace sizes follow the documented layout; compute entry points refuse
+    a host-only plan with ESD_EINVAL before touching any device."""
+    esd = _lib()
+    mesh = wl.split_box_mesh(3, 3, 2 * math.pi)
+    plan = esd.Plan(3, 3, mesh.elem_vertex_ids, mesh.elem_vertex_coords, host_only=True)
+    i = plan.info
+    a256 = lambda n: (n + 255) // 256 * 256
+    ndof_b = a256(i.n_dof * 8)
+    fac_b = a256(i.n_elements * i.n_vars * i.n_facets * i.n_facet_nodes * 8)
+    assert i.workspace_bytes == ndof_b + fac_b
+    assert i.rk4_workspace_bytes == i.workspace_bytes + 3 * ndof_b
+    assert i.vjp_workspace_bytes == i.workspace_bytes + fac_b
+    assert i.rk4_vjp_workspace_bytes == i.vjp_workspace_bytes + 3 * ndof_b
+    L = esd._lib
+    fake = 256
+    assert L.esd_residual(plan._h, fake, 2 * fake, 3 * fake, None) == -1
+    assert L.esd_residual_vjp(plan._h, fake, 2 * fake, 3 * fake, 4 * fake, None) == -1
+    assert L.esd_rk4(plan._h, fake, 1e-3, 1, 2 * fake, None, None) == -1
+    assert L.esd_rk4_vjp(plan._h, fake, 1e-3, 1, 2 * fake, 3 * fake, None) == -1
+    assert b"host-only" in L.esd_last_error()

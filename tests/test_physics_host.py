@@ -1,0 +1,184 @@
+"""The library's physics header, built for the host, against the oracle.
+
+tests/physics_host.cpp compiles paper_2312_07874_amd/csrc/physics.hpp (the
+source the kernels include) with g++.  Its two-point fluxes, interface flux,
+entropy-variable maps and their hand-written vector-Jacobian products are
+compared with the oracle's formulas (Sec. 7.1-7.2) and with reverse-mode
+autograd through them, on random admissible states, both branches of the
+logarithmic mean, and both flux choices."""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import physics as PH
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+GAMMA = 1.4
+dptr = ctypes.POINTER(ctypes.c_double)
+
+
+@pytest.fixture(scope="module")
+def lib(tmp_path_factory):
+    out = tmp_path_factory.mktemp("ph") / "libphysics_host.so"
+    subprocess.run(["g++", "-O2", "-std=c++17", "-shared", "-fPIC",
+                    "-I", os.path.join(ROOT, "paper_2312_07874_amd", "csrc"),
+                    os.path.join(ROOT, "tests", "physics_host.cpp"), "-o", str(out)], check=True)
+    L = ctypes.CDLL(str(out))
+    L.ph_flux.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64, dptr, dptr, dptr, dptr, ctypes.c_double,
+                          ctypes.c_int, ctypes.c_int, dptr]
+    L.ph_flux_vjp.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64, dptr, dptr, dptr, dptr, ctypes.c_double,
+                              ctypes.c_int, ctypes.c_int, dptr, dptr, dptr]
+    L.ph_entropy_vars.argtypes = [ctypes.c_int, ctypes.c_int64, dptr, ctypes.c_double, dptr]
+    L.ph_entropy_vars_vjp.argtypes = [ctypes.c_int, ctypes.c_int64, dptr, dptr, ctypes.c_double, dptr]
+    L.ph_log_means.argtypes = [ctypes.c_int64, dptr, dptr, dptr, dptr, dptr, dptr]
+    return L
+
+
+def P(a: np.ndarray):
+    return a.ctypes.data_as(dptr)
+
+
+def states(dim, m, seed, near=False):
+    """Random admissible conservative states; with near=True the second state
+    differs by a relative 1e-4..1e-3 (series branch of the log means)."""
+    rng = np.random.default_rng(seed)
+    rho = rng.uniform(0.4, 2.5, m)
+    v = rng.uniform(-1.2, 1.2, (m, dim))
+    p = rng.uniform(0.3, 3.0, m)
+    if near:
+        eps = rng.uniform(1e-4, 1e-3, m) * rng.choice([-1.0, 1.0], m)
+        rho2, p2 = rho * (1 + eps), p * (1 - 0.7 * eps)
+        v2 = v + 1e-3 * rng.standard_normal((m, dim))
+    else:
+        rho2 = rng.uniform(0.4, 2.5, m)
+        v2 = rng.uniform(-1.2, 1.2, (m, dim))
+        p2 = rng.uniform(0.3, 3.0, m)
+
+    def cons(r, vv, pp):
+        E = pp / (GAMMA - 1) + 0.5 * r * (vv * vv).sum(1)
+        return np.concatenate([r[:, None], r[:, None] * vv, E[:, None]], 1)
+
+    return cons(rho, v, p), cons(rho2, v2, p2)
+
+
+def wvars(u):
+    return np.ascontiguousarray(PH.entropy_vars(torch.tensor(u), GAMMA).numpy())
+
+
+def normals(dim, m, seed):
+    rng = np.random.default_rng(seed + 100)
+    n = rng.standard_normal((m, dim))
+    Jf = rng.uniform(0.3, 2.0, m)
+    return n, Jf
+
+
+CASES = [(d, f, near) for d in (2, 3) for f in (0, 1) for near in (False, True)]
+
+
+@pytest.mark.parametrize("dim,flux,near", CASES)
+def test_ec_flux_and_vjp(lib, dim, flux, near):
+    m = 400
+    ua, ub = states(dim, m, 7 + dim + 2 * flux, near)
+    wa, wb = wvars(ua), wvars(ub)
+    n, Jf = normals(dim, m, 3)
+    nc = dim + 2
+    F = np.zeros((m, nc))
+    lib.ph_flux(dim, flux, m, P(wa), P(wb), P(n), P(Jf), GAMMA, 0, 0, P(F))
+    ta = torch.tensor(wa, requires_grad=True)
+    tb = torch.tensor(wb, requires_grad=True)
+    Fo = PH.EC_FLUXES[flux](PH.cons_from_entropy(ta, GAMMA), PH.cons_from_entropy(tb, GAMMA), torch.tensor(n), GAMMA)
+    scale = np.abs(Fo.detach().numpy()).max(0)
+    assert np.all(np.abs(F - Fo.detach().numpy()).max(0) <= 1e-13 * scale)
+    Fb = np.random.default_rng(5).standard_normal((m, nc))
+    (Fo * torch.tensor(Fb)).sum().backward()
+    ga, gb = np.zeros((m, nc)), np.zeros((m, nc))
+    lib.ph_flux_vjp(dim, flux, m, P(wa), P(wb), P(n), P(Jf), GAMMA, 0, 0, P(Fb), P(ga), P(gb))
+    for mine, ref in ((ga, ta.grad.numpy()), (gb, tb.grad.numpy())):
+        err = np.abs(mine - ref).max(1)
+        mag = np.abs(ref).max(1)
+        assert np.all(err <= 1e-10 * np.maximum(mag, 1.0)), float((err / np.maximum(mag, 1.0)).max())
+
+
+@pytest.mark.parametrize("dim,flux,diss", [(d, f, s) for d in (2, 3) for f in (0, 1) for s in (0, 1)])
+def test_interface_flux_and_vjp(lib, dim, flux, diss):
+    """J_f f*(U-, U+, n) with the Jacobian-weighted normal nJ = J_f n."""
+    m = 400
+    ua, ub = states(dim, m, 21 + dim + flux)
+    wa, wb = wvars(ua), wvars(ub)
+    n, Jf = normals(dim, m, 9)
+    n = n / np.linalg.norm(n, axis=1, keepdims=True)
+    nJ = np.ascontiguousarray(n * Jf[:, None])
+    nc = dim + 2
+    F = np.zeros((m, nc))
+    lib.ph_flux(dim, flux, m, P(wa), P(wb), P(nJ), P(Jf), GAMMA, diss, 1, P(F))
+    ta = torch.tensor(wa, requires_grad=True)
+    tb = torch.tensor(wb, requires_grad=True)
+    Fo = torch.tensor(Jf)[:, None] * PH.interface_flux(PH.cons_from_entropy(ta, GAMMA), PH.cons_from_entropy(tb, GAMMA),
+                                                        torch.tensor(n), GAMMA, flux, diss)
+    scale = np.abs(Fo.detach().numpy()).max(0)
+    assert np.all(np.abs(F - Fo.detach().numpy()).max(0) <= 1e-13 * scale)
+    Fb = np.random.default_rng(6).standard_normal((m, nc))
+    (Fo * torch.tensor(Fb)).sum().backward()
+    ga, gb = np.zeros((m, nc)), np.zeros((m, nc))
+    lib.ph_flux_vjp(dim, flux, m, P(wa), P(wb), P(nJ), P(Jf), GAMMA, diss, 1, P(Fb), P(ga), P(gb))
+    for mine, ref in ((ga, ta.grad.numpy()), (gb, tb.grad.numpy())):
+        err = np.abs(mine - ref).max(1)
+        mag = np.abs(ref).max(1)
+        assert np.all(err <= 1e-10 * np.maximum(mag, 1.0)), float((err / np.maximum(mag, 1.0)).max())
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_entropy_vars_and_vjp(lib, dim):
+    m = 500
+    u, _ = states(dim, m, 40 + dim)
+    nc = dim + 2
+    w = np.zeros((m, nc))
+    lib.ph_entropy_vars(dim, m, P(u), GAMMA, P(w))
+    tu = torch.tensor(u, requires_grad=True)
+    wo = PH.entropy_vars(tu, GAMMA)
+    assert np.abs(w - wo.detach().numpy()).max() <= 1e-13 * np.abs(w).max()
+    wb = np.random.default_rng(8).standard_normal((m, nc))
+    (wo * torch.tensor(wb)).sum().backward()
+    ub = np.zeros((m, nc))
+    lib.ph_entropy_vars_vjp(dim, m, P(u), P(wb), GAMMA, P(ub))
+    ref = tu.grad.numpy()
+    assert np.abs(ub - ref).max() <= 1e-11 * np.abs(ref).max()
+
+
+def test_log_mean_branches_and_gradients(lib):
+    """Both branches of the log means, their values against the exact
+    (a+ - a-)/(ln a+ - ln a-) in extended precision, and their gradients against
+    the oracle's autograd; arguments straddle the series threshold f^2 = 1e-4."""
+    rng = np.random.default_rng(12)
+    a = rng.uniform(0.2, 3.0, 600)
+    f = np.concatenate([rng.uniform(1e-9, 9.9e-3, 300), rng.uniform(1.01e-2, 0.8, 300)])
+    f *= rng.choice([-1.0, 1.0], 600)
+    b = a * (1 + f) / (1 - f)
+    m = a.size
+    L, I = np.zeros(m), np.zeros(m)
+    dL, dI = np.zeros(2 * m), np.zeros(2 * m)
+    lib.ph_log_means(m, P(a), P(b), P(L), P(I), P(dL), P(dI))
+    al, bl = a.astype(np.longdouble), b.astype(np.longdouble)
+    exact = (bl - al) / (np.log(bl) - np.log(al))
+    # the log branch inherits the rounding of ln a+ - ln a-, relative
+    # eps (|ln a-| + |ln a+|) / |ln a+ - ln a-|; the series branch is a few ulp
+    la, lb = np.abs(np.log(a)), np.abs(np.log(b))
+    cond = np.where(f * f < 1e-4, 0.0, (la + lb) / np.abs(np.log(b) - np.log(a)))
+    bound = 2.0 ** -52 * (4.0 + 2.0 * cond)
+    assert np.all(np.abs(L - exact) <= bound * np.abs(exact))
+    assert np.all(np.abs(I - 1 / exact) <= bound * np.abs(1 / exact))
+    ta = torch.tensor(a, requires_grad=True)
+    tb = torch.tensor(b, requires_grad=True)
+    ga = torch.autograd.grad(PH.log_mean(ta, tb).sum(), (ta, tb))
+    gi = torch.autograd.grad(PH.inv_log_mean(ta, tb).sum(), (ta, tb))
+    mine = dL.reshape(m, 2)
+    assert np.abs(mine[:, 0] - ga[0].numpy()).max() <= 1e-9
+    assert np.abs(mine[:, 1] - ga[1].numpy()).max() <= 1e-9
+    mine = dI.reshape(m, 2)
+    scale = np.abs(gi[0].numpy()).max()
+    assert np.abs(mine[:, 0] - gi[0].numpy()).max() <= 1e-9 * scale
+    assert np.abs(mine[:, 1] - gi[1].numpy()).max() <= 1e-9 * scale
