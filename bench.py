@@ -93,6 +93,7 @@ def run_gpu(name: str, steps: int, warmup: int):
     roof["algorithmic_flops_per_launch"] = fl
     roof["algorithmic_bytes_per_launch"] = by
     roof["avg_launch_ms"] = k2_avg_s * 1e3
+    vjp = time_vjp(plan, u)
     return {
         "workload": name,
         "elements": info.n_elements,
@@ -107,7 +108,35 @@ def run_gpu(name: str, steps: int, warmup: int):
         "flux_pairs_distinct_per_s": n_res * info.flux_pairs_distinct / elapsed,
         "roofline": roof,
         "k1_flop_rate_tflops": pm.k1_flops(d, p) * info.n_elements / k1_avg_s / 1e12,
+        "vjp": vjp,
     }
+
+
+def time_vjp(plan, u, reps: int = 5):
+    """Cost of one residual VJP (forward projection + the two adjoint kernels)
+    against one residual evaluation, both timed with events on the stream the
+    library launches on (torch's current stream)."""
+    import torch
+
+    g = torch.Generator(device="cuda").manual_seed(0)
+    vbar = torch.randn(tuple(u.shape), generator=g, dtype=torch.float64, device="cuda")
+    out = torch.empty_like(u)
+    plan.vjp(u, vbar, out)
+    plan.residual(u, out)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev[0].record()
+    for _ in range(reps):
+        plan.residual(u, out)
+    ev[1].record()
+    ev[2].record()
+    for _ in range(reps):
+        plan.vjp(u, vbar, out)
+    ev[3].record()
+    torch.cuda.synchronize()
+    plan.sync_status()
+    f = ev[0].elapsed_time(ev[1]) / reps
+    b = ev[2].elapsed_time(ev[3]) / reps
+    return {"residual_ms": f, "vjp_ms": b, "vjp_over_forward": b / f}
 
 
 def cpu_baseline(name: str, budget_s: float):
@@ -180,6 +209,8 @@ def main():
         "flux_pairs_distinct_per_s": main_res["flux_pairs_distinct_per_s"],
         "ms_per_residual_k1_k2": main_res["ms_per_residual_k1_k2"],
         "roofline": main_res["roofline"],
+        "vjp_over_forward": main_res["vjp"]["vjp_over_forward"],
+        "vjp": main_res["vjp"],
         "cpu_baseline": cpu,
         "extra": extra,
     }

@@ -18,6 +18,8 @@ States are tensors [..., d+2]; directions n are [..., d].
 """
 from __future__ import annotations
 
+import contextlib
+
 import torch
 
 LOG_SERIES_THRESHOLD = 1.0e-4
@@ -160,6 +162,36 @@ def chandrashekar_flux(um: torch.Tensor, up: torch.Tensor, n: torch.Tensor, gamm
 EC_FLUXES = {0: ranocha_flux, 1: chandrashekar_flux}
 
 
+# Reverse-mode derivative of max(a-, a+) at (near) ties.  max is not
+# differentiable where its arguments agree; by default the derivative follows
+# the branch the value takes (the interior side on exact ties).  Inside
+# tie_derivative(side, tol) the derivative is taken from the chosen side
+# ("-" interior, "+" exterior) wherever |a- - a+| <= tol max(|a-|, |a+|); the
+# value is never changed.  Used to bound the spread of valid one-sided
+# gradients when states tie to within rounding.
+_TIE = {"side": None, "tol": 1e-12}
+
+
+@contextlib.contextmanager
+def tie_derivative(side: str, tol: float = 1e-12):
+    assert side in ("-", "+")
+    old = dict(_TIE)
+    _TIE.update(side=side, tol=tol)
+    try:
+        yield
+    finally:
+        _TIE.update(old)
+
+
+def _max(a, b):
+    val = torch.where(a >= b, a, b)
+    if _TIE["side"] is None:
+        return val
+    near = (a - b).abs() <= _TIE["tol"] * torch.maximum(a.abs(), b.abs())
+    src = torch.where(near, a if _TIE["side"] == "-" else b, val)
+    return val.detach() + (src - src.detach())
+
+
 def davis_speed(um, up, n, gamma):
     """lambda of eq. (wave_speed); ties take the interior (-) branch."""
     rm, vm, pm = prim(um, gamma)
@@ -168,7 +200,7 @@ def davis_speed(um, up, n, gamma):
     b = (vp * n).sum(-1).abs()
     cm = torch.sqrt(gamma * pm / rm)
     cp = torch.sqrt(gamma * pp / rp)
-    return torch.where(a >= b, a, b) + torch.where(cm >= cp, cm, cp)
+    return _max(a, b) + _max(cm, cp)
 
 
 def interface_flux(um, up, n, gamma, ecflux: int, dissipation: int):

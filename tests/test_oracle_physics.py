@@ -5,6 +5,8 @@ the log mean against 50-digit arithmetic across its series threshold, and the
 defining properties of the EC two-point fluxes (consistency, symmetry, Tadmor's
 condition) and of the interface flux (conservation, consistency, entropy
 stability)."""
+import contextlib
+
 import mpmath
 import numpy as np
 import pytest
@@ -107,3 +109,46 @@ def test_interface_flux_properties(diss):
         assert bool((lhs <= rhs + 1e-12).all())
     else:
         np.testing.assert_allclose(lhs.numpy(), rhs.numpy(), atol=1e-12)
+
+
+def test_tie_derivative_changes_only_the_derivative():
+    """At equal sound speeds the wave speed max(c-, c+) is not differentiable:
+    the one-sided derivatives differ by J (grad c+ - grad c-) x [u].  Under
+    tie_derivative the value is bit-identical and the gradient moves entirely
+    to the chosen side; away from ties nothing changes."""
+    g = 1.4
+    # same p/rho (same c), different velocity and density
+    f64 = dict(dtype=torch.float64)
+    um = torch.tensor([[1.0, 0.3, -0.2, 1.0 / 0.4 + 0.5 * 1.0 * (0.3 ** 2 + 0.2 ** 2)]], **f64)
+    rp, vp = 2.0, torch.tensor([-0.1, 0.4], **f64)
+    pp = 2.0   # p/rho = 1 on both sides
+    up = torch.cat([torch.tensor([rp], **f64), rp * vp,
+                    torch.tensor([pp / 0.4 + 0.5 * rp * float((vp * vp).sum())], **f64)])[None]
+    n = torch.tensor([[0.6, 0.8]], dtype=torch.float64)
+    vals, grads = [], []
+    for side in (None, "-", "+"):
+        a = um.clone().requires_grad_(True)
+        b = up.clone().requires_grad_(True)
+        ctx = contextlib.nullcontext() if side is None else ph.tie_derivative(side)
+        with ctx:
+            lam = ph.davis_speed(a, b, n, g)
+        lam.sum().backward()
+        vals.append(lam.detach())
+        grads.append((a.grad.clone(), b.grad.clone()))
+    assert torch.equal(vals[0], vals[1]) and torch.equal(vals[0], vals[2])
+    # default and "-" take the interior side: d lambda / d u+ has no sound-speed part
+    assert torch.allclose(grads[0][0], grads[1][0]) and torch.allclose(grads[0][1], grads[1][1])
+    dc_p = grads[2][1] - grads[1][1]
+    dc_m = grads[1][0] - grads[2][0]
+    assert float(dc_p.abs().max()) > 0.1 and float(dc_m.abs().max()) > 0.1
+    # away from a tie the context manager changes nothing
+    up2 = up.clone()
+    up2[0, 3] += 1.0
+    res = []
+    for side in (None, "+"):
+        b = up2.clone().requires_grad_(True)
+        ctx = contextlib.nullcontext() if side is None else ph.tie_derivative(side)
+        with ctx:
+            ph.davis_speed(um, b, n, g).sum().backward()
+        res.append(b.grad.clone())
+    assert torch.equal(res[0], res[1])
