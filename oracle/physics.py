@@ -162,21 +162,22 @@ def chandrashekar_flux(um: torch.Tensor, up: torch.Tensor, n: torch.Tensor, gamm
 EC_FLUXES = {0: ranocha_flux, 1: chandrashekar_flux}
 
 
-# Reverse-mode derivative of max(a-, a+) at (near) ties.  max is not
-# differentiable where its arguments agree; by default the derivative follows
-# the branch the value takes (the interior side on exact ties).  Inside
-# tie_derivative(side, tol) the derivative is taken from the chosen side
-# ("-" interior, "+" exterior) wherever |a- - a+| <= tol max(|a-|, |a+|); the
-# value is never changed.  Used to bound the spread of valid one-sided
-# gradients when states tie to within rounding.
-_TIE = {"side": None, "tol": 1e-12}
+# Reverse-mode derivative of max(a-, a+) at ties.  max is not differentiable
+# where its arguments agree, and a tie up to rounding makes the one-sided
+# choice depend on rounding.  Convention: where |a- - a+| <= TIE_REL max(|a-|,
+# |a+|) the derivative is the mean of the two one-sided derivatives (the value
+# is max either way).  Inside tie_derivative(side) the derivative at such
+# near-ties is instead taken from one side ("-" interior, "+" exterior), to
+# measure the spread of the valid one-sided derivatives.
+TIE_REL = 1.0e-10
+_TIE = {"side": None}
 
 
 @contextlib.contextmanager
-def tie_derivative(side: str, tol: float = 1e-12):
+def tie_derivative(side: str):
     assert side in ("-", "+")
     old = dict(_TIE)
-    _TIE.update(side=side, tol=tol)
+    _TIE.update(side=side)
     try:
         yield
     finally:
@@ -185,10 +186,10 @@ def tie_derivative(side: str, tol: float = 1e-12):
 
 def _max(a, b):
     val = torch.where(a >= b, a, b)
-    if _TIE["side"] is None:
-        return val
-    near = (a - b).abs() <= _TIE["tol"] * torch.maximum(a.abs(), b.abs())
-    src = torch.where(near, a if _TIE["side"] == "-" else b, val)
+    near = (a - b).abs() <= TIE_REL * torch.maximum(a.abs(), b.abs())
+    side = _TIE["side"]
+    tie = 0.5 * (a + b) if side is None else (a if side == "-" else b)
+    src = torch.where(near, tie, val)
     return val.detach() + (src - src.detach())
 
 

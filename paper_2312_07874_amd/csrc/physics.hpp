@@ -293,6 +293,20 @@ ESD_HD void ec_flux_vjp(const Node<DIM>& A, const Node<DIM>& B, const double* n,
 }
 
 // ---------------------------------------------------------------- interface flux
+constexpr double TIE_REL = 1.0e-10;
+
+// weights of the one-sided derivatives of max(a, b), a, b >= 0: the branch the
+// value takes (a on exact ties), or 1/2 each where |a - b| <= TIE_REL max(a, b)
+ESD_HD void tie_weights(double a, double b, double& wa, double& wb) {
+  const double mx = a >= b ? a : b;
+  if (fabs(a - b) <= TIE_REL * mx) {
+    wa = wb = 0.5;
+  } else {
+    wa = a > b ? 1.0 : 0.0;
+    wb = 1.0 - wa;
+  }
+}
+
 // J_f f*(U-, U+, n) with nJ = J_f n:  f#(U-, U+, nJ) - (J_f lambda)/2 (U+ - U-),
 // J_f lambda = max(|v-.nJ|, |v+.nJ|) + J_f max(c-, c+) (ties take the interior branch)
 template <int DIM, int FLUX>
@@ -365,22 +379,24 @@ ESD_HD void interface_flux_vjp(const Node<DIM>& Um, const Node<DIM>& Up, const d
   cons_vjp<DIM>(Up, Ub, gm1_inv, Upb);
   cons_vjp<DIM>(Um, Umb_c, gm1_inv, Umb);
   const double lam_b = 0.5 * h_b;
-  // lam = max(am, ap) + Jf max(cm, cp); d|x| = sign(x) (0 at 0)
-  if (am >= ap) {
-    const double sg = vmn > 0.0 ? 1.0 : (vmn < 0.0 ? -1.0 : 0.0);
-    for (int i = 0; i < DIM; ++i) Umb.v[i] += lam_b * sg * nJ[i];
-  } else {
-    const double sg = vpn > 0.0 ? 1.0 : (vpn < 0.0 ? -1.0 : 0.0);
-    for (int i = 0; i < DIM; ++i) Upb.v[i] += lam_b * sg * nJ[i];
+  // lam = max(am, ap) + Jf max(cm, cp); d|x| = sign(x) (0 at 0).  max is not
+  // differentiable at a tie; where its arguments agree to TIE_REL relative
+  // (a tie up to rounding) the derivative is the mean of the two one-sided ones.
+  double wm, wp;
+  tie_weights(am, ap, wm, wp);
+  const double sgm = vmn > 0.0 ? 1.0 : (vmn < 0.0 ? -1.0 : 0.0);
+  const double sgp = vpn > 0.0 ? 1.0 : (vpn < 0.0 ? -1.0 : 0.0);
+  for (int i = 0; i < DIM; ++i) {
+    Umb.v[i] += lam_b * wm * sgm * nJ[i];
+    Upb.v[i] += lam_b * wp * sgp * nJ[i];
   }
   // c = sqrt(gamma p/rho): dc/dp = c/(2p), dc/drho = -c/(2 rho)
-  if (cm >= cp) {
-    Umb.p += 0.5 * lam_b * Jf * cm * frcp(Um.p);
-    Umb.rho -= 0.5 * lam_b * Jf * cm * frcp(Um.rho);
-  } else {
-    Upb.p += 0.5 * lam_b * Jf * cp * frcp(Up.p);
-    Upb.rho -= 0.5 * lam_b * Jf * cp * frcp(Up.rho);
-  }
+  tie_weights(cm, cp, wm, wp);
+  const double bm = 0.5 * lam_b * Jf * cm * wm, bp = 0.5 * lam_b * Jf * cp * wp;
+  Umb.p += bm * frcp(Um.p);
+  Umb.rho -= bm * frcp(Um.rho);
+  Upb.p += bp * frcp(Up.p);
+  Upb.rho -= bp * frcp(Up.rho);
 }
 
 }  // namespace esd

@@ -113,9 +113,10 @@ def test_interface_flux_properties(diss):
 
 def test_tie_derivative_changes_only_the_derivative():
     """At equal sound speeds the wave speed max(c-, c+) is not differentiable:
-    the one-sided derivatives differ by J (grad c+ - grad c-) x [u].  Under
-    tie_derivative the value is bit-identical and the gradient moves entirely
-    to the chosen side; away from ties nothing changes."""
+    the one-sided derivatives differ by J (grad c+ - grad c-) x [u].  The
+    default derivative there is the mean of the one-sided ones; under
+    tie_derivative it moves entirely to the chosen side; the value is
+    bit-identical in every mode, and away from ties nothing changes."""
     g = 1.4
     # same p/rho (same c), different velocity and density
     f64 = dict(dtype=torch.float64)
@@ -136,8 +137,9 @@ def test_tie_derivative_changes_only_the_derivative():
         vals.append(lam.detach())
         grads.append((a.grad.clone(), b.grad.clone()))
     assert torch.equal(vals[0], vals[1]) and torch.equal(vals[0], vals[2])
-    # default and "-" take the interior side: d lambda / d u+ has no sound-speed part
-    assert torch.allclose(grads[0][0], grads[1][0]) and torch.allclose(grads[0][1], grads[1][1])
+    # the default is the mean of the two one-sided derivatives
+    for k in (0, 1):
+        assert torch.allclose(grads[0][k], 0.5 * (grads[1][k] + grads[2][k]), rtol=0, atol=1e-15)
     dc_p = grads[2][1] - grads[1][1]
     dc_m = grads[1][0] - grads[2][0]
     assert float(dc_p.abs().max()) > 0.1 and float(dc_m.abs().max()) > 0.1

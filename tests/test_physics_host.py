@@ -182,3 +182,52 @@ def test_log_mean_branches_and_gradients(lib):
     scale = np.abs(gi[0].numpy()).max()
     assert np.abs(mine[:, 0] - gi[0].numpy()).max() <= 1e-9 * scale
     assert np.abs(mine[:, 1] - gi[1].numpy()).max() <= 1e-9 * scale
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_interface_vjp_tie_convention(lib, dim):
+    """Equal sound speeds on both sides (p/rho equal) and equal |v.n|: the
+    derivative of both maxima in the wave speed is the mean of the one-sided
+    derivatives, in the library as in the oracle."""
+    m = 200
+    rng = np.random.default_rng(77 + dim)
+    T = rng.uniform(0.5, 2.0, m)
+    rho_a, rho_b = rng.uniform(0.5, 2.0, m), rng.uniform(0.5, 2.0, m)
+    n = rng.standard_normal((m, dim))
+    n /= np.linalg.norm(n, axis=1, keepdims=True)
+    va = rng.uniform(-1, 1, (m, dim))
+    vb = rng.uniform(-1, 1, (m, dim))
+    # half of the points also tie in |v.n|: reflect v_b's normal part onto v_a's
+    half = np.arange(m) < m // 2
+    vna, vnb = (va * n).sum(1), (vb * n).sum(1)
+    vb[half] += ((np.sign(vnb) * np.abs(vna) - vnb)[:, None] * n)[half]
+
+    def cons(r, vv):
+        p = r * T
+        E = p / (GAMMA - 1) + 0.5 * r * (vv * vv).sum(1)
+        return np.concatenate([r[:, None], r[:, None] * vv, E[:, None]], 1)
+
+    wa, wb = wvars(cons(rho_a, va)), wvars(cons(rho_b, vb))
+    Jf = rng.uniform(0.5, 1.5, m)
+    nJ = np.ascontiguousarray(n * Jf[:, None])
+    nc = dim + 2
+    ta = torch.tensor(wa, requires_grad=True)
+    tb = torch.tensor(wb, requires_grad=True)
+    Fo = torch.tensor(Jf)[:, None] * PH.interface_flux(PH.cons_from_entropy(ta, GAMMA), PH.cons_from_entropy(tb, GAMMA),
+                                                        torch.tensor(n), GAMMA, 0, 1)
+    Fb = rng.standard_normal((m, nc))
+    (Fo * torch.tensor(Fb)).sum().backward()
+    ga, gb = np.zeros((m, nc)), np.zeros((m, nc))
+    lib.ph_flux_vjp(dim, 0, m, P(wa), P(wb), P(nJ), P(Jf), GAMMA, 1, 1, P(Fb), P(ga), P(gb))
+    for mine, ref in ((ga, ta.grad.numpy()), (gb, tb.grad.numpy())):
+        err = np.abs(mine - ref).max(1)
+        mag = np.abs(ref).max(1)
+        assert np.all(err <= 1e-10 * np.maximum(mag, 1.0)), float((err / np.maximum(mag, 1.0)).max())
+    # and the convention matters: forcing one side in the oracle moves the gradient
+    ta2 = torch.tensor(wa, requires_grad=True)
+    tb2 = torch.tensor(wb, requires_grad=True)
+    with PH.tie_derivative("-"):
+        Fo2 = torch.tensor(Jf)[:, None] * PH.interface_flux(PH.cons_from_entropy(ta2, GAMMA),
+                                                             PH.cons_from_entropy(tb2, GAMMA), torch.tensor(n), GAMMA, 0, 1)
+    (Fo2 * torch.tensor(Fb)).sum().backward()
+    assert float((ta2.grad - ta.grad).abs().max()) > 1e-3
