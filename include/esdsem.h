@@ -73,7 +73,9 @@ typedef void (*esd_warp_fn)(int64_t n, const double* x_in, double* x_out, void* 
 
 typedef struct {
   int32_t dim;                         /* 2 (triangles) or 3 (tetrahedra)          */
-  int32_t degree;                      /* p = q = p_g for every element (Sec. 7.3) */
+  int32_t degree;                      /* p = q = p_g for every element (Sec. 7.3); built:
+                                          1..10 (triangles and tetrahedra); the VJP
+                                          entry points: tetrahedra up to 8         */
   int64_t n_elements;
   const int64_t* elem_vertex_ids;      /* host [n_elements][dim+1] global ids; periodic
                                           images of a vertex share one id           */

@@ -26,6 +26,15 @@
 
 namespace esd {
 
+// The adjoint kernels hold more live state per thread than the forward ones:
+// their workgroups are capped at 256 threads so that the register file is
+// not split further (same elements per workgroup as the forward launch).
+template <int DIM, int P>
+struct VjpLaunch {
+  static constexpr int EPB = Launch<DIM, P>::EPB;
+  static constexpr int BS = Launch<DIM, P>::BS > 256 ? 256 : Launch<DIM, P>::BS;
+};
+
 // One volume adjoint task: node a of the line base + stride*k and the same
 // partners as the forward task; F_bar = r_bar_b - r_bar_a.
 template <int DIM, int P, int FLUX, int NA>
@@ -109,7 +118,7 @@ __device__ __forceinline__ void facet_task_vjp(const Node<DIM>& Vi, const double
 
 // ------------------------------------------------------------------ VK2: reverse of the right-hand side
 template <int DIM, int P, int FLUX>
-__global__ void __launch_bounds__((Launch<DIM, P>::BS))
+__global__ void __launch_bounds__((VjpLaunch<DIM, P>::BS))
 k_rhs_vjp(const double* __restrict__ wt, const double* __restrict__ wfb, const double* __restrict__ vbar,
           double* __restrict__ gpart, double* __restrict__ xbar, const double* __restrict__ gvol,
           const double* __restrict__ gfac, const int32_t* __restrict__ conn, DevTables T, Scheme S, int64_t ne,
@@ -117,6 +126,7 @@ k_rhs_vjp(const double* __restrict__ wt, const double* __restrict__ wfb, const d
   using Sh = Shape<DIM, P>;
   constexpr int EPB = Launch<DIM, P>::EPB;
   constexpr int Q = Sh::Q, NC = Sh::NC, NQ = Sh::NQ, NP = Sh::NP, NQF = Sh::NQF, NFQ = Sh::NFQ, NGV = Sh::NGV;
+  constexpr int LPF = Sh::LPF;
   __shared__ double sN[EPB * Sh::SCR];      // transform scratch; node data [el][8][NQ]
   __shared__ double sR[EPB * NC * NQ];      // r_bar
   __shared__ double sX[EPB * NC * NQ];      // modal / nodal staging; x_bar, then w_bar at volume nodes
@@ -179,7 +189,12 @@ k_rhs_vjp(const double* __restrict__ wt, const double* __restrict__ wfb, const d
     constexpr int TPE = DIM * NQ;
     for (int task = tid; task < nel * TPE; task += nth) {
       const int el = task / TPE, lt = task % TPE;
-      const int fam = lt / NQ, rem = lt % NQ, L = rem / Q, a = rem % Q;
+      const int fam = lt / NQ, rem = lt % NQ;
+      // lanes run along a line (a fastest) for the families of stride 1 and Q,
+      // across lines (L fastest) for the family of stride Q^2: consecutive
+      // lanes then address distinct LDS banks
+      const bool across = DIM == 3 && fam == 2;
+      const int L = across ? rem % LPF : rem / Q, a = across ? rem / LPF : rem % Q;
       const double* sNe = sN + el * Sh::SCR;
       const double* sRe = sR + el * NC * NQ;
       double* sXe = sX + el * NC * NQ;
@@ -354,7 +369,7 @@ k_rhs_vjp(const double* __restrict__ wt, const double* __restrict__ wfb, const d
 // g holds the partial w~_bar on entry and u~_bar on exit (same element, read
 // before it is written).
 template <int DIM, int P>
-__global__ void __launch_bounds__((Launch<DIM, P>::BS))
+__global__ void __launch_bounds__((VjpLaunch<DIM, P>::BS))
 k_projection_vjp(const double* __restrict__ u, double* g, const double* __restrict__ xbar,
                  const double* __restrict__ gvol, const int32_t* __restrict__ conn, DevTables T, Scheme S,
                  int64_t ne) {
@@ -442,7 +457,7 @@ __global__ void k_scale(double* __restrict__ y, const double* __restrict__ x, do
 template <int DIM, int P>
 static int run_vjp(const esd_plan* pl, const double* u, const double* vbar, double* grad, Workspace ws,
                    hipStream_t s) {
-  using L = Launch<DIM, P>;
+  using L = VjpLaunch<DIM, P>;
   const int64_t nb = (pl->ne + L::EPB - 1) / L::EPB;
   int rc = launch_entropy_projection(pl, u, ws, s);
   if (rc != 0) return rc;
@@ -461,7 +476,7 @@ int launch_vjp(const esd_plan* pl, const double* u, const double* vbar, double* 
 #define X(D, PP) \
   if (pl->dim == D && pl->p == PP) return run_vjp<D, PP>(pl, u, vbar, grad, ws, s);
   ESD_TRI_DEGREES(X)
-  ESD_TET_DEGREES(X)
+  ESD_TET_VJP_DEGREES(X)
 #undef X
   return -1;
 }

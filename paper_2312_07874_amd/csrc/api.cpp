@@ -124,7 +124,9 @@ esd_status esd_plan_create(const esd_mesh_desc* mesh, const esd_scheme_desc* sch
     const esd::RefTables& R = P->ref;
     const size_t ndof = (size_t)P->ne * P->nc * R.NP;
     const size_t fbytes = align256((size_t)P->ne * P->nc * R.NFQ * sizeof(double));
-    P->ws_bytes = align256(ndof * sizeof(double)) + fbytes;
+    P->frec_bytes = esd::needs_facet_records(P->dim, P->p)
+                        ? align256((size_t)P->ne * 8 * R.NFQ * sizeof(double)) : 0;
+    P->ws_bytes = align256(ndof * sizeof(double)) + fbytes + P->frec_bytes;
     P->rk_ws_bytes = P->ws_bytes + 3 * align256(ndof * sizeof(double));
     P->vjp_ws_bytes = P->ws_bytes + fbytes;
     P->rk_vjp_ws_bytes = P->vjp_ws_bytes + 3 * align256(ndof * sizeof(double));
@@ -330,6 +332,7 @@ static esd::Workspace split_ws(const esd_plan* P, void* ws) {
   esd::Workspace w;
   w.wt = (double*)ws;
   w.wf = (double*)((char*)ws + align256(ndof * sizeof(double)));
+  w.frec = P->frec_bytes ? (double*)((char*)ws + P->ws_bytes - P->frec_bytes) : nullptr;
   w.xbar = (double*)((char*)ws + P->ws_bytes);   // inside the workspace only for the VJP entry points
   return w;
 }
@@ -388,6 +391,7 @@ esd_status esd_residual_vjp(const esd_plan* P, const double* u_dev, const double
     return fail(ESD_EINVAL, "grad overlaps u or vbar");
   if (((uintptr_t)ws_dev) % 256 != 0) return fail(ESD_EINVAL, "workspace not 256-byte aligned");
   if (!P->conn_involutive) return fail(ESD_EUNSUPPORTED, "facet permutation is not an involution");
+  if (!esd::vjp_degree_supported(P->dim, P->p)) return fail(ESD_EUNSUPPORTED, "VJP not built for this degree");
   const int rc = esd::launch_vjp(P, u_dev, vbar_dev, grad_dev, split_ws(P, ws_dev), (hipStream_t)stream);
   if (rc < 0) return fail(ESD_EUNSUPPORTED, "degree not built");
   if (rc != 0) return fail(ESD_EHIP, std::string("VJP launch failed: ") + hipGetErrorString((hipError_t)rc));
@@ -402,6 +406,7 @@ esd_status esd_rk4_vjp(const esd_plan* P, const double* stage_ckpt_dev, double d
     return fail(ESD_EINVAL, "bad argument");
   if (((uintptr_t)ws_dev) % 256 != 0) return fail(ESD_EINVAL, "workspace not 256-byte aligned");
   if (!P->conn_involutive) return fail(ESD_EUNSUPPORTED, "facet permutation is not an involution");
+  if (!esd::vjp_degree_supported(P->dim, P->p)) return fail(ESD_EUNSUPPORTED, "VJP not built for this degree");
   hipStream_t s = (hipStream_t)stream;
   const int64_t n = P->ne * P->nc * P->ref.NP;
   const size_t nb = align256((size_t)n * sizeof(double));

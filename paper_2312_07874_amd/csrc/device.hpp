@@ -13,7 +13,9 @@ namespace esd {
 
 // degrees built into the library, per dimension
 #define ESD_TRI_DEGREES(X) X(2, 1) X(2, 2) X(2, 3) X(2, 4) X(2, 5) X(2, 6) X(2, 7) X(2, 8) X(2, 9) X(2, 10)
-#define ESD_TET_DEGREES(X) X(3, 1) X(3, 2) X(3, 3) X(3, 4) X(3, 5) X(3, 6) X(3, 7) X(3, 8)
+#define ESD_TET_DEGREES(X) X(3, 1) X(3, 2) X(3, 3) X(3, 4) X(3, 5) X(3, 6) X(3, 7) X(3, 8) X(3, 9) X(3, 10)
+// the adjoint kernels hold more state per element in LDS: tetrahedra up to p = 8
+#define ESD_TET_VJP_DEGREES(X) X(3, 1) X(3, 2) X(3, 3) X(3, 4) X(3, 5) X(3, 6) X(3, 7) X(3, 8)
 
 // ------------------------------------------------------------------ shapes
 template <int DIM, int P>
@@ -32,6 +34,9 @@ struct Shape {
   static constexpr int T1 = DIM == 2 ? NC * (P + 1) * Q : NC * NPAIR * Q;
   static constexpr int T2 = DIM == 2 ? 0 : NC * (P + 1) * Q * Q;
   static constexpr int SCR = (T1 + T2 > 8 * NQ) ? (T1 + T2) : 8 * NQ;   // per element
+  // the right-hand-side kernel keeps the own facet node records in LDS when
+  // node data, r, facet records and facet sums fit the 160 KB of a CU
+  static constexpr bool K2_FACET_LDS = 8 * (SCR + NC * NQ + 8 * NFQ + NC * NFQ) <= 160 * 1024;
 };
 
 template <int DIM, int P>
@@ -41,7 +46,9 @@ struct Launch<3, P> {
   // one element per workgroup; small workgroups keep several elements in
   // flight per CU, which hides the latency of the barrier-separated phases
   static constexpr int EPB = 1;
-  static constexpr int BS = P <= 3 ? 64 : (P == 4 ? 128 : (P <= 6 ? 192 : 256));
+  // measured on MI355X (K2 at p = 4..8): 128, 192, 256, 256, 512 threads
+  static constexpr int BS = P <= 3 ? 64 : (P == 4 ? 128 : (P == 5 ? 192 : (P <= 7 ? 256 : 512)));
+  static_assert(P <= 10, "tetrahedra up to p = 10");
 };
 template <int P>
 struct Launch<2, P> {

@@ -177,19 +177,26 @@ template <int DIM, int P, int FLUX>
 __global__ void __launch_bounds__((Launch<DIM, P>::BS))
 k_rhs(const double* __restrict__ wt, const double* __restrict__ wfb, double* __restrict__ dudt,
       const double* __restrict__ gvol, const double* __restrict__ gfac, const int32_t* __restrict__ conn,
-      DevTables T, Scheme S, int64_t ne, int* flag) {
+      DevTables T, Scheme S, int64_t ne, int* flag, double* frec) {
   using Sh = Shape<DIM, P>;
   constexpr int EPB = Launch<DIM, P>::EPB;
   constexpr int Q = Sh::Q, NC = Sh::NC, NQ = Sh::NQ, NP = Sh::NP, NQF = Sh::NQF, NFQ = Sh::NFQ, NGV = Sh::NGV;
   constexpr int LPF = Sh::LPF;
-  __shared__ double sM[EPB * NC * NP];
+  // own facet node records live in LDS when everything fits, else in this
+  // element's slice of the workspace (frec, [e][8][NFQ]; read through the caches)
+  constexpr bool FLDS = Sh::K2_FACET_LDS;
   __shared__ double sN[EPB * Sh::SCR];      // node data [el][8][NQ]; transform scratch
   __shared__ double sR[EPB * NC * NQ];      // w at nodes, then r
-  __shared__ double sF[EPB * 8 * NFQ];      // own facet node data; later R^T scratch
+  __shared__ double sF[FLDS ? EPB * 8 * NFQ : 1];   // own facet node records (LDS case)
   __shared__ double sT[EPB * NC * NFQ];     // C^T 1, then s = B J_f f* - C^T 1
+  static_assert(FLDS ? 8 * NFQ >= NC * NP : NFQ >= NP, "modal staging must fit the facet buffers");
+  // modal w~ before the facet data exist, du~/dt after they are dead
+  double* sM = FLDS ? sF : sT;
+  double* lift_scratch = FLDS ? sF : sN;
   const int64_t e0 = (int64_t)blockIdx.x * EPB;
   const int nel = (int)((ne - e0) < EPB ? (ne - e0) : EPB);
   const int nec = nel * NC;
+  double* fr = FLDS ? sF : frec + e0 * 8 * NFQ;
   const int tid = threadIdx.x, nth = blockDim.x;
   double* T1 = sN;
   double* T2 = sN + EPB * Sh::T1;
@@ -216,7 +223,7 @@ k_rhs(const double* __restrict__ wt, const double* __restrict__ wfb, double* __r
     for (int c = 0; c < NC; ++c) w[c] = wfb[((e0 + el) * NC + c) * NFQ + j];
     Node<DIM> nd;
     bad |= !from_entropy<DIM>(w, S.gamma, S.gm1_inv, nd);
-    store_node<DIM>(sF + el * 8 * NFQ, NFQ, j, nd);
+    store_node<DIM>(fr + el * 8 * NFQ, NFQ, j, nd);
   }
   for (int o = tid; o < nec * NFQ; o += nth) sT[o] = 0.0;
   if (bad) atomicOr(flag, 1);
@@ -234,7 +241,12 @@ k_rhs(const double* __restrict__ wt, const double* __restrict__ wfb, double* __r
     constexpr int TPE = DIM * NQ;           // volume tasks per element
     for (int task = tid; task < nel * TPE; task += nth) {
       const int el = task / TPE, lt = task % TPE;
-      const int fam = lt / NQ, rem = lt % NQ, L = rem / Q, a = rem % Q;
+      const int fam = lt / NQ, rem = lt % NQ;
+      // lanes run along a line (a fastest) for the families of stride 1 and Q,
+      // across lines (L fastest) for the family of stride Q^2: consecutive
+      // lanes then address distinct LDS banks
+      const bool across = DIM == 3 && fam == 2;
+      const int L = across ? rem % LPF : rem / Q, a = across ? rem / LPF : rem % Q;
       const double* sNe = sN + el * Sh::SCR;
       double* sRe = sR + el * NC * NQ;
       const double* g = gvol + (e0 + el) * NGV * NQ;
@@ -262,7 +274,7 @@ k_rhs(const double* __restrict__ wt, const double* __restrict__ wfb, double* __r
   for (int task = tid; task < nel * NQ; task += nth) {
     const int el = task / NQ, t = task % NQ;
     const double* sNe = sN + el * Sh::SCR;
-    const double* sFe = sF + el * 8 * NFQ;
+    const double* sFe = fr + el * 8 * NFQ;
     double* sTe = sT + el * NC * NFQ;
     const double* g = gvol + (e0 + el) * NGV * NQ;
     const double* gf = gfac + (e0 + el) * (DIM + 1) * NFQ;
@@ -329,7 +341,7 @@ k_rhs(const double* __restrict__ wt, const double* __restrict__ wfb, double* __r
   for (int o = tid; o < nel * NFQ; o += nth) {
     const int j = o % NFQ, le = o / NFQ;
     const int64_t e = e0 + le;
-    const Node<DIM> Um = load_node<DIM>(sF + le * 8 * NFQ, NFQ, j);
+    const Node<DIM> Um = load_node<DIM>(fr + le * 8 * NFQ, NFQ, j);
     const int32_t addr = conn[e * NFQ + j];
     double w[NC];
 #pragma unroll
@@ -353,7 +365,7 @@ k_rhs(const double* __restrict__ wt, const double* __restrict__ wfb, double* __r
   __syncthreads();
 
   // ---- r -= R^T s
-  facet_lift<DIM, P>(sT, sF, T, nec, [&](int o, double d) { sR[o] -= d; });
+  facet_lift<DIM, P>(sT, lift_scratch, T, nec, [&](int o, double d) { sR[o] -= d; });
   __syncthreads();
 
   // ---- du~/dt = V^T (w/J) V V^T r
@@ -408,10 +420,10 @@ static int run_residual(const esd_plan* pl, const double* u, double* dudt, Works
   if (pl->timing) timing_event(pl, s);
   if (pl->scheme.ecflux == FLUX_RANOCHA)
     hipLaunchKernelGGL((k_rhs<DIM, P, FLUX_RANOCHA>), dim3(nb), dim3(L::BS), 0, s, ws.wt, ws.wf, dudt, pl->d_gvol,
-                       pl->d_gfac, pl->d_conn, pl->tab, pl->scheme, pl->ne, pl->d_flag);
+                       pl->d_gfac, pl->d_conn, pl->tab, pl->scheme, pl->ne, pl->d_flag, ws.frec);
   else
     hipLaunchKernelGGL((k_rhs<DIM, P, FLUX_CHANDRASHEKAR>), dim3(nb), dim3(L::BS), 0, s, ws.wt, ws.wf, dudt,
-                       pl->d_gvol, pl->d_gfac, pl->d_conn, pl->tab, pl->scheme, pl->ne, pl->d_flag);
+                       pl->d_gvol, pl->d_gfac, pl->d_conn, pl->tab, pl->scheme, pl->ne, pl->d_flag, ws.frec);
   if (pl->timing) timing_event(pl, s);
   return (int)hipGetLastError();
 }
@@ -427,7 +439,22 @@ static int run_project(const esd_plan* pl, const double* un, double* u, hipStrea
 
 bool degree_supported(int dim, int p) {
   if (dim == 2) return p >= 1 && p <= 10;
+  if (dim == 3) return p >= 1 && p <= 10;
+  return false;
+}
+
+bool vjp_degree_supported(int dim, int p) {
+  if (dim == 2) return p >= 1 && p <= 10;
   if (dim == 3) return p >= 1 && p <= 8;
+  return false;
+}
+
+bool needs_facet_records(int dim, int p) {
+#define X(D, PP) \
+  if (dim == D && p == PP) return !Shape<D, PP>::K2_FACET_LDS;
+  ESD_TRI_DEGREES(X)
+  ESD_TET_DEGREES(X)
+#undef X
   return false;
 }
 

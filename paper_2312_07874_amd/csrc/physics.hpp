@@ -194,15 +194,38 @@ ESD_HD void inv_log_mean_grad(double a, double b, double la, double lb, double* 
   g[3] = id;
 }
 
+// Both logarithmic means of a flux pair, {rho}_ln and 1/{b}_ln, branch-free
+// with one reciprocal.  The series branch is chosen where d^2 < 1e-4 s^2
+// (f^2 < 1e-4); otherwise d / (ln a+ - ln a-) and its reciprocal.  With
+// L = ln-difference (or 1 on the series branch), D = difference of b (or 1),
+// x = L D and y = s_rho s_b, r = 1/(x y) yields 1/x = r y and 1/y = r x, hence
+// 1/L, 1/D, 1/s_rho, 1/s_b by one more product each.
+ESD_HD void log_means(double ra, double rb, double lra, double lrb, double ba, double bb, double lba, double lbb,
+                      double& rho_ln, double& ib_ln, double& inv_sb) {
+  const double dr = rb - ra, sr = ra + rb, db = bb - ba, sb = ba + bb;
+  const bool ser_r = dr * dr < LOG_SERIES_THRESHOLD * (sr * sr);
+  const bool ser_b = db * db < LOG_SERIES_THRESHOLD * (sb * sb);
+  const double Lr = ser_r ? 1.0 : (lrb - lra);
+  const double Db = ser_b ? 1.0 : db;
+  const double x = Lr * Db, y = sr * sb;
+  const double r = frcp(x * y);
+  const double ix = r * y, iy = r * x;
+  const double inv_sr = iy * sb;
+  inv_sb = iy * sr;
+  const double fr = dr * inv_sr, ur = fr * fr;
+  const double fb = db * inv_sb, ub = fb * fb;
+  const double ser_rho = 0.5 * sr * (1.0 - ur * (1.0 / 3.0 + ur * (4.0 / 45.0 + ur * (44.0 / 945.0))));
+  const double ser_ib = 2.0 * (1.0 + ub * (1.0 / 3.0 + ub * (1.0 / 5.0 + ub * (1.0 / 7.0)))) * inv_sb;
+  rho_ln = ser_r ? ser_rho : dr * (ix * Db);
+  ib_ln = ser_b ? ser_ib : (lbb - lba) * (ix * Lr);
+}
+
 // ---------------------------------------------------------------- EC two-point flux
 // directional flux f#(A, B, n) = sum_m n_m f#_m(A, B)
 template <int DIM, int FLUX>
 ESD_HD void ec_flux(const Node<DIM>& A, const Node<DIM>& B, const double* n, double gm1_inv, double* F) {
-  // one reciprocal serves both means: 1/(sr sb) -> 1/sr = sb/(sr sb), 1/sb = sr/(sr sb)
-  const double sr = A.rho + B.rho, sb = A.b + B.b;
-  const double rr = frcp(sr * sb);
-  const double rho_ln = log_mean(A.rho, B.rho, A.lnrho, B.lnrho, sb * rr);
-  const double ib_ln = inv_log_mean(A.b, B.b, A.lnb, B.lnb, sr * rr);   // 1 / {rho/p}_ln
+  double rho_ln, ib_ln, inv_sb;   // {rho}_ln, 1/{rho/p}_ln, 1/(b- + b+)
+  log_means(A.rho, B.rho, A.lnrho, B.lnrho, A.b, B.b, A.lnb, B.lnb, rho_ln, ib_ln, inv_sb);
   double vavg[DIM];
   double vn = 0.0, vab = 0.0, van = 0.0, vbn = 0.0;
   for (int i = 0; i < DIM; ++i) {
@@ -219,7 +242,7 @@ ESD_HD void ec_flux(const Node<DIM>& A, const Node<DIM>& B, const double* n, dou
     for (int i = 0; i < DIM; ++i) F[1 + i] = frho * vavg[i] + pavg * n[i];
     F[DIM + 1] = frho * (0.5 * vab + ib_ln * gm1_inv) + 0.5 * (A.p * vbn + B.p * van);
   } else {
-    const double phat = sr * sr * rr;   // {rho} / (2 {beta}) = sr/sb, beta = b/2
+    const double phat = (A.rho + B.rho) * inv_sb;   // {rho} / (2 {beta}) = sr/sb, beta = b/2
     for (int i = 0; i < DIM; ++i) F[1 + i] = frho * vavg[i] + phat * n[i];
     F[DIM + 1] = frho * (0.5 * vab + ib_ln * gm1_inv) + phat * vn;
   }

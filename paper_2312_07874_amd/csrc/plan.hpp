@@ -51,6 +51,8 @@ struct Workspace {
   double* wt;     // [ne][NC][NP]  projected entropy variables (modal)
   double* wf;     // [ne][NC][NFQ] projected entropy variables at facet nodes
   double* xbar;   // [ne][NC][NFQ] VJP only: cotangent of the neighbour's facet value seen at each own facet node
+  double* frec;   // [ne][8][NFQ] own facet node records, only for degrees whose right-hand side
+                  // does not fit them in LDS (else nullptr)
 };
 
 }  // namespace esd
@@ -71,6 +73,7 @@ struct esd_plan {
   double* d_xvol = nullptr;
   int* d_flag = nullptr;
   size_t ws_bytes = 0;
+  size_t frec_bytes = 0;          // tail of the residual workspace holding Workspace::frec
   size_t rk_ws_bytes = 0;
   size_t vjp_ws_bytes = 0;
   size_t rk_vjp_ws_bytes = 0;
@@ -97,4 +100,6 @@ int launch_adj_stage(double* acc, double* kb, const double* ubar, const double* 
                      int64_t n, hipStream_t s);
 int launch_scale(double* y, const double* x, double a, int64_t n, hipStream_t s);
 bool degree_supported(int dim, int p);
+bool vjp_degree_supported(int dim, int p);
+bool needs_facet_records(int dim, int p);   // the residual workspace holds Workspace::frec
 }  // namespace esd

@@ -24,6 +24,7 @@ SMALL = [
     ("tri_p3_random_lf", wl.random_tri(M=3, degree=3, seed=2)),
     ("tri_p5_random_ec", wl.random_tri(M=3, degree=5, seed=3, dissipation=0)),
     ("tri_p8_random_lf", wl.random_tri(M=2 + 1, degree=8, seed=4)),
+    ("tri_p10_random_ec", wl.random_tri(M=3, degree=10, seed=10, dissipation=0)),
     ("tet_p1_random_lf", wl.random_tet(M=3, degree=1, seed=5)),
     ("tet_p2_random_ec", wl.random_tet(M=3, degree=2, seed=6, dissipation=0)),
     ("tet_p3_random_lf", wl.random_tet(M=3, degree=3, seed=7)),
@@ -54,7 +55,11 @@ def test_residual_parity_small(name, wk):
     assert_parity(out, ref, what=name, mag=mag)
 
 
-@pytest.mark.parametrize("name,wk", SMALL[:2] + SMALL[5:7], ids=[s[0] for s in SMALL[:2] + SMALL[5:7]])
+PROJ = [c for c in SMALL if c[0] in ("tri_p2_affine_chandrashekar_ec", "tri_p1_random_lf", "tet_p1_random_lf",
+                                     "tet_p2_random_ec")]
+
+
+@pytest.mark.parametrize("name,wk", PROJ, ids=[s[0] for s in PROJ])
 def test_projection_parity(name, wk):
     from oracle import residual as R
     prob = oracle_problem(wk)
@@ -108,6 +113,9 @@ FULL = [
     ("vortex_tri_M64_p4", wl.vortex_tri(M=64, degree=4), 24),
     ("vortex_tri_M64_p8", wl.vortex_tri(M=64, degree=8), 12),
     ("tgv_tet_M16_p4", wl.tgv_tet(M=16, degree=4), 8),
+    # high degrees on a small mesh: the dense oracle is O(N_q^2) per element
+    ("tet_p9_random_lf_M3", wl.random_tet(M=3, degree=9, seed=8), 2),
+    ("tet_p10_random_ec_M3", wl.random_tet(M=3, degree=10, seed=9, dissipation=0), 2),
 ]
 
 
