@@ -169,6 +169,22 @@ esd_status esd_residual_vjp(const esd_plan* plan, const double* u_dev, const dou
 esd_status esd_rk4_vjp(const esd_plan* plan, const double* stage_ckpt_dev, double dt, int32_t nsteps,
                        double* ubar_dev, void* ws_dev, void* stream);
 
+/* Global diagnostics of the state u_dev, written to out_host [dim + 4]:
+ *   out[0..dim+1]  conserved integrals sum_k w_k J_k u_k per variable (Theorem on
+ *                  conservation);
+ *   out[dim+2]     entropy integral sum_k w_k J_k S(u_k), S = -rho s/(gamma-1)
+ *                  (eq. euler_entropy);
+ *   out[dim+3]     its semi-discrete rate sum_k w_k J_k W(u_k) . (V du~/dt)_k,
+ *                  zero to rounding with the entropy-conservative interface flux,
+ *                  <= 0 with dissipation (Theorems on entropy conservation and
+ *                  stability);
+ * with u = V u~ at the volume nodes and J the interpolated Jacobian.  Evaluates
+ * the residual internally; ws_dev holds info.rk4_workspace_bytes (256-byte
+ * aligned).  Synchronises the stream.  The sums are reduced in a fixed order
+ * (bitwise reproducible for a given plan). */
+esd_status esd_diagnostics(const esd_plan* plan, const double* u_dev, double* out_host, void* ws_dev,
+                           void* stream);
+
 /* Synchronises the stream and returns ESD_EADMISSIBLE if any kernel since the
  * last call saw an inadmissible state (the flag is cleared), else ESD_OK. */
 esd_status esd_sync_status(const esd_plan* plan, void* stream);

@@ -68,6 +68,7 @@ EXPORTS = {
     "esd_rk4": (_c, [_vp, _vp, ctypes.c_double, ctypes.c_int32, _vp, _vp, _vp]),
     "esd_residual_vjp": (_c, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "esd_rk4_vjp": (_c, [_vp, _vp, ctypes.c_double, ctypes.c_int32, _vp, _vp, _vp]),
+    "esd_diagnostics": (_c, [_vp, _vp, ctypes.POINTER(ctypes.c_double), _vp, _vp]),
     "esd_sync_status": (_c, [_vp, _vp]),
     "esd_plan_set_timing": (_c, [_vp, ctypes.c_int32]),
     "esd_plan_get_timing": (_c, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
@@ -224,6 +225,16 @@ class Plan:
         _check(_lib.esd_rk4_vjp(self._h, _ptr(ckpt), float(dt), int(nsteps), _ptr(ubar),
                                 _ptr(self.workspace("rk4_vjp")), _stream()), "esd_rk4_vjp")
         return ubar
+
+    def diagnostics(self, u):
+        """Conserved integrals (per variable), entropy integral and entropy rate
+        of the state u (esd_diagnostics; synchronises)."""
+        assert u.is_contiguous() and tuple(u.shape) == self.state_shape
+        out = np.zeros(self.dim + 4, dtype=np.float64)
+        _check(_lib.esd_diagnostics(self._h, _ptr(u), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                    _ptr(self.workspace("rk4")), _stream()), "esd_diagnostics")
+        nc = self.dim + 2
+        return {"conserved": out[:nc].copy(), "entropy": float(out[nc]), "entropy_rate": float(out[nc + 1])}
 
     def set_timing(self, enable: bool):
         _check(_lib.esd_plan_set_timing(self._h, 1 if enable else 0), "esd_plan_set_timing")

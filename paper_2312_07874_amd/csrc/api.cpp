@@ -434,6 +434,27 @@ esd_status esd_rk4_vjp(const esd_plan* P, const double* stage_ckpt_dev, double d
   return ESD_OK;
 }
 
+esd_status esd_diagnostics(const esd_plan* P, const double* u_dev, double* out_host, void* ws_dev, void* stream) {
+  esd_status st = check_device(P);
+  if (st != ESD_OK) return st;
+  if (!u_dev || !out_host || !ws_dev) return fail(ESD_EINVAL, "NULL buffer");
+  if (((uintptr_t)ws_dev) % 256 != 0) return fail(ESD_EINVAL, "workspace not 256-byte aligned");
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t n = P->ne * P->nc * P->ref.NP;
+  const size_t nb = align256((size_t)n * sizeof(double));
+  // residual workspace, then du~/dt, then the partial sums and the result
+  double* dudt = (double*)((char*)ws_dev + P->ws_bytes);
+  double* part = (double*)((char*)ws_dev + P->ws_bytes + nb);
+  double* res = part + P->ne * (P->nc + 2);
+  int rc = esd::launch_residual(P, u_dev, dudt, split_ws(P, ws_dev), s);
+  if (rc == 0) rc = esd::launch_diagnostics(P, u_dev, dudt, part, res, s);
+  if (rc < 0) return fail(ESD_EUNSUPPORTED, "degree not built");
+  if (rc != 0) return fail(ESD_EHIP, std::string("diagnostics launch failed: ") + hipGetErrorString((hipError_t)rc));
+  HIP_TRY(hipMemcpyAsync(out_host, res, (P->nc + 2) * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return ESD_OK;
+}
+
 esd_status esd_sync_status(const esd_plan* P, void* stream) {
   esd_status st = check_device(P);
   if (st != ESD_OK) return st;

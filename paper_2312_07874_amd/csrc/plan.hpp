@@ -99,6 +99,9 @@ int launch_vjp(const esd_plan* P, const double* u, const double* vbar, double* g
 int launch_adj_stage(double* acc, double* kb, const double* ubar, const double* G, double cu, double cg, int first,
                      int64_t n, hipStream_t s);
 int launch_scale(double* y, const double* x, double a, int64_t n, hipStream_t s);
+// diagnostics.hip: part [ne][dim+4] partial sums, out [dim+4] (device)
+int launch_diagnostics(const esd_plan* P, const double* u, const double* dudt, double* part, double* out,
+                       hipStream_t s);
 bool degree_supported(int dim, int p);
 bool vjp_degree_supported(int dim, int p);
 bool needs_facet_records(int dim, int p);   // the residual workspace holds Workspace::frec

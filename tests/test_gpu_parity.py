@@ -135,3 +135,41 @@ def test_residual_parity_full_size_sampled(name, wk, nsample):
     ref = R.residual_chunked(prob, ut, el, chunk=4)
     mag = torch.cat([R.residual_magnitude(prob, ut, el[i:i + 4]) for i in range(0, len(el), 4)], 0)
     assert_parity(out[el], ref, what=name, mag=mag)
+
+
+DIAG = [c for c in SMALL if c[0] in ("tri_p2_affine_chandrashekar_ec", "tri_p3_random_lf", "tet_p2_random_ec",
+                                     "tet_p3_random_lf", "tet_p4_tgv_ec")]
+
+
+@pytest.mark.parametrize("name,wk", DIAG, ids=[s[0] for s in DIAG])
+def test_diagnostics_parity(name, wk):
+    """esd_diagnostics against the oracle's conserved integrals, entropy
+    integral and entropy rate; the rate vanishes to rounding with the
+    entropy-conservative interface flux and is negative with dissipation."""
+    from oracle import physics as PH
+    from oracle import residual as R
+    prob = oracle_problem(wk)
+    ut = oracle_state(prob, wk)
+    plan = gpu_plan(wk)
+    d = plan.diagnostics(ut.cuda().contiguous())
+    ref_c = R.conserved_integrals(prob, ut).numpy()
+    u = torch.einsum("ki,eci->ekc", prob.ref.V, ut)
+    wJ = prob.ref.w[None, :] * prob.geo.J
+    S = PH.entropy(u, prob.gamma)
+    ref_s = float((wJ * S).sum())
+    dudt = R.residual_chunked(prob, ut)
+    ref_r = float(R.entropy_rate(prob, ut, dudt))
+    # magnitude of the rate's terms, for its rounding bound
+    Wu = PH.entropy_vars(u, prob.gamma)
+    du = torch.einsum("ki,eci->ekc", prob.ref.V, dudt)
+    mag_r = float((wJ[..., None] * (Wu * du).abs()).sum())
+    log(f"diagnostics {name}: conserved {d['conserved']}, entropy {d['entropy']:.15e}, "
+        f"rate {d['entropy_rate']:.3e} (oracle {ref_r:.3e}, terms {mag_r:.3e})")
+    scale_c = float((wJ[..., None] * u.abs()).sum((0, 1)).max())
+    assert np.abs(d["conserved"] - ref_c).max() <= 1e-13 * scale_c
+    assert abs(d["entropy"] - ref_s) <= 1e-13 * float((wJ * S.abs()).sum())
+    assert abs(d["entropy_rate"] - ref_r) <= 1e-12 * mag_r
+    if wk.dissipation:
+        assert d["entropy_rate"] < 0
+    else:
+        assert abs(d["entropy_rate"]) <= 1e-12 * mag_r
