@@ -106,8 +106,10 @@ def _pair_fluxes(prob: Problem, ua: torch.Tensor, ub: torch.Tensor) -> torch.Ten
     return torch.stack(out, -1)
 
 
-def _facet_states(prob: Problem, wt_all: torch.Tensor, idx_of: dict, elems):
-    """Own facet entropy-projected states and exterior states for each facet."""
+def _facet_states(prob: Problem, wt_all: torch.Tensor, idx_of: dict, elems, exterior=None):
+    """Own facet entropy-projected states and exterior states for each facet.
+    exterior(elems, z, ext_z) may replace the exterior states of facet z (used
+    for neighbours of another degree)."""
     ref, con = prob.ref, prob.con
     own, ext = [], []
     for z in range(ref.Nf):
@@ -121,7 +123,8 @@ def _facet_states(prob: Problem, wt_all: torch.Tensor, idx_of: dict, elems):
         wp = torch.stack([ref.R[int(nz[i])] @ wv_nb[i] for i in range(len(elems))])  # [nE, Nqf, Nc]
         perm = torch.as_tensor(con.node_map[elems, z])
         wp = torch.gather(wp, 1, perm[:, :, None].expand(-1, -1, wp.shape[-1]))
-        ext.append(ph.cons_from_entropy(wp, prob.gamma))
+        ext_z = ph.cons_from_entropy(wp, prob.gamma)
+        ext.append(ext_z if exterior is None else exterior(elems, z, ext_z))
     return own, ext
 
 
@@ -131,9 +134,9 @@ def _neighbourhood(prob: Problem, elems):
     return elems, need
 
 
-def residual_nodal(prob: Problem, ut: torch.Tensor, elems=None):
+def residual_nodal(prob: Problem, ut: torch.Tensor, elems=None, exterior=None):
     """Nodal right-hand side r of eq. (entropy_stable) for the given elements.
-    Returns (r [nE, Nq, Nc], w [nE, Nq, Nc])."""
+    Returns (r [nE, Nq, Nc], w [nE, Nq, Nc]).  exterior: see _facet_states."""
     ref, geo = prob.ref, prob.geo
     d, g = ref.dim, prob.gamma
     if elems is None:
@@ -153,7 +156,7 @@ def residual_nodal(prob: Problem, ut: torch.Tensor, elems=None):
         H = torch.einsum("eijm,eijcm->eijc", Gavg, F)
         r = r - torch.einsum("ij,eijc->eic", 2.0 * ref.S[l], H)
     del F
-    own, ext = _facet_states(prob, wt_need, idx_of, elems)
+    own, ext = _facet_states(prob, wt_need, idx_of, elems, exterior)
     for z in range(ref.Nf):
         uf = own[z]
         # facet correction C^z = R^T B o sum_m {J n_m} o F^{z,m}
@@ -172,12 +175,12 @@ def residual_nodal(prob: Problem, ut: torch.Tensor, elems=None):
     return r, w
 
 
-def residual(prob: Problem, ut: torch.Tensor, elems=None) -> torch.Tensor:
+def residual(prob: Problem, ut: torch.Tensor, elems=None, exterior=None) -> torch.Tensor:
     """du~/dt = Mt^{-1} V^T r for the given elements -> [nE, Nc, Np]."""
     if elems is None:
         elems = np.arange(prob.ne)
     elems = np.asarray(elems, dtype=np.int64).reshape(-1)
-    r, _ = residual_nodal(prob, ut, elems)
+    r, _ = residual_nodal(prob, ut, elems, exterior)
     A = wadj_inverse(prob, torch.as_tensor(elems))
     b = torch.einsum("ki,ekc->eci", prob.ref.V, r)
     return torch.einsum("eij,ecj->eci", A, b)
