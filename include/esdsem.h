@@ -114,6 +114,47 @@ esd_status esd_plan_create(const esd_mesh_desc* mesh, const esd_scheme_desc* sch
 void esd_plan_destroy(esd_plan* plan);
 esd_status esd_plan_query(const esd_plan* plan, esd_plan_info* out);
 
+/* Several independent meshes whose elements carry their own degrees, in one
+ * plan.  Elements are grouped into buckets by degree (all meshes together;
+ * ascending degree; within a bucket, in mesh order then element order); every
+ * bucket runs its degree's kernels.  Across a facet whose two elements have
+ * different degrees, the exterior state at a facet node is the neighbour's
+ * modal entropy expansion at the node's reference point on the shared facet
+ * (for equal degrees this is the conforming rule of Assumption conformal; with
+ * a change of degree the scheme is not conservative or entropy stable there).
+ * Vertex ids are per mesh; the warp applies to every mesh. */
+typedef struct {
+  int32_t dim;
+  int32_t n_meshes;
+  const int64_t* n_elements;                 /* host [n_meshes]                              */
+  const int64_t* const* elem_vertex_ids;     /* host [n_meshes] -> [n_elements][dim+1]      */
+  const double* const* elem_vertex_coords;   /* host [n_meshes] -> [n_elements][dim+1][dim] */
+  const int32_t* const* elem_degree;         /* host [n_meshes] -> [n_elements]             */
+  esd_warp_fn warp;                          /* may be NULL                                  */
+  void* warp_ctx;
+} esd_batch_desc;
+
+/* Builds a batched plan (see esd_batch_desc).  Its state is
+ * [bucket][element-in-bucket][variable][mode], nodal arrays (esd_project,
+ * esd_node_coords) are [bucket][element-in-bucket][node][...]; offsets from
+ * esd_plan_buckets.  esd_residual, esd_rk4, esd_project, esd_node_coords,
+ * esd_diagnostics and esd_sync_status accept it; the VJP entry points return
+ * ESD_EUNSUPPORTED and esd_plan_host_array ESD_EINVAL.  Errors as
+ * esd_plan_create. */
+esd_status esd_plan_create_batched(const esd_batch_desc* batch, const esd_scheme_desc* scheme, uint32_t flags,
+                                   esd_plan** out);
+
+/* Buckets of a plan (a single-degree plan has one): count, degree[b],
+ * n_elements[b], and offsets dof_offset[b] (doubles into the state) and
+ * node_offset[b] (volume nodes into nodal arrays), b = 0..n (n + 1 entries).
+ * The arrays hold at least 16 (17 for the offsets) entries. */
+esd_status esd_plan_buckets(const esd_plan* plan, int32_t* n_buckets, int32_t* degree, int64_t* n_elements,
+                            int64_t* dof_offset, int64_t* node_offset);
+
+/* Bucket and slot of every input element (meshes concatenated in order);
+ * count must equal info.n_elements. */
+esd_status esd_plan_element_map(const esd_plan* plan, int32_t* bucket, int64_t* slot, int64_t count);
+
 /* Copies a host-side setup array of the plan into out (count doubles).  Names:
  * "x_vol" [e][node][dim] physical volume-node coordinates, "J" [e][node]
  * interpolated Jacobian (eq. jacobian_approx), "G" [e][node][l][m] metric terms

@@ -45,6 +45,14 @@ class _SchemeDesc(ctypes.Structure):
     _fields_ = [("gamma", ctypes.c_double), ("ecflux", ctypes.c_int32), ("dissipation", ctypes.c_int32)]
 
 
+class _BatchDesc(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("n_meshes", ctypes.c_int32), ("n_elements", ctypes.POINTER(ctypes.c_int64)),
+                ("elem_vertex_ids", ctypes.POINTER(ctypes.POINTER(ctypes.c_int64))),
+                ("elem_vertex_coords", ctypes.POINTER(ctypes.POINTER(ctypes.c_double))),
+                ("elem_degree", ctypes.POINTER(ctypes.POINTER(ctypes.c_int32))),
+                ("warp", WARP_FN), ("warp_ctx", ctypes.c_void_p)]
+
+
 class PlanInfo(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("degree", ctypes.c_int32), ("n_vars", ctypes.c_int32),
                 ("n_modes", ctypes.c_int32), ("n_vol_nodes", ctypes.c_int32), ("n_facets", ctypes.c_int32),
@@ -59,6 +67,13 @@ _c = ctypes.c_int
 EXPORTS = {
     "esd_plan_create": (_c, [ctypes.POINTER(_MeshDesc), ctypes.POINTER(_SchemeDesc), ctypes.c_uint32,
                              ctypes.POINTER(_vp)]),
+    "esd_plan_create_batched": (_c, [ctypes.POINTER(_BatchDesc), ctypes.POINTER(_SchemeDesc), ctypes.c_uint32,
+                                     ctypes.POINTER(_vp)]),
+    "esd_plan_buckets": (_c, [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                              ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                              ctypes.POINTER(ctypes.c_int64)]),
+    "esd_plan_element_map": (_c, [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64),
+                                  ctypes.c_int64]),
     "esd_plan_destroy": (None, [_vp]),
     "esd_plan_query": (_c, [_vp, ctypes.POINTER(PlanInfo)]),
     "esd_plan_host_array": (_c, [_vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int64]),
@@ -248,6 +263,88 @@ class Plan:
 
     def sync_status(self):
         _check(_lib.esd_sync_status(self._h, _stream()), "esd_sync_status")
+
+
+def _warp_callback(dim, warp):
+    if warp is None:
+        return WARP_FN()
+
+    def _cb(n, xin, xout, ctx, _dim=dim, _warp=warp):
+        a = np.ctypeslib.as_array(xin, shape=(n * _dim,)).reshape(n, _dim)
+        b = np.ctypeslib.as_array(xout, shape=(n * _dim,)).reshape(n, _dim)
+        b[...] = _warp(a.copy())
+    return WARP_FN(_cb)
+
+
+class BatchedPlan(Plan):
+    """Several meshes with per-element degrees in one plan
+    (esd_plan_create_batched).  The state is a flat tensor [n_dof] holding the
+    buckets one after the other ([element][variable][mode] inside a bucket);
+    nodal arrays are flat [n_nodes, ...] in the same bucket order."""
+
+    def __init__(self, dim: int, meshes, warp=None, gamma: float = 1.4, ecflux: int = FLUX_RANOCHA,
+                 dissipation: int = DISS_LLF_DAVIS, host_only: bool = False):
+        """meshes: list of (elem_vertex_ids, elem_vertex_coords, elem_degree)."""
+        self._ids = [np.ascontiguousarray(m[0], dtype=np.int64) for m in meshes]
+        self._xy = [np.ascontiguousarray(m[1], dtype=np.float64) for m in meshes]
+        self._deg = [np.ascontiguousarray(m[2], dtype=np.int32) for m in meshes]
+        nm = len(meshes)
+        self._ne = np.array([a.shape[0] for a in self._ids], dtype=np.int64)
+        P64, PD, P32 = ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)
+        self._pid = (P64 * nm)(*[a.ctypes.data_as(P64) for a in self._ids])
+        self._pxy = (PD * nm)(*[a.ctypes.data_as(PD) for a in self._xy])
+        self._pdeg = (P32 * nm)(*[a.ctypes.data_as(P32) for a in self._deg])
+        self._cb = _warp_callback(dim, warp)
+        desc = _BatchDesc(dim, nm, self._ne.ctypes.data_as(P64), self._pid, self._pxy, self._pdeg, self._cb, None)
+        sch = _SchemeDesc(gamma, ecflux, dissipation)
+        h = _vp()
+        _check(_lib.esd_plan_create_batched(ctypes.byref(desc), ctypes.byref(sch), 1 if host_only else 0,
+                                            ctypes.byref(h)), "esd_plan_create_batched")
+        self._h = h
+        self.info = PlanInfo()
+        _check(_lib.esd_plan_query(self._h, ctypes.byref(self.info)), "esd_plan_query")
+        self.dim, self.degree, self.gamma = dim, None, gamma
+        self._ws = None
+        nb = ctypes.c_int32()
+        deg = (ctypes.c_int32 * 16)()
+        nel = (ctypes.c_int64 * 16)()
+        doff = (ctypes.c_int64 * 17)()
+        noff = (ctypes.c_int64 * 17)()
+        _check(_lib.esd_plan_buckets(self._h, ctypes.byref(nb), deg, nel, doff, noff), "esd_plan_buckets")
+        self.buckets = [dict(degree=deg[b], n_elements=nel[b], dof=(doff[b], doff[b + 1]), nodes=(noff[b], noff[b + 1]))
+                        for b in range(nb.value)]
+        ne = int(self.info.n_elements)
+        self.elem_bucket = np.empty(ne, dtype=np.int32)
+        self.elem_slot = np.empty(ne, dtype=np.int64)
+        _check(_lib.esd_plan_element_map(self._h, self.elem_bucket.ctypes.data_as(P32),
+                                         self.elem_slot.ctypes.data_as(P64), ne), "esd_plan_element_map")
+
+    @property
+    def state_shape(self):
+        return (int(self.info.n_dof),)
+
+    @property
+    def n_nodes(self):
+        return int(self.buckets[-1]["nodes"][1])
+
+    @property
+    def nodal_shape(self):
+        return (self.n_nodes, self.info.n_vars)
+
+    def bucket_view(self, u, b):
+        """[n_elements, n_vars, n_modes] view of bucket b of a flat state."""
+        bk = self.buckets[b]
+        a, e = bk["dof"]
+        return u[a:e].view(bk["n_elements"], self.info.n_vars, -1)
+
+    def node_coords(self):
+        import torch
+        x = torch.empty((self.n_nodes, self.dim), dtype=torch.float64, device="cuda")
+        _check(_lib.esd_node_coords(self._h, _ptr(x), _stream()), "esd_node_coords")
+        return x
+
+    def vjp(self, *a, **k):
+        raise EsdError(-4, "BatchedPlan.vjp")
 
 
 def _autograd_residual():

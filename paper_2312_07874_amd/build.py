@@ -49,13 +49,15 @@ def build(verbose: bool = False) -> str:
         [HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "kernels.hip"), "-o", os.path.join(BUILD, "kernels.o")],
         [HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "adjoint.hip"), "-o", os.path.join(BUILD, "adjoint.o")],
         [HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "diagnostics.hip"), "-o", os.path.join(BUILD, "diagnostics.o")],
+        [HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "batch.hip"), "-o", os.path.join(BUILD, "batch.o")],
     ]
     with ThreadPoolExecutor(max_workers=len(jobs)) as ex:
         list(ex.map(lambda c: _run(c, verbose), jobs))
     tmp = LIB + ".tmp"
     _run([HIPCC, "-shared", f"--offload-arch={ARCH}", "-o", tmp,
           os.path.join(BUILD, "host_setup.o"), os.path.join(BUILD, "api.o"), os.path.join(BUILD, "kernels.o"),
-          os.path.join(BUILD, "adjoint.o"), os.path.join(BUILD, "diagnostics.o"), "-pthread"], verbose)
+          os.path.join(BUILD, "adjoint.o"), os.path.join(BUILD, "diagnostics.o"),
+          os.path.join(BUILD, "batch.o"), "-pthread"], verbose)
     os.replace(tmp, LIB)
     return LIB
 

@@ -4,7 +4,9 @@
 #include <cmath>
 #include <cstring>
 #include <exception>
+#include <array>
 #include <limits>
+#include <map>
 #include <new>
 #include <string>
 #include <vector>
@@ -41,9 +43,14 @@ void free_device(esd_plan* p) {
   if (p->d_gfac) (void)hipFree(p->d_gfac);
   if (p->d_conn) (void)hipFree(p->d_conn);
   if (p->d_xvol) (void)hipFree(p->d_xvol);
-  if (p->d_flag) (void)hipFree(p->d_flag);
-  p->d_tables = p->d_gvol = p->d_gfac = p->d_xvol = nullptr;
-  p->d_conn = nullptr;
+  if (p->d_flag && p->flag_owned) (void)hipFree(p->d_flag);
+  if (p->d_tasks) (void)hipFree(p->d_tasks);
+  if (p->d_mats) (void)hipFree(p->d_mats);
+  if (p->d_mat_off) (void)hipFree(p->d_mat_off);
+  if (p->d_wt_off) (void)hipFree(p->d_wt_off);
+  p->d_tables = p->d_gvol = p->d_gfac = p->d_xvol = p->d_mats = nullptr;
+  p->d_conn = p->d_tasks = nullptr;
+  p->d_mat_off = p->d_wt_off = nullptr;
   p->d_flag = nullptr;
 }
 
@@ -87,11 +94,15 @@ extern "C" {
 
 const char* esd_last_error(void) { return g_err.c_str(); }
 
-esd_status esd_plan_create(const esd_mesh_desc* mesh, const esd_scheme_desc* scheme, uint32_t flags,
-                           esd_plan** out) {
-  if (!out) return fail(ESD_EINVAL, "out is NULL");
+}  // extern "C"
+
+namespace {
+// One plan for elements of one degree.  connect = false leaves the facet
+// permutation to the caller (elements of one degree out of a mixed mesh, whose
+// facet-state region then holds 2 ne slots: own values and exterior values).
+esd_status create_single(const esd_mesh_desc* mesh, const esd_scheme_desc* scheme, uint32_t flags, bool connect,
+                         esd_plan** out) {
   *out = nullptr;
-  if (!mesh || !scheme) return fail(ESD_EINVAL, "mesh or scheme is NULL");
   if (mesh->dim != 2 && mesh->dim != 3) return fail(ESD_EUNSUPPORTED, "dim must be 2 or 3");
   if (!esd::degree_supported(mesh->dim, mesh->degree))
     return fail(ESD_EUNSUPPORTED, "degree " + std::to_string(mesh->degree) + " not built for dim " +
@@ -116,14 +127,15 @@ esd_status esd_plan_create(const esd_mesh_desc* mesh, const esd_scheme_desc* sch
     P->ref = esd::build_ref_tables(P->dim, P->p);
     std::string msg;
     const int rc = esd::build_geometry(P->ref, P->ne, mesh->elem_vertex_ids, mesh->elem_vertex_coords,
-                                       (esd::warp_fn)mesh->warp, mesh->warp_ctx, P->geo, msg);
+                                       (esd::warp_fn)mesh->warp, mesh->warp_ctx, P->geo, msg, connect);
+    P->wext = !connect;
     if (rc != 0) {
       delete P;
       return fail((esd_status)rc, msg);
     }
     const esd::RefTables& R = P->ref;
     const size_t ndof = (size_t)P->ne * P->nc * R.NP;
-    const size_t fbytes = align256((size_t)P->ne * P->nc * R.NFQ * sizeof(double));
+    const size_t fbytes = align256((size_t)P->ne * P->nc * R.NFQ * sizeof(double) * (P->wext ? 2 : 1));
     P->frec_bytes = esd::needs_facet_records(P->dim, P->p)
                         ? align256((size_t)P->ne * 8 * R.NFQ * sizeof(double)) : 0;
     P->ws_bytes = align256(ndof * sizeof(double)) + fbytes + P->frec_bytes;
@@ -181,6 +193,7 @@ esd_status esd_plan_create(const esd_mesh_desc* mesh, const esd_scheme_desc* sch
       for (int j = 0; j < NFQ; ++j) {
         for (int m = 0; m < dim; ++m) gf[((size_t)e * (dim + 1) + m) * NFQ + j] = P->geo.nJ[((size_t)e * NFQ + j) * dim + m];
         gf[((size_t)e * (dim + 1) + dim) * NFQ + j] = P->geo.Jf[(size_t)e * NFQ + j];
+        if (!connect) continue;
         const int64_t nb = P->geo.nbr[(size_t)e * NFQ + j];
         const int64_t ne_ = nb / NFQ, rem = nb % NFQ;
         const int64_t nf = rem / NQF, nn = rem % NQF;
@@ -189,7 +202,7 @@ esd_status esd_plan_create(const esd_mesh_desc* mesh, const esd_scheme_desc* sch
       }
     // the VJP gathers exterior cotangents through the same permutation, which
     // needs it to pair facet nodes both ways
-    P->conn_involutive = true;
+    P->conn_involutive = connect;
     for (int64_t e = 0; e < P->ne && P->conn_involutive; ++e)
       for (int j = 0; j < NFQ; ++j) {
         const int64_t a = conn[(size_t)e * NFQ + j];
@@ -200,7 +213,7 @@ esd_status esd_plan_create(const esd_mesh_desc* mesh, const esd_scheme_desc* sch
         }
       }
     if (st == ESD_OK) st = upload(&P->d_gfac, gf);
-    if (st == ESD_OK) st = upload(&P->d_conn, conn);
+    if (st == ESD_OK && connect) st = upload(&P->d_conn, conn);
     if (st == ESD_OK) st = upload(&P->d_xvol, P->geo.x_vol);
     if (st == ESD_OK) st = upload(&P->d_flag, std::vector<int>(1, 0));
     if (st != ESD_OK) {
@@ -216,9 +229,262 @@ esd_status esd_plan_create(const esd_mesh_desc* mesh, const esd_scheme_desc* sch
   *out = P;
   return ESD_OK;
 }
+}  // namespace
+
+extern "C" {
+
+esd_status esd_plan_create(const esd_mesh_desc* mesh, const esd_scheme_desc* scheme, uint32_t flags,
+                           esd_plan** out) {
+  if (!out) return fail(ESD_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!mesh || !scheme) return fail(ESD_EINVAL, "mesh or scheme is NULL");
+  return create_single(mesh, scheme, flags, true, out);
+}
+
+esd_status esd_plan_create_batched(const esd_batch_desc* d, const esd_scheme_desc* scheme, uint32_t flags,
+                                   esd_plan** out) {
+  if (!out) return fail(ESD_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!d || !scheme || d->n_meshes <= 0 || !d->n_elements || !d->elem_vertex_ids || !d->elem_vertex_coords ||
+      !d->elem_degree)
+    return fail(ESD_EINVAL, "bad batch description");
+  if (d->dim != 2 && d->dim != 3) return fail(ESD_EUNSUPPORTED, "dim must be 2 or 3");
+  if (!(scheme->gamma > 1.0) || scheme->ecflux < 0 || scheme->ecflux > 1 || scheme->dissipation < 0 ||
+      scheme->dissipation > 1)
+    return fail(ESD_EINVAL, "bad scheme parameters");
+  const int dim = d->dim, nv = dim + 1, NF = dim + 1, nc = dim + 2;
+  const bool host_only = (flags & 1u) != 0;
+  esd_plan* P = new (std::nothrow) esd_plan();
+  if (!P) return fail(ESD_ENOMEM, "host allocation failed");
+  auto bail = [&](esd_status st, const std::string& m) {
+    esd_plan_destroy(P);
+    return fail(st, m);
+  };
+  try {
+    P->batched = true;
+    P->dim = dim;
+    P->nc = nc;
+    P->p = 0;
+    P->host_only = host_only;
+    P->scheme.gamma = scheme->gamma;
+    P->scheme.gm1_inv = 1.0 / (scheme->gamma - 1.0);
+    P->scheme.ecflux = scheme->ecflux;
+    P->scheme.dissipation = scheme->dissipation;
+    // ---- face adjacency and orientation of every mesh, from a degree-1 pass
+    //      (orientation depends only on vertex ids and coordinates)
+    const esd::RefTables r1 = esd::build_ref_tables(dim, 1);
+    const int nqf1 = r1.NQF;
+    std::vector<std::vector<int64_t>> nbr_e(d->n_meshes);
+    std::vector<std::vector<int8_t>> nbr_f(d->n_meshes), flip(d->n_meshes);
+    std::vector<int64_t> first(d->n_meshes + 1, 0);
+    std::vector<int> present(esd::MAX_DEGREE + 1, 0);
+    for (int m = 0; m < d->n_meshes; ++m) {
+      const int64_t ne = d->n_elements[m];
+      if (ne <= 0 || !d->elem_vertex_ids[m] || !d->elem_vertex_coords[m] || !d->elem_degree[m])
+        return bail(ESD_EINVAL, "mesh " + std::to_string(m) + ": empty or NULL arrays");
+      for (int64_t e = 0; e < ne; ++e) {
+        const int p = d->elem_degree[m][e];
+        if (!esd::degree_supported(dim, p))
+          return bail(ESD_EUNSUPPORTED, "degree " + std::to_string(p) + " not built");
+        present[p] = 1;
+      }
+      esd::HostGeometry g;
+      std::string msg;
+      const int rc = esd::build_geometry(r1, ne, d->elem_vertex_ids[m], d->elem_vertex_coords[m],
+                                         (esd::warp_fn)d->warp, d->warp_ctx, g, msg, true);
+      if (rc != 0) return bail((esd_status)rc, "mesh " + std::to_string(m) + ": " + msg);
+      nbr_e[m].resize(ne * NF);
+      nbr_f[m].resize(ne * NF);
+      flip[m].resize(ne * NF);
+      for (int64_t e = 0; e < ne; ++e)
+        for (int f = 0; f < NF; ++f) {
+          const int64_t nb = g.nbr[((size_t)e * NF + f) * nqf1];   // facet node 0 (a1 = a2 = 0)
+          nbr_e[m][e * NF + f] = nb / (NF * nqf1);
+          nbr_f[m][e * NF + f] = (int8_t)((nb / nqf1) % NF);
+          flip[m][e * NF + f] = (int8_t)((nb % nqf1) % 2 == 1);    // its partner has a1 = Q - 1 = 1
+        }
+      first[m + 1] = first[m] + ne;
+    }
+    // ---- buckets by degree, slots in mesh order
+    std::vector<int> degs;
+    for (int p = 0; p <= esd::MAX_DEGREE; ++p)
+      if (present[p]) degs.push_back(p);
+    std::vector<int> bidx(esd::MAX_DEGREE + 1, -1);
+    for (size_t b = 0; b < degs.size(); ++b) bidx[degs[b]] = (int)b;
+    const int nb_ = (int)degs.size();
+    P->elem_bucket.resize(first.back());
+    P->elem_slot.resize(first.back());
+    std::vector<std::vector<std::pair<int, int64_t>>> members(nb_);
+    for (int m = 0; m < d->n_meshes; ++m)
+      for (int64_t e = 0; e < d->n_elements[m]; ++e) {
+        const int b = bidx[d->elem_degree[m][e]];
+        P->elem_bucket[first[m] + e] = b;
+        P->elem_slot[first[m] + e] = (int64_t)members[b].size();
+        members[b].push_back({m, e});
+      }
+    // ---- one single-degree plan per bucket (geometry without connectivity)
+    for (int b = 0; b < nb_; ++b) {
+      const int64_t ne_b = (int64_t)members[b].size();
+      std::vector<int64_t> ids(ne_b * nv);
+      std::vector<double> xy(ne_b * nv * dim);
+      for (int64_t i = 0; i < ne_b; ++i) {
+        const int m = members[b][i].first;
+        const int64_t e = members[b][i].second;
+        for (int k = 0; k < nv; ++k) ids[i * nv + k] = d->elem_vertex_ids[m][e * nv + k];
+        for (int k = 0; k < nv * dim; ++k) xy[i * nv * dim + k] = d->elem_vertex_coords[m][e * nv * dim + k];
+      }
+      esd_mesh_desc md{dim, degs[b], ne_b, ids.data(), xy.data(), d->warp, d->warp_ctx};
+      esd_plan* sp = nullptr;
+      const esd_status st = create_single(&md, scheme, flags, false, &sp);
+      if (st != ESD_OK) {
+        const std::string m = g_err;
+        return bail(st, "bucket p=" + std::to_string(degs[b]) + ": " + m);
+      }
+      P->sub.push_back(sp);
+    }
+    // ---- facet permutation tables, mixed-interface tasks and matrices
+    std::map<std::array<int, 4>, int> matid;
+    std::vector<double> mats;
+    std::vector<int64_t> mat_off;
+    for (int b = 0; b < nb_; ++b) {
+      esd_plan* sp = P->sub[b];
+      const esd::RefTables& R = sp->ref;
+      const int NFQ = R.NFQ, NQF = R.NQF, Q = R.Q;
+      const int64_t ne_b = sp->ne, stride = (int64_t)nc * NFQ;
+      if (2 * ne_b * stride >= std::numeric_limits<int32_t>::max())
+        return bail(ESD_EUNSUPPORTED, "bucket too large for 32-bit facet addressing");
+      std::vector<int32_t> conn(ne_b * NFQ);
+      std::vector<int32_t> tasks;
+      for (int64_t i = 0; i < ne_b; ++i) {
+        const int m = members[b][i].first;
+        const int64_t e = members[b][i].second;
+        for (int f = 0; f < NF; ++f) {
+          const int64_t en = nbr_e[m][e * NF + f];
+          const int fn = nbr_f[m][e * NF + f];
+          const bool fl = flip[m][e * NF + f] != 0;
+          const int bn = P->elem_bucket[first[m] + en];
+          const int64_t in = P->elem_slot[first[m] + en];
+          if (bn == b) {
+            for (int j = 0; j < NQF; ++j) {
+              const int a1 = j % Q, a2 = j / Q;
+              const int b1 = fl ? Q - 1 - a1 : a1;
+              const int jb = dim == 2 ? b1 : b1 + Q * a2;
+              conn[i * NFQ + f * NQF + j] = (int32_t)(in * stride + fn * NQF + jb);
+            }
+            continue;
+          }
+          for (int j = 0; j < NQF; ++j)
+            conn[i * NFQ + f * NQF + j] = (int32_t)(ne_b * stride + i * stride + f * NQF + j);
+          const int pn = degs[bn];
+          const std::array<int, 4> key = {degs[b], pn, fn, fl ? 1 : 0};
+          auto it = matid.find(key);
+          if (it == matid.end()) {
+            // the neighbour's PKD basis at the reference points of this degree's
+            // facet nodes, carried across the shared facet (reversed Legendre
+            // coordinate when the orientations differ)
+            const int npn = esd::n_modes(dim, pn);
+            mat_off.push_back((int64_t)mats.size());
+            std::vector<double> row(npn);
+            for (int j = 0; j < NQF; ++j) {
+              const int a1 = j % Q, a2 = j / Q;
+              const double sc = fl ? -R.xl[a1] : R.xl[a1];
+              const double tc = dim == 3 ? R.xj[a2] : 0.0;
+              double xi[3];
+              esd::facet_point(dim, fn, sc, tc, xi);
+              esd::pkd_eval(dim, pn, xi, 1, row.data());
+              mats.insert(mats.end(), row.begin(), row.end());
+            }
+            it = matid.emplace(key, (int)mat_off.size() - 1).first;
+          }
+          const int32_t t[8] = {(int32_t)i, f, bn, (int32_t)in, it->second, 0, esd::n_modes(dim, pn), 0};
+          tasks.insert(tasks.end(), t, t + 8);
+        }
+      }
+      sp->n_tasks = (int64_t)tasks.size() / 8;
+      if (!host_only) {
+        esd_status st = upload(&sp->d_conn, conn);
+        if (st == ESD_OK && !tasks.empty()) st = upload(&sp->d_tasks, tasks);
+        if (st != ESD_OK) return bail(st, "upload failed");
+      }
+    }
+    // ---- offsets and workspace
+    P->dof_off.assign(nb_ + 1, 0);
+    P->node_off.assign(nb_ + 1, 0);
+    P->ws_off.assign(nb_, 0);
+    size_t ws = 0;
+    std::vector<int64_t> wt_off(nb_);
+    for (int b = 0; b < nb_; ++b) {
+      esd_plan* sp = P->sub[b];
+      P->dof_off[b + 1] = P->dof_off[b] + sp->ne * nc * sp->ref.NP;
+      P->node_off[b + 1] = P->node_off[b] + sp->ne * sp->ref.NQ;
+      P->ws_off[b] = ws;
+      wt_off[b] = (int64_t)(ws / sizeof(double));
+      ws += align256(sp->ws_bytes);
+    }
+    P->ne = first.back();
+    const size_t ndof = (size_t)P->dof_off.back();
+    P->ws_bytes = ws;
+    P->rk_ws_bytes = ws + 3 * align256(ndof * sizeof(double));
+    P->vjp_ws_bytes = P->rk_vjp_ws_bytes = 0;
+    if (!host_only) {
+      if (hipGetDevice(&P->device) != hipSuccess) return bail(ESD_EHIP, "no HIP device");
+      esd_status st = upload(&P->d_flag, std::vector<int>(1, 0));
+      if (st == ESD_OK && !mats.empty()) st = upload(&P->d_mats, mats);
+      if (st == ESD_OK && !mat_off.empty()) st = upload(&P->d_mat_off, mat_off);
+      if (st == ESD_OK) st = upload(&P->d_wt_off, wt_off);
+      if (st != ESD_OK) return bail(st, "upload failed");
+      for (esd_plan* sp : P->sub) {
+        (void)hipFree(sp->d_flag);
+        sp->d_flag = P->d_flag;
+        sp->flag_owned = false;
+      }
+    }
+  } catch (const std::exception& ex) {
+    return bail(ESD_ENOMEM, std::string("setup failed: ") + ex.what());
+  }
+  *out = P;
+  return ESD_OK;
+}
+
+esd_status esd_plan_buckets(const esd_plan* P, int32_t* n_buckets, int32_t* degree, int64_t* n_elements,
+                            int64_t* dof_offset, int64_t* node_offset) {
+  if (!P || !n_buckets || !degree || !n_elements || !dof_offset || !node_offset)
+    return fail(ESD_EINVAL, "NULL argument");
+  if (!P->batched) {
+    *n_buckets = 1;
+    degree[0] = P->p;
+    n_elements[0] = P->ne;
+    dof_offset[0] = node_offset[0] = 0;
+    dof_offset[1] = P->ne * P->nc * P->ref.NP;
+    node_offset[1] = P->ne * P->ref.NQ;
+    return ESD_OK;
+  }
+  const int nb = (int)P->sub.size();
+  *n_buckets = nb;
+  for (int b = 0; b < nb; ++b) {
+    degree[b] = P->sub[b]->p;
+    n_elements[b] = P->sub[b]->ne;
+  }
+  for (int b = 0; b <= nb; ++b) {
+    dof_offset[b] = P->dof_off[b];
+    node_offset[b] = P->node_off[b];
+  }
+  return ESD_OK;
+}
+
+esd_status esd_plan_element_map(const esd_plan* P, int32_t* bucket, int64_t* slot, int64_t count) {
+  if (!P || !bucket || !slot) return fail(ESD_EINVAL, "NULL argument");
+  if (count != P->ne) return fail(ESD_EINVAL, "count must equal the number of elements");
+  for (int64_t i = 0; i < count; ++i) {
+    bucket[i] = P->batched ? P->elem_bucket[i] : 0;
+    slot[i] = P->batched ? P->elem_slot[i] : i;
+  }
+  return ESD_OK;
+}
 
 void esd_plan_destroy(esd_plan* plan) {
   if (!plan) return;
+  for (esd_plan* b : plan->sub) esd_plan_destroy(b);
   for (hipEvent_t e : plan->ev) (void)hipEventDestroy(e);
   for (hipEvent_t e : plan->ev_pool) (void)hipEventDestroy(e);
   free_device(plan);
@@ -252,8 +518,24 @@ esd_status esd_plan_get_timing(esd_plan* P, double* k1_ms, double* k2_ms, int64_
 
 esd_status esd_plan_query(const esd_plan* P, esd_plan_info* out) {
   if (!P || !out) return fail(ESD_EINVAL, "NULL argument");
-  const esd::RefTables& R = P->ref;
   std::memset(out, 0, sizeof(*out));
+  if (P->batched) {
+    out->dim = P->dim;
+    out->n_vars = P->nc;
+    out->n_facets = P->dim + 1;
+    out->n_elements = P->ne;
+    out->n_dof = P->dof_off.back();
+    for (const esd_plan* b : P->sub) {
+      esd_plan_info bi;
+      esd_plan_query(b, &bi);
+      out->flux_pairs_paper += bi.flux_pairs_paper;
+      out->flux_pairs_distinct += bi.flux_pairs_distinct;
+    }
+    out->workspace_bytes = P->ws_bytes;
+    out->rk4_workspace_bytes = P->rk_ws_bytes;
+    return ESD_OK;
+  }
+  const esd::RefTables& R = P->ref;
   out->dim = P->dim;
   out->degree = P->p;
   out->n_vars = P->nc;
@@ -283,6 +565,7 @@ esd_status esd_plan_query(const esd_plan* P, esd_plan_info* out) {
 
 esd_status esd_plan_host_array(const esd_plan* P, const char* name, double* out, int64_t count) {
   if (!P || !name || !out) return fail(ESD_EINVAL, "NULL argument");
+  if (P->batched) return fail(ESD_EINVAL, "setup arrays of a batched plan are per bucket; not exposed");
   const std::string n(name);
   if (n == "nbr") {
     if ((int64_t)P->geo.nbr.size() != count) return fail(ESD_EINVAL, "count mismatch for nbr");
@@ -312,6 +595,13 @@ esd_status esd_node_coords(const esd_plan* P, double* x_dev, void* stream) {
   esd_status st = check_device(P);
   if (st != ESD_OK) return st;
   if (!x_dev) return fail(ESD_EINVAL, "x_dev is NULL");
+  if (P->batched) {
+    for (size_t b = 0; b < P->sub.size(); ++b)
+      HIP_TRY(hipMemcpyAsync(x_dev + P->node_off[b] * P->dim, P->sub[b]->d_xvol,
+                             P->sub[b]->geo.x_vol.size() * sizeof(double), hipMemcpyDeviceToDevice,
+                             (hipStream_t)stream));
+    return ESD_OK;
+  }
   HIP_TRY(hipMemcpyAsync(x_dev, P->d_xvol, P->geo.x_vol.size() * sizeof(double), hipMemcpyDeviceToDevice,
                          (hipStream_t)stream));
   return ESD_OK;
@@ -321,6 +611,14 @@ esd_status esd_project(const esd_plan* P, const double* u_nodal_dev, double* u_d
   esd_status st = check_device(P);
   if (st != ESD_OK) return st;
   if (!u_nodal_dev || !u_dev) return fail(ESD_EINVAL, "NULL buffer");
+  if (P->batched) {
+    for (size_t b = 0; b < P->sub.size(); ++b) {
+      const int rc = esd::launch_project(P->sub[b], u_nodal_dev + P->node_off[b] * P->nc, u_dev + P->dof_off[b],
+                                         (hipStream_t)stream);
+      if (rc != 0) return fail(ESD_EHIP, std::string("launch failed: ") + hipGetErrorString((hipError_t)rc));
+    }
+    return ESD_OK;
+  }
   const int rc = esd::launch_project(P, u_nodal_dev, u_dev, (hipStream_t)stream);
   if (rc < 0) return fail(ESD_EUNSUPPORTED, "degree not built");
   if (rc != 0) return fail(ESD_EHIP, std::string("launch failed: ") + hipGetErrorString((hipError_t)rc));
@@ -337,13 +635,42 @@ static esd::Workspace split_ws(const esd_plan* P, void* ws) {
   return w;
 }
 
+static int64_t total_dof(const esd_plan* P) {
+  return P->batched ? P->dof_off.back() : P->ne * P->nc * P->ref.NP;
+}
+
+// one residual evaluation; for a batched plan: K1 of every bucket, the
+// mixed-interface exterior values, then K2 of every bucket
+static int residual_any(const esd_plan* P, const double* u, double* dudt, void* ws, hipStream_t s) {
+  if (!P->batched) return esd::launch_residual(P, u, dudt, split_ws(P, ws), s);
+  const int nb = (int)P->sub.size();
+  if (P->timing) esd::timing_event(P, s);
+  for (int b = 0; b < nb; ++b) {
+    const int rc = esd::launch_entropy_projection(P->sub[b], u + P->dof_off[b],
+                                                  split_ws(P->sub[b], (char*)ws + P->ws_off[b]), s);
+    if (rc != 0) return rc;
+  }
+  for (int b = 0; b < nb; ++b) {
+    const int rc = esd::launch_mixed_exterior(P->sub[b], P, (const double*)ws,
+                                              split_ws(P->sub[b], (char*)ws + P->ws_off[b]), s);
+    if (rc != 0) return rc;
+  }
+  if (P->timing) esd::timing_event(P, s);
+  for (int b = 0; b < nb; ++b) {
+    const int rc = esd::launch_rhs(P->sub[b], dudt + P->dof_off[b], split_ws(P->sub[b], (char*)ws + P->ws_off[b]), s);
+    if (rc != 0) return rc;
+  }
+  if (P->timing) esd::timing_event(P, s);
+  return 0;
+}
+
 esd_status esd_residual(const esd_plan* P, const double* u_dev, double* dudt_dev, void* ws_dev, void* stream) {
   esd_status st = check_device(P);
   if (st != ESD_OK) return st;
   if (!u_dev || !dudt_dev || !ws_dev) return fail(ESD_EINVAL, "NULL buffer");
   if ((const void*)u_dev == (const void*)dudt_dev) return fail(ESD_EINVAL, "u and dudt overlap");
   if (((uintptr_t)ws_dev) % 256 != 0) return fail(ESD_EINVAL, "workspace not 256-byte aligned");
-  const int rc = esd::launch_residual(P, u_dev, dudt_dev, split_ws(P, ws_dev), (hipStream_t)stream);
+  const int rc = residual_any(P, u_dev, dudt_dev, ws_dev, (hipStream_t)stream);
   if (rc < 0) return fail(ESD_EUNSUPPORTED, "degree not built");
   if (rc != 0) return fail(ESD_EHIP, std::string("launch failed: ") + hipGetErrorString((hipError_t)rc));
   return ESD_OK;
@@ -356,9 +683,8 @@ esd_status esd_rk4(const esd_plan* P, double* u_dev, double dt, int32_t nsteps, 
   if (!u_dev || !ws_dev || nsteps < 0 || !std::isfinite(dt)) return fail(ESD_EINVAL, "bad argument");
   if (((uintptr_t)ws_dev) % 256 != 0) return fail(ESD_EINVAL, "workspace not 256-byte aligned");
   hipStream_t s = (hipStream_t)stream;
-  const int64_t n = P->ne * P->nc * P->ref.NP;
+  const int64_t n = total_dof(P);
   const size_t nb = align256((size_t)n * sizeof(double));
-  esd::Workspace w = split_ws(P, ws_dev);
   double* k = (double*)((char*)ws_dev + P->ws_bytes);
   double* U = (double*)((char*)ws_dev + P->ws_bytes + nb);
   double* acc = (double*)((char*)ws_dev + P->ws_bytes + 2 * nb);
@@ -370,7 +696,7 @@ esd_status esd_rk4(const esd_plan* P, double* u_dev, double dt, int32_t nsteps, 
       if (stage_ckpt_dev)
         HIP_TRY(hipMemcpyAsync(stage_ckpt_dev + ((int64_t)4 * step + stg) * n, in, n * sizeof(double),
                                hipMemcpyDeviceToDevice, s));
-      int rc = esd::launch_residual(P, in, k, w, s);
+      int rc = residual_any(P, in, k, ws_dev, s);
       if (rc != 0) return fail(ESD_EHIP, "residual launch failed");
       if (stg < 3)
         rc = esd::launch_rk_stage(acc, U, u_dev, k, ca[stg], cu[stg], stg == 0, n, s);
@@ -390,6 +716,7 @@ esd_status esd_residual_vjp(const esd_plan* P, const double* u_dev, const double
   if ((const void*)grad_dev == (const void*)u_dev || (const void*)grad_dev == (const void*)vbar_dev)
     return fail(ESD_EINVAL, "grad overlaps u or vbar");
   if (((uintptr_t)ws_dev) % 256 != 0) return fail(ESD_EINVAL, "workspace not 256-byte aligned");
+  if (P->batched) return fail(ESD_EUNSUPPORTED, "VJP of a batched plan");
   if (!P->conn_involutive) return fail(ESD_EUNSUPPORTED, "facet permutation is not an involution");
   if (!esd::vjp_degree_supported(P->dim, P->p)) return fail(ESD_EUNSUPPORTED, "VJP not built for this degree");
   const int rc = esd::launch_vjp(P, u_dev, vbar_dev, grad_dev, split_ws(P, ws_dev), (hipStream_t)stream);
@@ -405,6 +732,7 @@ esd_status esd_rk4_vjp(const esd_plan* P, const double* stage_ckpt_dev, double d
   if (!stage_ckpt_dev || !ubar_dev || !ws_dev || nsteps < 0 || !std::isfinite(dt))
     return fail(ESD_EINVAL, "bad argument");
   if (((uintptr_t)ws_dev) % 256 != 0) return fail(ESD_EINVAL, "workspace not 256-byte aligned");
+  if (P->batched) return fail(ESD_EUNSUPPORTED, "VJP of a batched plan");
   if (!P->conn_involutive) return fail(ESD_EUNSUPPORTED, "facet permutation is not an involution");
   if (!esd::vjp_degree_supported(P->dim, P->p)) return fail(ESD_EUNSUPPORTED, "VJP not built for this degree");
   hipStream_t s = (hipStream_t)stream;
@@ -440,18 +768,32 @@ esd_status esd_diagnostics(const esd_plan* P, const double* u_dev, double* out_h
   if (!u_dev || !out_host || !ws_dev) return fail(ESD_EINVAL, "NULL buffer");
   if (((uintptr_t)ws_dev) % 256 != 0) return fail(ESD_EINVAL, "workspace not 256-byte aligned");
   hipStream_t s = (hipStream_t)stream;
-  const int64_t n = P->ne * P->nc * P->ref.NP;
+  const int64_t n = total_dof(P);
   const size_t nb = align256((size_t)n * sizeof(double));
-  // residual workspace, then du~/dt, then the partial sums and the result
+  const int no = P->nc + 2;
+  // residual workspace, then du~/dt, then the partial sums and the results
   double* dudt = (double*)((char*)ws_dev + P->ws_bytes);
   double* part = (double*)((char*)ws_dev + P->ws_bytes + nb);
-  double* res = part + P->ne * (P->nc + 2);
-  int rc = esd::launch_residual(P, u_dev, dudt, split_ws(P, ws_dev), s);
-  if (rc == 0) rc = esd::launch_diagnostics(P, u_dev, dudt, part, res, s);
+  double* res = part + P->ne * no;
+  int rc = residual_any(P, u_dev, dudt, ws_dev, s);
+  const int nbk = P->batched ? (int)P->sub.size() : 1;
+  int64_t eoff = 0;
+  for (int b = 0; b < nbk && rc == 0; ++b) {
+    const esd_plan* B = P->batched ? P->sub[b] : P;
+    const int64_t doff = P->batched ? P->dof_off[b] : 0;
+    rc = esd::launch_diagnostics(B, u_dev + doff, dudt + doff, part + eoff * no, res + b * no, s);
+    eoff += B->ne;
+  }
   if (rc < 0) return fail(ESD_EUNSUPPORTED, "degree not built");
   if (rc != 0) return fail(ESD_EHIP, std::string("diagnostics launch failed: ") + hipGetErrorString((hipError_t)rc));
-  HIP_TRY(hipMemcpyAsync(out_host, res, (P->nc + 2) * sizeof(double), hipMemcpyDeviceToHost, s));
+  std::vector<double> h((size_t)nbk * no);
+  HIP_TRY(hipMemcpyAsync(h.data(), res, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
+  for (int c = 0; c < no; ++c) {
+    double acc = 0.0;
+    for (int b = 0; b < nbk; ++b) acc += h[(size_t)b * no + c];
+    out_host[c] = acc;
+  }
   return ESD_OK;
 }
 

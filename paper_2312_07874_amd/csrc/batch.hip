@@ -1,0 +1,45 @@
+// Exterior facet values across interfaces between elements of different
+// degree (gfx950, FP64).
+//
+// Each task is one facet of an element whose neighbour has another degree:
+//   w+[c][j] = sum_k I[j][k] w~_nb[c][k],   j < NQF (this degree), k < NP (neighbour's),
+// I the neighbour's PKD basis at the reference points of this facet's nodes
+// (built on the host).  The result lands in the element's exterior slot, laid
+// out like its own facet values, where the right-hand-side kernel reads it
+// through the facet permutation table like any other neighbour value.
+#include <hip/hip_runtime.h>
+
+#include "device.hpp"
+
+namespace esd {
+
+// task layout, int32 [8]: slot, face, neighbour bucket, neighbour slot, matrix,
+// unused, neighbour NP, unused
+__global__ void __launch_bounds__(128)
+k_mixed_exterior(const int32_t* __restrict__ tasks, const double* __restrict__ ws_base,
+                 const int64_t* __restrict__ wt_off, const double* __restrict__ mats,
+                 const int64_t* __restrict__ mat_off, double* __restrict__ wext, int nc, int nfq, int nqf) {
+  const int32_t* t = tasks + 8 * (int64_t)blockIdx.x;
+  const int slot = t[0], face = t[1], nbb = t[2], nbs = t[3], mat = t[4], np = t[6];
+  const double* wtn = ws_base + wt_off[nbb] + (int64_t)nbs * nc * np;
+  const double* I = mats + mat_off[mat];
+  double* dst = wext + (int64_t)slot * nc * nfq + face * nqf;
+  for (int o = threadIdx.x; o < nc * nqf; o += blockDim.x) {
+    const int c = o / nqf, j = o % nqf;
+    double acc = 0.0;
+    for (int k = 0; k < np; ++k) acc += I[j * np + k] * wtn[c * np + k];
+    dst[c * nfq + j] = acc;
+  }
+}
+
+int launch_mixed_exterior(const esd_plan* b, const esd_plan* top, const double* ws_base, Workspace ws,
+                          hipStream_t s) {
+  if (b->n_tasks == 0) return 0;
+  const int nfq = b->ref.NFQ, nqf = b->ref.NQF;
+  double* wext = ws.wf + b->ne * b->nc * nfq;
+  hipLaunchKernelGGL(k_mixed_exterior, dim3((unsigned)b->n_tasks), dim3(128), 0, s, b->d_tasks, ws_base,
+                     top->d_wt_off, top->d_mats, top->d_mat_off, wext, b->nc, nfq, nqf);
+  return (int)hipGetLastError();
+}
+
+}  // namespace esd

@@ -447,6 +447,16 @@ static Interp lagrange_to(int dim, int N, const std::vector<double>& X) {
   return I;
 }
 
+void facet_point(int dim, int face, double s, double t, double* xi) {
+  if (dim == 2) {
+    const double e[3][2] = {{s, -1.0}, {1.0, s}, {-1.0, s}};
+    chi(2, e[face], xi);
+  } else {
+    const double e[4][3] = {{s, -1.0, t}, {1.0, s, t}, {-1.0, s, t}, {s, t, -1.0}};
+    chi(3, e[face], xi);
+  }
+}
+
 // ============================================================ geometry
 static const int FACET_VERTS[2][4][3] = {
     {{0, 1, -1}, {1, 2, -1}, {0, 2, -1}, {-1, -1, -1}},
@@ -462,7 +472,7 @@ static double det(int dim, const double* A /* [c][m] */) {
 }
 
 int build_geometry(const RefTables& ref, int64_t ne, const int64_t* ids, const double* coords,
-                   warp_fn warp, void* ctx, HostGeometry& out, std::string& msg) {
+                   warp_fn warp, void* ctx, HostGeometry& out, std::string& msg, bool connect) {
   const int dim = ref.dim, p = ref.p, NQ = ref.NQ, NF = ref.NF, NQF = ref.NQF, NFQ = ref.NFQ;
   const int nv = dim + 1;
   out = HostGeometry();
@@ -698,6 +708,7 @@ int build_geometry(const RefTables& ref, int64_t ne, const int64_t* ids, const d
       msg = "mapping Jacobian not positive in element " + std::to_string(e);
       return -2;  // ESD_EJACOBIAN
     }
+  if (!connect) return 0;
   // ---- connectivity: match facets by their sorted global vertex ids
   const int di = dim - 2;
   std::map<std::array<int64_t, 3>, std::vector<std::pair<int64_t, int>>> table;

@@ -44,6 +44,10 @@ struct RefTables {
   std::vector<int32_t> mode_a;               // [NP][3] multi-indices
 };
 RefTables build_ref_tables(int dim, int p);
+// Reference point of facet `face` at facet coordinates (s, t): s along the
+// facet's Legendre direction, t (tetrahedra) the Gauss-Jacobi direction
+// towards the facet's collapse vertex; the facet nodes are (xl[a], xj[b]).
+void facet_point(int dim, int face, double s, double t, double* xi);
 
 // PKD basis and gradient at reference points (Sec. 4.3).
 int n_modes(int dim, int p);
@@ -63,8 +67,10 @@ struct HostGeometry {
 
 typedef void (*warp_fn)(int64_t n, const double* xin, double* xout, void* ctx);
 
-// Returns 0 or a negative esd_status; msg receives a description.
+// Returns 0 or a negative esd_status; msg receives a description.  With
+// connect = false the facet connectivity (nbr) is not built (elements of one
+// degree out of a mixed-degree mesh).
 int build_geometry(const RefTables& ref, int64_t ne, const int64_t* ids, const double* coords,
-                   warp_fn warp, void* ctx, HostGeometry& out, std::string& msg);
+                   warp_fn warp, void* ctx, HostGeometry& out, std::string& msg, bool connect = true);
 
 }  // namespace esd

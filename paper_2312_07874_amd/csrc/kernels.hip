@@ -397,7 +397,7 @@ __global__ void k_axpy(double* __restrict__ y, const double* __restrict__ x, dou
 }
 
 // ------------------------------------------------------------------ dispatch
-static hipEvent_t timing_event(const esd_plan* pl, hipStream_t s) {
+hipEvent_t timing_event(const esd_plan* pl, hipStream_t s) {
   hipEvent_t e;
   if (!pl->ev_pool.empty()) {
     e = pl->ev_pool.back();
@@ -425,6 +425,19 @@ static int run_residual(const esd_plan* pl, const double* u, double* dudt, Works
     hipLaunchKernelGGL((k_rhs<DIM, P, FLUX_CHANDRASHEKAR>), dim3(nb), dim3(L::BS), 0, s, ws.wt, ws.wf, dudt,
                        pl->d_gvol, pl->d_gfac, pl->d_conn, pl->tab, pl->scheme, pl->ne, pl->d_flag, ws.frec);
   if (pl->timing) timing_event(pl, s);
+  return (int)hipGetLastError();
+}
+
+template <int DIM, int P>
+static int run_rhs(const esd_plan* pl, double* dudt, Workspace ws, hipStream_t s) {
+  using L = Launch<DIM, P>;
+  const int64_t nb = (pl->ne + L::EPB - 1) / L::EPB;
+  if (pl->scheme.ecflux == FLUX_RANOCHA)
+    hipLaunchKernelGGL((k_rhs<DIM, P, FLUX_RANOCHA>), dim3(nb), dim3(L::BS), 0, s, ws.wt, ws.wf, dudt, pl->d_gvol,
+                       pl->d_gfac, pl->d_conn, pl->tab, pl->scheme, pl->ne, pl->d_flag, ws.frec);
+  else
+    hipLaunchKernelGGL((k_rhs<DIM, P, FLUX_CHANDRASHEKAR>), dim3(nb), dim3(L::BS), 0, s, ws.wt, ws.wf, dudt,
+                       pl->d_gvol, pl->d_gfac, pl->d_conn, pl->tab, pl->scheme, pl->ne, pl->d_flag, ws.frec);
   return (int)hipGetLastError();
 }
 
@@ -476,6 +489,15 @@ int launch_entropy_projection(const esd_plan* pl, const double* u, Workspace ws,
                        pl->d_gvol, pl->tab, pl->scheme, pl->ne, pl->d_flag);                                  \
     return (int)hipGetLastError();                                                                            \
   }
+  ESD_TRI_DEGREES(X)
+  ESD_TET_DEGREES(X)
+#undef X
+  return -1;
+}
+
+int launch_rhs(const esd_plan* pl, double* dudt, Workspace ws, hipStream_t s) {
+#define X(D, PP) \
+  if (pl->dim == D && pl->p == PP) return run_rhs<D, PP>(pl, dudt, ws, s);
   ESD_TRI_DEGREES(X)
   ESD_TET_DEGREES(X)
 #undef X

@@ -72,6 +72,7 @@ struct esd_plan {
   int32_t* d_conn = nullptr;
   double* d_xvol = nullptr;
   int* d_flag = nullptr;
+  bool flag_owned = true;         // false for buckets sharing the batched plan's flag
   size_t ws_bytes = 0;
   size_t frec_bytes = 0;          // tail of the residual workspace holding Workspace::frec
   size_t rk_ws_bytes = 0;
@@ -79,6 +80,23 @@ struct esd_plan {
   size_t rk_vjp_ws_bytes = 0;
   bool conn_involutive = false;   // facet permutation pairs nodes both ways (needed by the VJP gather)
   // measurement: events bracketing each K1 / K2 launch (mutable: recorded by const calls)
+  // mixed-degree batches: elements of this degree out of several meshes; the
+  // facet-state region of the workspace holds 2 ne slots (own values, then the
+  // exterior values of facets whose neighbour has another degree)
+  bool wext = false;
+  int32_t* d_tasks = nullptr;     // [n_tasks][8] mixed-interface tasks (see batch.hip)
+  int64_t n_tasks = 0;
+  // batched plan: container of one single-degree plan per bucket
+  bool batched = false;
+  std::vector<esd_plan*> sub;
+  std::vector<int64_t> dof_off;   // [nb+1] offsets of the buckets in the state (doubles)
+  std::vector<int64_t> node_off;  // [nb+1] offsets in volume nodes
+  std::vector<size_t> ws_off;     // [nb] residual workspace slice of each bucket (bytes)
+  std::vector<int32_t> elem_bucket;   // per input element (meshes concatenated)
+  std::vector<int64_t> elem_slot;
+  double* d_mats = nullptr;       // mixed-interface evaluation matrices
+  int64_t* d_mat_off = nullptr;   // [n_mats] offsets into d_mats
+  int64_t* d_wt_off = nullptr;    // [nb] offsets (doubles) of each bucket's w~ in the workspace
   bool timing = false;
   mutable std::vector<hipEvent_t> ev;       // triples: before K1, between, after K2
   mutable std::vector<hipEvent_t> ev_pool;
@@ -99,6 +117,12 @@ int launch_vjp(const esd_plan* P, const double* u, const double* vbar, double* g
 int launch_adj_stage(double* acc, double* kb, const double* ubar, const double* G, double cu, double cg, int first,
                      int64_t n, hipStream_t s);
 int launch_scale(double* y, const double* x, double a, int64_t n, hipStream_t s);
+// K2 alone (K1 must have run for every element whose facet values it reads)
+int launch_rhs(const esd_plan* P, double* dudt, Workspace ws, hipStream_t s);
+// batch.hip: exterior facet values of mixed-degree interfaces of one bucket
+int launch_mixed_exterior(const esd_plan* bucket, const esd_plan* top, const double* ws_base, Workspace ws,
+                          hipStream_t s);
+hipEvent_t timing_event(const esd_plan* pl, hipStream_t s);
 // diagnostics.hip: part [ne][dim+4] partial sums, out [dim+4] (device)
 int launch_diagnostics(const esd_plan* P, const double* u, const double* dudt, double* part, double* out,
                        hipStream_t s);

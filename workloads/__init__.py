@@ -248,3 +248,30 @@ def random_tri(M=4, degree=3, seed=7, dissipation=1, L=2.0) -> Workload:
 def mixed_degrees(n_elements: int, seed: int, lo: int = 2, hi: int = 10) -> np.ndarray:
     rng = np.random.default_rng(seed)
     return rng.integers(lo, hi + 1, size=n_elements).astype(np.int32)
+
+
+@dataclass
+class Batch:
+    """Several independent meshes with per-element degrees."""
+    name: str
+    dim: int
+    meshes: list          # [Mesh]
+    degrees: list         # [np.ndarray int32 per mesh]
+    L: float
+    warp: Callable
+    state: Callable
+    ecflux: int = 0
+    dissipation: int = 1
+    gamma: float = GAMMA
+
+
+def batched_tets(Ms=(8, 10, 12, 14), lo=2, hi=10, seed=20231213) -> Batch:
+    """Periodic [0,2pi]^3 meshes of 6 M^3 curved tetrahedra, element degrees
+    uniform on {lo..hi} from one seeded generator, random smooth Euler state
+    (rho, p in [0.8, 1.2], |v| < 0.3), Ranocha flux with LF dissipation."""
+    L = 2.0 * math.pi
+    rng = np.random.default_rng(seed)
+    meshes = [split_box_mesh(3, M, L) for M in Ms]
+    degs = [rng.integers(lo, hi + 1, size=m.n_elements).astype(np.int32) for m in meshes]
+    name = f"batched_tets_M{'-'.join(str(M) for M in Ms)}_p{lo}-{hi}"
+    return Batch(name, 3, meshes, degs, L, make_warp_sinprod(L, 0.05), RandomSmooth(3, L, seed))
