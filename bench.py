@@ -58,6 +58,7 @@ def run_gpu(name: str, steps: int, warmup: int):
     x = plan.node_coords().cpu().numpy()
     u = plan.project(torch.tensor(wk.state(x), device="cuda").contiguous())
     plan.sync_status()
+    blocks = plan.autotune(u)
     dt = 1e-4
     for _ in range(warmup):
         plan.rk4(u, dt, 1)
@@ -94,6 +95,7 @@ def run_gpu(name: str, steps: int, warmup: int):
     roof["algorithmic_bytes_per_launch"] = by
     roof["avg_launch_ms"] = k2_avg_s * 1e3
     vjp = time_vjp(plan, u)
+    graph_ms = time_graph_steps(plan, u, dt, steps)
     return {
         "workload": name,
         "elements": info.n_elements,
@@ -109,7 +111,23 @@ def run_gpu(name: str, steps: int, warmup: int):
         "roofline": roof,
         "k1_flop_rate_tflops": pm.k1_flops(d, p) * info.n_elements / k1_avg_s / 1e12,
         "vjp": vjp,
+        "k2_block_autotuned": blocks[0],
+        "ms_per_step_graph": graph_ms,
     }
+
+
+def time_graph_steps(plan, u, dt, steps):
+    """The same RK4 steps replayed from the captured graph (no per-kernel events)."""
+    import torch
+
+    plan.rk4(u, dt, 1)            # capture
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.rk4(u, dt, steps)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    plan.sync_status()
+    return ms
 
 
 def time_vjp(plan, u, reps: int = 5):
@@ -137,6 +155,55 @@ def time_vjp(plan, u, reps: int = 5):
     f = ev[0].elapsed_time(ev[1]) / reps
     b = ev[2].elapsed_time(ev[3]) / reps
     return {"residual_ms": f, "vjp_ms": b, "vjp_over_forward": b / f}
+
+
+def run_batched(steps: int, warmup: int):
+    """Four periodic tetrahedral meshes (6 M^3 elements, M = 8, 10, 12, 14) with
+    per-element degrees uniform on 2..10 in one batched plan."""
+    import torch
+
+    import paper_2312_07874_amd as esd
+
+    bt = wl.batched_tets()
+    t0 = time.perf_counter()
+    plan = esd.BatchedPlan(3, [(m.elem_vertex_ids, m.elem_vertex_coords, d) for m, d in zip(bt.meshes, bt.degrees)],
+                           bt.warp, bt.gamma, bt.ecflux, bt.dissipation)
+    log(f"[bench] {bt.name}: plan {plan.info.n_elements} elements in {len(plan.buckets)} buckets, "
+        f"{plan.info.n_dof} DOF, setup {time.perf_counter() - t0:.1f}s")
+    x = plan.node_coords().cpu().numpy()
+    u = plan.project(torch.tensor(bt.state(x), device="cuda").reshape(plan.nodal_shape).contiguous())
+    plan.sync_status()
+    blocks = plan.autotune(u)
+    dt = 1e-4
+    for _ in range(warmup):
+        plan.rk4(u, dt, 1)
+    torch.cuda.synchronize()
+    plan.set_timing(True)
+    plan.get_timing()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.rk4(u, dt, 1)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    plan.set_timing(False)
+    k1_ms, k2_ms, nres = plan.get_timing()
+    plan.sync_status()
+    graph_ms = time_graph_steps(plan, u, dt, steps)
+    n_res = 4 * steps
+    return {
+        "workload": bt.name,
+        "elements": int(plan.info.n_elements),
+        "dof": int(plan.info.n_dof),
+        "buckets": [[b["degree"], int(b["n_elements"])] for b in plan.buckets],
+        "value": n_res * plan.info.n_dof / elapsed,
+        "ms_per_step": elapsed / steps * 1e3,
+        "ms_per_residual_k1_k2": (k1_ms + k2_ms) / nres,
+        "k1_and_interfaces_avg_ms": k1_ms / nres,
+        "k2_all_buckets_avg_ms": k2_ms / nres,
+        "flux_pairs_per_s": n_res * plan.info.flux_pairs_paper / elapsed,
+        "k2_blocks_autotuned": blocks,
+        "ms_per_step_graph": graph_ms,
+    }
 
 
 def cpu_baseline(name: str, budget_s: float):
@@ -176,6 +243,7 @@ def main():
     ap.add_argument("--extra", default="vortex_tri_M64_p8,tgv_tet_M16_p4,tgv_tet_M16_p6",
                     help="comma-separated additional workloads reported under 'extra' ('' for none)")
     ap.add_argument("--extra-steps", type=int, default=3)
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched mixed-degree workload")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -188,6 +256,8 @@ def main():
     for name in [s for s in args.extra.split(",") if s]:
         if name != args.workload:
             extra.append(run_gpu(name, args.extra_steps, 1))
+    if not args.no_batched:
+        extra.append(run_batched(args.extra_steps, 1))
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.workload, args.cpu_seconds)
     out = {
         "metric": METRIC,
@@ -208,6 +278,7 @@ def main():
         "flux_pairs_per_s": main_res["flux_pairs_per_s"],
         "flux_pairs_distinct_per_s": main_res["flux_pairs_distinct_per_s"],
         "ms_per_residual_k1_k2": main_res["ms_per_residual_k1_k2"],
+        "ms_per_step_graph": main_res["ms_per_step_graph"],
         "roofline": main_res["roofline"],
         "vjp_over_forward": main_res["vjp"]["vjp_over_forward"],
         "vjp": main_res["vjp"],

@@ -189,6 +189,21 @@ esd_status esd_residual(const esd_plan* plan, const double* u_dev, double* dudt_
 esd_status esd_rk4(const esd_plan* plan, double* u_dev, double dt, int32_t nsteps,
                    void* ws_dev, double* stage_ckpt_dev, void* stream);
 
+/* RK4 execution: without checkpoints and with timing off, esd_rk4 captures one
+ * step (every residual launch and stage combination) into a HIP graph on the
+ * plan's own stream at the first call for a given (u_dev, ws_dev, dt), and
+ * replays it nsteps times, ordered after the caller's stream by events.
+ * esd_plan_set_graphs(plan, 0) launches every kernel individually instead. */
+esd_status esd_plan_set_graphs(esd_plan* plan, int32_t enable);
+
+/* Chooses the block size of the right-hand-side kernel for every bucket by
+ * timing the candidates (multiples of 64 up to its compiled bound) on the state
+ * u_dev; ws_dev holds info.rk4_workspace_bytes.  Synchronises.  The choice is
+ * kept by the plan and reported by esd_plan_get_tuning (k2_block[bucket],
+ * capacity entries available). */
+esd_status esd_plan_autotune(esd_plan* plan, const double* u_dev, void* ws_dev, void* stream);
+esd_status esd_plan_get_tuning(const esd_plan* plan, int32_t* k2_block, int32_t capacity);
+
 /* Vector-Jacobian product of the semi-discrete right-hand side (the adjoint of
  * esd_residual, differentiating eqs. entropy_expansion, entropy_stable,
  * facet_correction, num_flux and dudt_modal exactly, including the interface

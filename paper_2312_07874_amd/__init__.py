@@ -85,6 +85,9 @@ EXPORTS = {
     "esd_rk4_vjp": (_c, [_vp, _vp, ctypes.c_double, ctypes.c_int32, _vp, _vp, _vp]),
     "esd_diagnostics": (_c, [_vp, _vp, ctypes.POINTER(ctypes.c_double), _vp, _vp]),
     "esd_sync_status": (_c, [_vp, _vp]),
+    "esd_plan_set_graphs": (_c, [_vp, ctypes.c_int32]),
+    "esd_plan_autotune": (_c, [_vp, _vp, _vp, _vp]),
+    "esd_plan_get_tuning": (_c, [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]),
     "esd_plan_set_timing": (_c, [_vp, ctypes.c_int32]),
     "esd_plan_get_timing": (_c, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                  ctypes.POINTER(ctypes.c_int64)]),
@@ -250,6 +253,22 @@ class Plan:
                                     _ptr(self.workspace("rk4")), _stream()), "esd_diagnostics")
         nc = self.dim + 2
         return {"conserved": out[:nc].copy(), "entropy": float(out[nc]), "entropy_rate": float(out[nc + 1])}
+
+    def set_graphs(self, enable: bool):
+        _check(_lib.esd_plan_set_graphs(self._h, 1 if enable else 0), "esd_plan_set_graphs")
+
+    def autotune(self, u):
+        """Times the right-hand-side block-size candidates of every bucket on u
+        and keeps the fastest; returns the chosen block sizes."""
+        assert u.is_contiguous() and tuple(u.shape) == self.state_shape
+        _check(_lib.esd_plan_autotune(self._h, _ptr(u), _ptr(self.workspace("rk4")), _stream()), "esd_plan_autotune")
+        return self.tuning()
+
+    def tuning(self):
+        out = (ctypes.c_int32 * 16)()
+        _check(_lib.esd_plan_get_tuning(self._h, out, 16), "esd_plan_get_tuning")
+        n = len(getattr(self, "buckets", [None]))
+        return [out[b] for b in range(n)]
 
     def set_timing(self, enable: bool):
         _check(_lib.esd_plan_set_timing(self._h, 1 if enable else 0), "esd_plan_set_timing")

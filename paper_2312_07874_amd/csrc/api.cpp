@@ -382,8 +382,11 @@ esd_status esd_plan_create_batched(const esd_batch_desc* d, const esd_scheme_des
             // the neighbour's PKD basis at the reference points of this degree's
             // facet nodes, carried across the shared facet (reversed Legendre
             // coordinate when the orientations differ)
+            // stored transposed, [k][j]
             const int npn = esd::n_modes(dim, pn);
-            mat_off.push_back((int64_t)mats.size());
+            const size_t base = mats.size();
+            mat_off.push_back((int64_t)base);
+            mats.resize(base + (size_t)npn * NQF);
             std::vector<double> row(npn);
             for (int j = 0; j < NQF; ++j) {
               const int a1 = j % Q, a2 = j / Q;
@@ -392,7 +395,7 @@ esd_status esd_plan_create_batched(const esd_batch_desc* d, const esd_scheme_des
               double xi[3];
               esd::facet_point(dim, fn, sc, tc, xi);
               esd::pkd_eval(dim, pn, xi, 1, row.data());
-              mats.insert(mats.end(), row.begin(), row.end());
+              for (int k = 0; k < npn; ++k) mats[base + (size_t)k * NQF + j] = row[k];
             }
             it = matid.emplace(key, (int)mat_off.size() - 1).first;
           }
@@ -485,6 +488,10 @@ esd_status esd_plan_element_map(const esd_plan* P, int32_t* bucket, int64_t* slo
 void esd_plan_destroy(esd_plan* plan) {
   if (!plan) return;
   for (esd_plan* b : plan->sub) esd_plan_destroy(b);
+  for (auto& g : plan->graphs) (void)hipGraphExecDestroy(g.exec);
+  if (plan->gev[0]) (void)hipEventDestroy(plan->gev[0]);
+  if (plan->gev[1]) (void)hipEventDestroy(plan->gev[1]);
+  if (plan->gstream) (void)hipStreamDestroy(plan->gstream);
   for (hipEvent_t e : plan->ev) (void)hipEventDestroy(e);
   for (hipEvent_t e : plan->ev_pool) (void)hipEventDestroy(e);
   free_device(plan);
@@ -676,13 +683,8 @@ esd_status esd_residual(const esd_plan* P, const double* u_dev, double* dudt_dev
   return ESD_OK;
 }
 
-esd_status esd_rk4(const esd_plan* P, double* u_dev, double dt, int32_t nsteps, void* ws_dev,
-                   double* stage_ckpt_dev, void* stream) {
-  esd_status st = check_device(P);
-  if (st != ESD_OK) return st;
-  if (!u_dev || !ws_dev || nsteps < 0 || !std::isfinite(dt)) return fail(ESD_EINVAL, "bad argument");
-  if (((uintptr_t)ws_dev) % 256 != 0) return fail(ESD_EINVAL, "workspace not 256-byte aligned");
-  hipStream_t s = (hipStream_t)stream;
+// one RK4 step: four residual evaluations and stage combinations
+static int rk4_step(const esd_plan* P, double* u_dev, double dt, void* ws_dev, double* ckpt, hipStream_t s) {
   const int64_t n = total_dof(P);
   const size_t nb = align256((size_t)n * sizeof(double));
   double* k = (double*)((char*)ws_dev + P->ws_bytes);
@@ -690,20 +692,150 @@ esd_status esd_rk4(const esd_plan* P, double* u_dev, double dt, int32_t nsteps, 
   double* acc = (double*)((char*)ws_dev + P->ws_bytes + 2 * nb);
   const double ca[4] = {dt / 6.0, dt / 3.0, dt / 3.0, dt / 6.0};
   const double cu[4] = {0.5 * dt, 0.5 * dt, dt, 0.0};
-  for (int step = 0; step < nsteps; ++step) {
-    for (int stg = 0; stg < 4; ++stg) {
-      const double* in = (stg == 0) ? u_dev : U;
-      if (stage_ckpt_dev)
-        HIP_TRY(hipMemcpyAsync(stage_ckpt_dev + ((int64_t)4 * step + stg) * n, in, n * sizeof(double),
-                               hipMemcpyDeviceToDevice, s));
-      int rc = residual_any(P, in, k, ws_dev, s);
-      if (rc != 0) return fail(ESD_EHIP, "residual launch failed");
-      if (stg < 3)
-        rc = esd::launch_rk_stage(acc, U, u_dev, k, ca[stg], cu[stg], stg == 0, n, s);
-      else
-        rc = esd::launch_axpy(u_dev, acc, ca[3], k, n, s);
-      if (rc != 0) return fail(ESD_EHIP, "stage launch failed");
+  for (int stg = 0; stg < 4; ++stg) {
+    const double* in = (stg == 0) ? u_dev : U;
+    if (ckpt) {
+      const hipError_t e = hipMemcpyAsync(ckpt + (int64_t)stg * n, in, n * sizeof(double), hipMemcpyDeviceToDevice, s);
+      if (e != hipSuccess) return (int)e;
     }
+    int rc = residual_any(P, in, k, ws_dev, s);
+    if (rc != 0) return rc;
+    if (stg < 3)
+      rc = esd::launch_rk_stage(acc, U, u_dev, k, ca[stg], cu[stg], stg == 0, n, s);
+    else
+      rc = esd::launch_axpy(u_dev, acc, ca[3], k, n, s);
+    if (rc != 0) return rc;
+  }
+  return 0;
+}
+
+// the instantiated graph of one RK4 step for (u, ws, dt), captured on the
+// plan's own stream at first use
+static esd_status step_graph(esd_plan* P, double* u_dev, double dt, void* ws_dev, hipGraphExec_t* exec) {
+  for (const auto& g : P->graphs)
+    if (g.u == u_dev && g.ws == ws_dev && g.dt == dt) {
+      *exec = g.exec;
+      return ESD_OK;
+    }
+  if (!P->gstream) {
+    HIP_TRY(hipStreamCreateWithFlags(&P->gstream, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&P->gev[0], hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&P->gev[1], hipEventDisableTiming));
+  }
+  hipGraph_t graph = nullptr;
+  HIP_TRY(hipStreamBeginCapture(P->gstream, hipStreamCaptureModeThreadLocal));
+  const int rc = rk4_step(P, u_dev, dt, ws_dev, nullptr, P->gstream);
+  const hipError_t ec = hipStreamEndCapture(P->gstream, &graph);
+  if (rc != 0 || ec != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return fail(ESD_EHIP, "graph capture failed");
+  }
+  hipGraphExec_t ex = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ei != hipSuccess) return fail(ESD_EHIP, std::string("graph instantiation: ") + hipGetErrorString(ei));
+  if (P->graphs.size() >= 8) {
+    (void)hipGraphExecDestroy(P->graphs.front().exec);
+    P->graphs.erase(P->graphs.begin());
+  }
+  P->graphs.push_back({u_dev, ws_dev, dt, ex});
+  *exec = ex;
+  return ESD_OK;
+}
+
+esd_status esd_rk4(const esd_plan* Pc, double* u_dev, double dt, int32_t nsteps, void* ws_dev,
+                   double* stage_ckpt_dev, void* stream) {
+  esd_status st = check_device(Pc);
+  if (st != ESD_OK) return st;
+  if (!u_dev || !ws_dev || nsteps < 0 || !std::isfinite(dt)) return fail(ESD_EINVAL, "bad argument");
+  if (((uintptr_t)ws_dev) % 256 != 0) return fail(ESD_EINVAL, "workspace not 256-byte aligned");
+  esd_plan* P = const_cast<esd_plan*>(Pc);   // graph cache only
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t n = total_dof(P);
+  if (!stage_ckpt_dev && !P->timing && P->use_graphs && nsteps > 0) {
+    hipGraphExec_t ex = nullptr;
+    st = step_graph(P, u_dev, dt, ws_dev, &ex);
+    if (st != ESD_OK) return st;
+    // order the replays after the caller's stream and the caller's later work after them
+    HIP_TRY(hipEventRecord(P->gev[0], s));
+    HIP_TRY(hipStreamWaitEvent(P->gstream, P->gev[0], 0));
+    for (int step = 0; step < nsteps; ++step) HIP_TRY(hipGraphLaunch(ex, P->gstream));
+    HIP_TRY(hipEventRecord(P->gev[1], P->gstream));
+    HIP_TRY(hipStreamWaitEvent(s, P->gev[1], 0));
+    return ESD_OK;
+  }
+  for (int step = 0; step < nsteps; ++step) {
+    const int rc = rk4_step(P, u_dev, dt, ws_dev, stage_ckpt_dev ? stage_ckpt_dev + (int64_t)4 * step * n : nullptr, s);
+    if (rc < 0) return fail(ESD_EUNSUPPORTED, "degree not built");
+    if (rc != 0) return fail(ESD_EHIP, std::string("RK4 launch failed: ") + hipGetErrorString((hipError_t)rc));
+  }
+  return ESD_OK;
+}
+
+esd_status esd_plan_set_graphs(esd_plan* P, int32_t enable) {
+  if (!P) return fail(ESD_EINVAL, "plan is NULL");
+  P->use_graphs = enable != 0;
+  return ESD_OK;
+}
+
+// K2 block size per bucket, timed on the given state: the full residual once
+// (facet values of every bucket), then each candidate launch of each bucket's
+// right-hand side three times after one warm-up; the fastest is kept.
+esd_status esd_plan_autotune(esd_plan* P, const double* u_dev, void* ws_dev, void* stream) {
+  esd_status st = check_device(P);
+  if (st != ESD_OK) return st;
+  if (!u_dev || !ws_dev) return fail(ESD_EINVAL, "NULL buffer");
+  if (((uintptr_t)ws_dev) % 256 != 0) return fail(ESD_EINVAL, "workspace not 256-byte aligned");
+  hipStream_t s = (hipStream_t)stream;
+  double* dudt = (double*)((char*)ws_dev + P->ws_bytes);   // inside the RK4 workspace
+  const bool timing = P->timing;
+  P->timing = false;
+  int rc = residual_any(P, u_dev, dudt, ws_dev, s);
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  const int nbk = P->batched ? (int)P->sub.size() : 1;
+  for (int b = 0; b < nbk && rc == 0; ++b) {
+    esd_plan* B = P->batched ? P->sub[b] : P;
+    void* wsb = P->batched ? (char*)ws_dev + P->ws_off[b] : ws_dev;
+    double* out = dudt + (P->batched ? P->dof_off[b] : 0);
+    float best = 1e30f;
+    int best_bs = 0;
+    for (int bs : esd::rhs_block_candidates(B->dim, B->p)) {
+      B->k2_block = bs;
+      rc = esd::launch_rhs(B, out, split_ws(B, wsb), s);
+      if (rc != 0) break;
+      HIP_TRY(hipEventRecord(e0, s));
+      for (int r = 0; r < 3 && rc == 0; ++r) rc = esd::launch_rhs(B, out, split_ws(B, wsb), s);
+      HIP_TRY(hipEventRecord(e1, s));
+      HIP_TRY(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best) {
+        best = ms;
+        best_bs = bs;
+      }
+    }
+    B->k2_block = best_bs;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  P->timing = timing;
+  // graphs captured before the change keep the old launch shape
+  for (auto& g : P->graphs) (void)hipGraphExecDestroy(g.exec);
+  P->graphs.clear();
+  if (rc < 0) return fail(ESD_EUNSUPPORTED, "degree not built");
+  if (rc != 0) return fail(ESD_EHIP, std::string("autotune launch failed: ") + hipGetErrorString((hipError_t)rc));
+  return ESD_OK;
+}
+
+esd_status esd_plan_get_tuning(const esd_plan* P, int32_t* k2_block, int32_t capacity) {
+  if (!P || !k2_block) return fail(ESD_EINVAL, "NULL argument");
+  const int nbk = P->batched ? (int)P->sub.size() : 1;
+  if (capacity < nbk) return fail(ESD_EINVAL, "capacity below the number of buckets");
+  for (int b = 0; b < nbk; ++b) {
+    const esd_plan* B = P->batched ? P->sub[b] : P;
+    k2_block[b] = B->k2_block > 0 ? B->k2_block : esd::rhs_block_candidates(B->dim, B->p)[0];
   }
   return ESD_OK;
 }

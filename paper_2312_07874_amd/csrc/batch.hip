@@ -14,21 +14,31 @@
 namespace esd {
 
 // task layout, int32 [8]: slot, face, neighbour bucket, neighbour slot, matrix,
-// unused, neighbour NP, unused
+// unused, neighbour NP, unused.  Matrices are stored transposed, I^T [k][j], so
+// that the threads of a task (one per facet node j) read consecutive words;
+// the neighbour's w~ (at most 5 x 286 values) is staged in LDS.
+constexpr int MIX_MAX_NP = 286;   // PKD modes of a degree-10 tetrahedron
+
 __global__ void __launch_bounds__(128)
 k_mixed_exterior(const int32_t* __restrict__ tasks, const double* __restrict__ ws_base,
                  const int64_t* __restrict__ wt_off, const double* __restrict__ mats,
                  const int64_t* __restrict__ mat_off, double* __restrict__ wext, int nc, int nfq, int nqf) {
+  __shared__ double sW[5 * MIX_MAX_NP];
   const int32_t* t = tasks + 8 * (int64_t)blockIdx.x;
   const int slot = t[0], face = t[1], nbb = t[2], nbs = t[3], mat = t[4], np = t[6];
   const double* wtn = ws_base + wt_off[nbb] + (int64_t)nbs * nc * np;
-  const double* I = mats + mat_off[mat];
+  for (int o = threadIdx.x; o < nc * np; o += blockDim.x) sW[o] = wtn[o];
+  __syncthreads();
+  const double* IT = mats + mat_off[mat];
   double* dst = wext + (int64_t)slot * nc * nfq + face * nqf;
-  for (int o = threadIdx.x; o < nc * nqf; o += blockDim.x) {
-    const int c = o / nqf, j = o % nqf;
-    double acc = 0.0;
-    for (int k = 0; k < np; ++k) acc += I[j * np + k] * wtn[c * np + k];
-    dst[c * nfq + j] = acc;
+  for (int j = threadIdx.x; j < nqf; j += blockDim.x) {
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int k = 0; k < np; ++k) {
+      const double a = IT[(int64_t)k * nqf + j];
+      for (int c = 0; c < 5; ++c)
+        if (c < nc) acc[c] += a * sW[c * np + k];
+    }
+    for (int c = 0; c < nc; ++c) dst[c * nfq + j] = acc[c];
   }
 }
 

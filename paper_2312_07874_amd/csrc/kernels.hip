@@ -174,7 +174,7 @@ __device__ __forceinline__ void facet_task(const Node<DIM>& Vi, const double* gn
 
 // ------------------------------------------------------------------ K2: right-hand side
 template <int DIM, int P, int FLUX>
-__global__ void __launch_bounds__((Launch<DIM, P>::BS))
+__global__ void __launch_bounds__((Launch<DIM, P>::BSMAX))
 k_rhs(const double* __restrict__ wt, const double* __restrict__ wfb, double* __restrict__ dudt,
       const double* __restrict__ gvol, const double* __restrict__ gfac, const int32_t* __restrict__ conn,
       DevTables T, Scheme S, int64_t ne, int* flag, double* frec) {
@@ -418,11 +418,12 @@ static int run_residual(const esd_plan* pl, const double* u, double* dudt, Works
   hipLaunchKernelGGL((k_entropy_projection<DIM, P, false>), dim3(nb), dim3(L::BS), 0, s, u, ws.wt, ws.wf,
                      pl->d_gvol, pl->tab, pl->scheme, pl->ne, pl->d_flag);
   if (pl->timing) timing_event(pl, s);
+  const int bs = pl->k2_block > 0 ? pl->k2_block : L::BS;
   if (pl->scheme.ecflux == FLUX_RANOCHA)
-    hipLaunchKernelGGL((k_rhs<DIM, P, FLUX_RANOCHA>), dim3(nb), dim3(L::BS), 0, s, ws.wt, ws.wf, dudt, pl->d_gvol,
+    hipLaunchKernelGGL((k_rhs<DIM, P, FLUX_RANOCHA>), dim3(nb), dim3(bs), 0, s, ws.wt, ws.wf, dudt, pl->d_gvol,
                        pl->d_gfac, pl->d_conn, pl->tab, pl->scheme, pl->ne, pl->d_flag, ws.frec);
   else
-    hipLaunchKernelGGL((k_rhs<DIM, P, FLUX_CHANDRASHEKAR>), dim3(nb), dim3(L::BS), 0, s, ws.wt, ws.wf, dudt,
+    hipLaunchKernelGGL((k_rhs<DIM, P, FLUX_CHANDRASHEKAR>), dim3(nb), dim3(bs), 0, s, ws.wt, ws.wf, dudt,
                        pl->d_gvol, pl->d_gfac, pl->d_conn, pl->tab, pl->scheme, pl->ne, pl->d_flag, ws.frec);
   if (pl->timing) timing_event(pl, s);
   return (int)hipGetLastError();
@@ -432,11 +433,12 @@ template <int DIM, int P>
 static int run_rhs(const esd_plan* pl, double* dudt, Workspace ws, hipStream_t s) {
   using L = Launch<DIM, P>;
   const int64_t nb = (pl->ne + L::EPB - 1) / L::EPB;
+  const int bs = pl->k2_block > 0 ? pl->k2_block : L::BS;
   if (pl->scheme.ecflux == FLUX_RANOCHA)
-    hipLaunchKernelGGL((k_rhs<DIM, P, FLUX_RANOCHA>), dim3(nb), dim3(L::BS), 0, s, ws.wt, ws.wf, dudt, pl->d_gvol,
+    hipLaunchKernelGGL((k_rhs<DIM, P, FLUX_RANOCHA>), dim3(nb), dim3(bs), 0, s, ws.wt, ws.wf, dudt, pl->d_gvol,
                        pl->d_gfac, pl->d_conn, pl->tab, pl->scheme, pl->ne, pl->d_flag, ws.frec);
   else
-    hipLaunchKernelGGL((k_rhs<DIM, P, FLUX_CHANDRASHEKAR>), dim3(nb), dim3(L::BS), 0, s, ws.wt, ws.wf, dudt,
+    hipLaunchKernelGGL((k_rhs<DIM, P, FLUX_CHANDRASHEKAR>), dim3(nb), dim3(bs), 0, s, ws.wt, ws.wf, dudt,
                        pl->d_gvol, pl->d_gfac, pl->d_conn, pl->tab, pl->scheme, pl->ne, pl->d_flag, ws.frec);
   return (int)hipGetLastError();
 }
@@ -454,6 +456,22 @@ bool degree_supported(int dim, int p) {
   if (dim == 2) return p >= 1 && p <= 10;
   if (dim == 3) return p >= 1 && p <= 10;
   return false;
+}
+
+// block sizes the right-hand-side kernel may be launched with (multiples of
+// 64 up to its compiled bound), default first
+std::vector<int> rhs_block_candidates(int dim, int p) {
+  std::vector<int> c;
+#define X(D, PP)                                                        \
+  if (dim == D && p == PP) {                                            \
+    c.push_back(Launch<D, PP>::BS);                                     \
+    for (int b = 64; b <= Launch<D, PP>::BSMAX; b += 64)                \
+      if (b != Launch<D, PP>::BS) c.push_back(b);                       \
+  }
+  ESD_TRI_DEGREES(X)
+  ESD_TET_DEGREES(X)
+#undef X
+  return c;
 }
 
 bool vjp_degree_supported(int dim, int p) {

@@ -97,6 +97,18 @@ struct esd_plan {
   double* d_mats = nullptr;       // mixed-interface evaluation matrices
   int64_t* d_mat_off = nullptr;   // [n_mats] offsets into d_mats
   int64_t* d_wt_off = nullptr;    // [nb] offsets (doubles) of each bucket's w~ in the workspace
+  int k2_block = 0;               // right-hand-side block size chosen by esd_plan_autotune (0: default)
+  // RK4 steps replayed from a captured graph (no checkpoints, no timing)
+  bool use_graphs = true;
+  hipStream_t gstream = nullptr;
+  hipEvent_t gev[2] = {nullptr, nullptr};
+  struct GraphEntry {
+    const void* u;
+    const void* ws;
+    double dt;
+    hipGraphExec_t exec;
+  };
+  std::vector<GraphEntry> graphs;
   bool timing = false;
   mutable std::vector<hipEvent_t> ev;       // triples: before K1, between, after K2
   mutable std::vector<hipEvent_t> ev_pool;
@@ -129,4 +141,5 @@ int launch_diagnostics(const esd_plan* P, const double* u, const double* dudt, d
 bool degree_supported(int dim, int p);
 bool vjp_degree_supported(int dim, int p);
 bool needs_facet_records(int dim, int p);   // the residual workspace holds Workspace::frec
+std::vector<int> rhs_block_candidates(int dim, int p);
 }  // namespace esd

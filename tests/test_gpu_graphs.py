@@ -1,0 +1,86 @@
+"""Graph-replayed RK4 steps and the right-hand-side autotuner.
+
+Every replay is compared with the same step launched kernel by kernel, with
+the program's own eager work and synchronisations between replays; equality
+is up to the order of the LDS atomic sums (1e-13 of the state per variable)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as wl
+from tests.parity_util import gpu_plan, log
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.init()
+
+
+def _close(a, b, what):
+    a, b = a.detach().cpu(), b.detach().cpu()
+    err = float((a - b).abs().max())
+    scale = float(b.abs().max())
+    log(f"{what}: max |graph - eager| / max |eager| = {err / scale:.2e}")
+    assert err <= 1e-13 * scale, what
+
+
+def _replays_match_eager(plan, u0, dt, nrep):
+    ug = u0.clone()
+    ue = u0.clone()
+    scratch = torch.empty_like(u0)
+    for r in range(nrep):
+        plan.set_graphs(True)
+        plan.rk4(ug, dt, 1)                      # replay (captured at r = 0)
+        plan.residual(ue, scratch)               # unrelated eager work between replays
+        torch.cuda.synchronize()
+        plan.set_graphs(False)
+        plan.rk4(ue, dt, 1)
+        torch.cuda.synchronize()
+        plan.sync_status()
+        _close(ug, ue, f"replay {r}")
+    # several replays in one call
+    plan.set_graphs(True)
+    plan.rk4(ug, dt, 3)
+    plan.set_graphs(False)
+    plan.rk4(ue, dt, 3)
+    torch.cuda.synchronize()
+    _close(ug, ue, "3 replays in one call")
+
+
+def test_graph_rk4_single_plan():
+    wk = wl.random_tet(M=3, degree=3, seed=7)
+    plan = gpu_plan(wk)
+    x = plan.node_coords().cpu().numpy()
+    u0 = plan.project(torch.tensor(wk.state(x), device="cuda").contiguous())
+    _replays_match_eager(plan, u0, 1e-3, 4)
+
+
+def test_graph_rk4_batched_plan():
+    import paper_2312_07874_amd as esd
+    L = 2 * math.pi
+    m = wl.split_box_mesh(3, 3, L)
+    deg = wl.mixed_degrees(m.n_elements, 3, 2, 5)
+    plan = esd.BatchedPlan(3, [(m.elem_vertex_ids, m.elem_vertex_coords, deg)], wl.make_warp_sinprod(L, 0.05))
+    x = plan.node_coords().cpu().numpy()
+    u0 = plan.project(torch.tensor(wl.RandomSmooth(3, L, 2)(x), device="cuda").reshape(plan.nodal_shape).contiguous())
+    _replays_match_eager(plan, u0, 1e-3, 3)
+
+
+def test_autotune_keeps_the_residual():
+    wk = wl.random_tet(M=3, degree=6, seed=9)
+    plan = gpu_plan(wk)
+    x = plan.node_coords().cpu().numpy()
+    u = plan.project(torch.tensor(wk.state(x), device="cuda").contiguous())
+    before = plan.residual(u).clone()
+    blocks = plan.autotune(u)
+    after = plan.residual(u)
+    plan.sync_status()
+    log(f"autotuned right-hand-side block: {blocks}")
+    assert blocks[0] % 64 == 0 and 64 <= blocks[0] <= 512
+    _close(after, before, "residual after autotune")
