@@ -44,7 +44,37 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_gpu(name: str, steps: int, warmup: int):
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+KERNEL_SOURCES = ("device.hpp", "physics.hpp", "kernels.hip", "plan.hpp")
+
+
+def kernel_source_hash() -> str:
+    """sha256 over the sources the right-hand-side kernel is built from."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2312_07874_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(name: str):
+    """HBM bytes per K2 launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs
+    recorded in profiles/traffic.json, if they were taken on these kernel
+    sources (else None)."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    w = t.get("workloads", {}).get(name)
+    return None if w is None else w["read_bytes_per_launch"] + w["write_bytes_per_launch"]
+
+
+def run_gpu(name: str, steps: int, warmup: int, autotune: bool = True):
     import torch
 
     import paper_2312_07874_amd as esd
@@ -58,7 +88,10 @@ def run_gpu(name: str, steps: int, warmup: int):
     x = plan.node_coords().cpu().numpy()
     u = plan.project(torch.tensor(wk.state(x), device="cuda").contiguous())
     plan.sync_status()
-    blocks = plan.autotune(u)
+    if autotune:
+        plan.autotune(u)
+    blocks = plan.tuning()
+    blocks_k1 = plan.tuning_k1()
     dt = 1e-4
     for _ in range(warmup):
         plan.rk4(u, dt, 1)
@@ -89,7 +122,7 @@ def run_gpu(name: str, steps: int, warmup: int):
     else:
         roof = {"bound": "hbm", "achieved": by / k2_avg_s / 1e9, "peak": pm.PEAK_HBM_GBS, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    roof["traffic"] = measured_traffic(name)
     roof["kernel"] = "k_rhs (K2)"
     roof["algorithmic_flops_per_launch"] = fl
     roof["algorithmic_bytes_per_launch"] = by
@@ -112,6 +145,7 @@ def run_gpu(name: str, steps: int, warmup: int):
         "k1_flop_rate_tflops": pm.k1_flops(d, p) * info.n_elements / k1_avg_s / 1e12,
         "vjp": vjp,
         "k2_block_autotuned": blocks[0],
+        "k1_block_autotuned": blocks_k1[0],
         "ms_per_step_graph": graph_ms,
     }
 
@@ -244,6 +278,9 @@ def main():
                     help="comma-separated additional workloads reported under 'extra' ('' for none)")
     ap.add_argument("--extra-steps", type=int, default=3)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched mixed-degree workload")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default block sizes")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="finish with a plain 1 GiB device-to-device copy (counter calibration for profiles)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -251,11 +288,11 @@ def main():
         print("bench.py runs on one GPU only: this build has no multi-GPU path (see the sharding "
               "design notes); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
-    main_res = run_gpu(args.workload, args.steps, args.warmup)
+    main_res = run_gpu(args.workload, args.steps, args.warmup, not args.no_autotune)
     extra = []
     for name in [s for s in args.extra.split(",") if s]:
         if name != args.workload:
-            extra.append(run_gpu(name, args.extra_steps, 1))
+            extra.append(run_gpu(name, args.extra_steps, 1, not args.no_autotune))
     if not args.no_batched:
         extra.append(run_batched(args.extra_steps, 1))
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.workload, args.cpu_seconds)
@@ -279,6 +316,9 @@ def main():
         "flux_pairs_distinct_per_s": main_res["flux_pairs_distinct_per_s"],
         "ms_per_residual_k1_k2": main_res["ms_per_residual_k1_k2"],
         "ms_per_step_graph": main_res["ms_per_step_graph"],
+        "k1_avg_ms": main_res["k1_avg_ms"],
+        "k2_block_autotuned": main_res["k2_block_autotuned"],
+        "k1_block_autotuned": main_res["k1_block_autotuned"],
         "roofline": main_res["roofline"],
         "vjp_over_forward": main_res["vjp"]["vjp_over_forward"],
         "vjp": main_res["vjp"],
@@ -286,6 +326,14 @@ def main():
         "extra": extra,
     }
     print(json.dumps(out), flush=True)
+    if args.calibrate_copy:
+        import torch
+
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log("[bench] calibration copy: 1 GiB read + 1 GiB written")
 
 
 if __name__ == "__main__":

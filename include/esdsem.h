@@ -196,11 +196,12 @@ esd_status esd_rk4(const esd_plan* plan, double* u_dev, double dt, int32_t nstep
  * esd_plan_set_graphs(plan, 0) launches every kernel individually instead. */
 esd_status esd_plan_set_graphs(esd_plan* plan, int32_t enable);
 
-/* Chooses the block size of the right-hand-side kernel for every bucket by
- * timing the candidates (multiples of 64 up to its compiled bound) on the state
- * u_dev; ws_dev holds info.rk4_workspace_bytes.  Synchronises.  The choice is
- * kept by the plan and reported by esd_plan_get_tuning (k2_block[bucket],
- * capacity entries available). */
+/* Chooses the block sizes of the right-hand-side kernel (K2) and of the
+ * entropy-projection kernel (K1) for every bucket by timing the candidates
+ * (multiples of 64 up to their compiled bound) on the state u_dev; ws_dev holds
+ * info.rk4_workspace_bytes.  Synchronises.  The choice is kept by the plan and
+ * reported by esd_plan_get_tuning: k2_block[bucket], and, when capacity allows
+ * 2 n_buckets entries, the K1 block sizes in k2_block[n_buckets + bucket]. */
 esd_status esd_plan_autotune(esd_plan* plan, const double* u_dev, void* ws_dev, void* stream);
 esd_status esd_plan_get_tuning(const esd_plan* plan, int32_t* k2_block, int32_t capacity);
 

@@ -265,10 +265,16 @@ class Plan:
         return self.tuning()
 
     def tuning(self):
-        out = (ctypes.c_int32 * 16)()
-        _check(_lib.esd_plan_get_tuning(self._h, out, 16), "esd_plan_get_tuning")
+        """Right-hand-side (K2) block size per bucket; tuning_k1() the K1 ones."""
         n = len(getattr(self, "buckets", [None]))
+        out = (ctypes.c_int32 * (2 * n))()
+        _check(_lib.esd_plan_get_tuning(self._h, out, 2 * n), "esd_plan_get_tuning")
+        self._k1_blocks = [out[n + b] for b in range(n)]
         return [out[b] for b in range(n)]
+
+    def tuning_k1(self):
+        self.tuning()
+        return self._k1_blocks
 
     def set_timing(self, enable: bool):
         _check(_lib.esd_plan_set_timing(self._h, 1 if enable else 0), "esd_plan_set_timing")

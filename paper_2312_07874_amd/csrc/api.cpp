@@ -799,24 +799,33 @@ esd_status esd_plan_autotune(esd_plan* P, const double* u_dev, void* ws_dev, voi
     esd_plan* B = P->batched ? P->sub[b] : P;
     void* wsb = P->batched ? (char*)ws_dev + P->ws_off[b] : ws_dev;
     double* out = dudt + (P->batched ? P->dof_off[b] : 0);
-    float best = 1e30f;
-    int best_bs = 0;
-    for (int bs : esd::rhs_block_candidates(B->dim, B->p)) {
-      B->k2_block = bs;
-      rc = esd::launch_rhs(B, out, split_ws(B, wsb), s);
-      if (rc != 0) break;
-      HIP_TRY(hipEventRecord(e0, s));
-      for (int r = 0; r < 3 && rc == 0; ++r) rc = esd::launch_rhs(B, out, split_ws(B, wsb), s);
-      HIP_TRY(hipEventRecord(e1, s));
-      HIP_TRY(hipEventSynchronize(e1));
-      float ms = 0.f;
-      HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-      if (ms < best) {
-        best = ms;
-        best_bs = bs;
+    // K2 first (its inputs stay valid), then K1, which rewrites the facet values
+    // with the same data
+    for (int which = 2; which >= 1 && rc == 0; --which) {
+      float best = 1e30f;
+      int best_bs = 0;
+      for (int bs : esd::rhs_block_candidates(B->dim, B->p)) {
+        (which == 2 ? B->k2_block : B->k1_block) = bs;
+        auto launch = [&]() {
+          return which == 2 ? esd::launch_rhs(B, out, split_ws(B, wsb), s)
+                            : esd::launch_entropy_projection(B, u_dev + (P->batched ? P->dof_off[b] : 0),
+                                                             split_ws(B, wsb), s);
+        };
+        rc = launch();
+        if (rc != 0) break;
+        HIP_TRY(hipEventRecord(e0, s));
+        for (int r = 0; r < 3 && rc == 0; ++r) rc = launch();
+        HIP_TRY(hipEventRecord(e1, s));
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) {
+          best = ms;
+          best_bs = bs;
+        }
       }
+      (which == 2 ? B->k2_block : B->k1_block) = best_bs;
     }
-    B->k2_block = best_bs;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -836,6 +845,7 @@ esd_status esd_plan_get_tuning(const esd_plan* P, int32_t* k2_block, int32_t cap
   for (int b = 0; b < nbk; ++b) {
     const esd_plan* B = P->batched ? P->sub[b] : P;
     k2_block[b] = B->k2_block > 0 ? B->k2_block : esd::rhs_block_candidates(B->dim, B->p)[0];
+    if (capacity >= 2 * nbk) k2_block[nbk + b] = B->k1_block > 0 ? B->k1_block : esd::rhs_block_candidates(B->dim, B->p)[0];
   }
   return ESD_OK;
 }

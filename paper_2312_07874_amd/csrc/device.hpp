@@ -48,8 +48,8 @@ struct Launch<3, P> {
   static constexpr int EPB = 1;
   // measured on MI355X (K2 at p = 4..8): 128, 192, 256, 256, 512 threads
   static constexpr int BS = P <= 3 ? 64 : (P == 4 ? 128 : (P == 5 ? 192 : (P <= 7 ? 256 : 512)));
-  // right-hand-side kernel: compiled for up to 512 threads, launched with BS
-  // or with the block size the autotuner picked (its loops take any size)
+  // K1 and K2 are compiled for up to BSMAX threads and launched with BS or with
+  // the block size the autotuner picked (their loops take any size)
   static constexpr int BSMAX = 512;
   static_assert(P <= 10, "tetrahedra up to p = 10");
 };
@@ -58,7 +58,7 @@ struct Launch<2, P> {
   static constexpr int EPB = (P <= 4) ? 12 : ((P <= 7) ? 8 : 6);
   static constexpr int NQ = (P + 1) * (P + 1);
   static constexpr int BS = ((EPB * NQ + 63) / 64) * 64;
-  static constexpr int BSMAX = BS;
+  static constexpr int BSMAX = 2 * BS < 768 ? 2 * BS : (BS > 768 ? BS : 768);   // <= 3 waves per SIMD
 };
 
 __device__ __forceinline__ int pair_index(int P, int a1, int a2) { return a1 * (P + 1) - a1 * (a1 - 1) / 2 + a2; }

@@ -29,7 +29,7 @@ namespace esd {
 
 // ------------------------------------------------------------------ K1: entropy projection
 template <int DIM, int P, bool PROJECT_ONLY>
-__global__ void __launch_bounds__((Launch<DIM, P>::BS))
+__global__ void __launch_bounds__((Launch<DIM, P>::BSMAX))
 k_entropy_projection(const double* __restrict__ u, double* __restrict__ wt, double* __restrict__ wf,
                      const double* __restrict__ gvol, DevTables T, Scheme S, int64_t ne, int* flag) {
   using Sh = Shape<DIM, P>;
@@ -415,7 +415,8 @@ static int run_residual(const esd_plan* pl, const double* u, double* dudt, Works
   using L = Launch<DIM, P>;
   const int64_t nb = (pl->ne + L::EPB - 1) / L::EPB;
   if (pl->timing) timing_event(pl, s);
-  hipLaunchKernelGGL((k_entropy_projection<DIM, P, false>), dim3(nb), dim3(L::BS), 0, s, u, ws.wt, ws.wf,
+  const int bs1 = pl->k1_block > 0 ? pl->k1_block : L::BS;
+  hipLaunchKernelGGL((k_entropy_projection<DIM, P, false>), dim3(nb), dim3(bs1), 0, s, u, ws.wt, ws.wf,
                      pl->d_gvol, pl->tab, pl->scheme, pl->ne, pl->d_flag);
   if (pl->timing) timing_event(pl, s);
   const int bs = pl->k2_block > 0 ? pl->k2_block : L::BS;
@@ -503,7 +504,8 @@ int launch_entropy_projection(const esd_plan* pl, const double* u, Workspace ws,
   if (pl->dim == D && pl->p == PP) {                                                                          \
     using L = Launch<D, PP>;                                                                                  \
     const int64_t nb = (pl->ne + L::EPB - 1) / L::EPB;                                                        \
-    hipLaunchKernelGGL((k_entropy_projection<D, PP, false>), dim3(nb), dim3(L::BS), 0, s, u, ws.wt, ws.wf,    \
+    hipLaunchKernelGGL((k_entropy_projection<D, PP, false>), dim3(nb),                                        \
+                       dim3(pl->k1_block > 0 ? pl->k1_block : L::BS), 0, s, u, ws.wt, ws.wf,                  \
                        pl->d_gvol, pl->tab, pl->scheme, pl->ne, pl->d_flag);                                  \
     return (int)hipGetLastError();                                                                            \
   }

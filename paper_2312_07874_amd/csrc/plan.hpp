@@ -98,6 +98,7 @@ struct esd_plan {
   int64_t* d_mat_off = nullptr;   // [n_mats] offsets into d_mats
   int64_t* d_wt_off = nullptr;    // [nb] offsets (doubles) of each bucket's w~ in the workspace
   int k2_block = 0;               // right-hand-side block size chosen by esd_plan_autotune (0: default)
+  int k1_block = 0;               // entropy-projection block size chosen likewise
   // RK4 steps replayed from a captured graph (no checkpoints, no timing)
   bool use_graphs = true;
   hipStream_t gstream = nullptr;
