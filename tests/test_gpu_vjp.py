@@ -30,6 +30,9 @@ SMALL = [
     ("tet_p1_random_lf", wl.random_tet(M=3, degree=1, seed=5)),
     ("tet_p2_random_ec", wl.random_tet(M=3, degree=2, seed=6, dissipation=0)),
     ("tet_p3_random_lf", wl.random_tet(M=3, degree=3, seed=7)),
+    ("tet_p2_chandrashekar_lf", wl.Workload("random_tet_chandrashekar", 3, 3, 2 * math.pi, 2,
+                                           wl.make_warp_sinprod(2 * math.pi, 0.05),
+                                           wl.RandomSmooth(3, 2 * math.pi, 12), 1, 1)),
 ]
 
 
@@ -87,6 +90,22 @@ def test_vjp_parity_small(name, wk):
     plan.sync_status()
     torch.cuda.synchronize()
     assert_close(out, ref, name)
+
+
+def test_vjp_parity_high_degree_sampled():
+    """Tet p = 5 and tri p = 8 on small meshes, 8 sampled elements each (the
+    oracle differentiates their 1-ring densely)."""
+    from oracle import residual as R
+    for wk in (wl.random_tet(M=3, degree=5, seed=13), wl.random_tri(M=3, degree=8, seed=14)):
+        prob = oracle_problem(wk)
+        ut = oracle_state(prob, wk)
+        vbar = cotangent(ut.shape, 29)
+        plan = gpu_plan(wk)
+        out = plan.vjp(ut.cuda().contiguous(), vbar.cuda().contiguous()).cpu()
+        plan.sync_status()
+        el = np.random.default_rng(5).choice(prob.ne, 8, replace=False)
+        ref = oracle_vjp_pair(prob, ut, vbar, el)
+        assert_close(out[el], ref, wk.name)
 
 
 FULL = [("vortex_tri_M64_p4", lambda: wl.vortex_tri(M=64, degree=4)),

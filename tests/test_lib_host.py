@@ -114,3 +114,26 @@ def test_workspace_sizes_and_host_only_rejection():
     assert L.esd_rk4(plan._h, fake, 1e-3, 1, 2 * fake, None, None) == -1
     assert L.esd_rk4_vjp(plan._h, fake, 1e-3, 1, 2 * fake, 3 * fake, None) == -1
     assert b"host-only" in L.esd_last_error()
+
+
+def test_batched_plan_buckets_and_element_map():
+    """Host-only batched plan: buckets by ascending degree over all meshes,
+    slots in mesh order, offsets consistent with the per-degree sizes."""
+    esd = _lib()
+    L = 2 * math.pi
+    m1, m2 = wl.split_box_mesh(3, 3, L), wl.split_box_mesh(3, 4, L)
+    d1, d2 = wl.mixed_degrees(m1.n_elements, 1, 2, 5), wl.mixed_degrees(m2.n_elements, 2, 3, 6)
+    plan = esd.BatchedPlan(3, [(m1.elem_vertex_ids, m1.elem_vertex_coords, d1),
+                               (m2.elem_vertex_ids, m2.elem_vertex_coords, d2)], host_only=True)
+    degs = np.concatenate([d1, d2])
+    assert [b["degree"] for b in plan.buckets] == sorted(set(degs.tolist()))
+    for bi, b in enumerate(plan.buckets):
+        members = np.where(degs == b["degree"])[0]
+        assert b["n_elements"] == len(members)
+        assert np.array_equal(plan.elem_bucket[members], np.full(len(members), bi))
+        assert np.array_equal(plan.elem_slot[members], np.arange(len(members)))
+        np_ = (b["degree"] + 1) * (b["degree"] + 2) * (b["degree"] + 3) // 6
+        assert b["dof"][1] - b["dof"][0] == len(members) * 5 * np_
+        assert b["nodes"][1] - b["nodes"][0] == len(members) * (b["degree"] + 1) ** 3
+    assert plan.info.n_dof == plan.buckets[-1]["dof"][1]
+    assert plan.info.n_elements == len(degs)
