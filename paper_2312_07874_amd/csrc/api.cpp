@@ -711,7 +711,7 @@ static int rk4_step(const esd_plan* P, double* u_dev, double dt, void* ws_dev, d
 
 // the instantiated graph of one RK4 step for (u, ws, dt), captured on the
 // plan's own stream at first use
-static esd_status step_graph(esd_plan* P, double* u_dev, double dt, void* ws_dev, hipGraphExec_t* exec) {
+static esd_status step_graph(const esd_plan* P, double* u_dev, double dt, void* ws_dev, hipGraphExec_t* exec) {
   for (const auto& g : P->graphs)
     if (g.u == u_dev && g.ws == ws_dev && g.dt == dt) {
       *exec = g.exec;
@@ -743,13 +743,12 @@ static esd_status step_graph(esd_plan* P, double* u_dev, double dt, void* ws_dev
   return ESD_OK;
 }
 
-esd_status esd_rk4(const esd_plan* Pc, double* u_dev, double dt, int32_t nsteps, void* ws_dev,
+esd_status esd_rk4(const esd_plan* P, double* u_dev, double dt, int32_t nsteps, void* ws_dev,
                    double* stage_ckpt_dev, void* stream) {
-  esd_status st = check_device(Pc);
+  esd_status st = check_device(P);
   if (st != ESD_OK) return st;
   if (!u_dev || !ws_dev || nsteps < 0 || !std::isfinite(dt)) return fail(ESD_EINVAL, "bad argument");
   if (((uintptr_t)ws_dev) % 256 != 0) return fail(ESD_EINVAL, "workspace not 256-byte aligned");
-  esd_plan* P = const_cast<esd_plan*>(Pc);   // graph cache only
   hipStream_t s = (hipStream_t)stream;
   const int64_t n = total_dof(P);
   if (!stage_ckpt_dev && !P->timing && P->use_graphs && nsteps > 0) {

@@ -100,16 +100,17 @@ struct esd_plan {
   int k2_block = 0;               // right-hand-side block size chosen by esd_plan_autotune (0: default)
   int k1_block = 0;               // entropy-projection block size chosen likewise
   // RK4 steps replayed from a captured graph (no checkpoints, no timing)
+  // (the cache below is filled by const compute calls, hence mutable)
   bool use_graphs = true;
-  hipStream_t gstream = nullptr;
-  hipEvent_t gev[2] = {nullptr, nullptr};
+  mutable hipStream_t gstream = nullptr;
+  mutable hipEvent_t gev[2] = {nullptr, nullptr};
   struct GraphEntry {
     const void* u;
     const void* ws;
     double dt;
     hipGraphExec_t exec;
   };
-  std::vector<GraphEntry> graphs;
+  mutable std::vector<GraphEntry> graphs;
   bool timing = false;
   mutable std::vector<hipEvent_t> ev;       // triples: before K1, between, after K2
   mutable std::vector<hipEvent_t> ev_pool;
