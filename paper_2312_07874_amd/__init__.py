@@ -15,6 +15,8 @@ from typing import Callable, Optional
 
 import numpy as np
 
+import torch  # noqa: F401  (first: the library then shares the HIP runtime torch loads)
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libesdsem.so")
 

@@ -275,3 +275,26 @@ def batched_tets(Ms=(8, 10, 12, 14), lo=2, hi=10, seed=20231213) -> Batch:
     degs = [rng.integers(lo, hi + 1, size=m.n_elements).astype(np.int32) for m in meshes]
     name = f"batched_tets_M{'-'.join(str(M) for M in Ms)}_p{lo}-{hi}"
     return Batch(name, 3, meshes, degs, L, make_warp_sinprod(L, 0.05), RandomSmooth(3, L, seed))
+
+
+def kelvin_helmholtz(x, gamma=GAMMA):
+    """Kelvin-Helmholtz instability on (0,2)^2 (Sec. 7.5): B = tanh(15(y-1/2)) -
+    tanh(15(y-3/2)), rho = 1/2 + 3B/4, v = (B-1)/2, sin(2 pi x)/10, p = 1."""
+    x = np.asarray(x, dtype=np.float64)
+    B = np.tanh(15.0 * (x[..., 1] - 0.5)) - np.tanh(15.0 * (x[..., 1] - 1.5))
+    rho = 0.5 + 0.75 * B
+    v = np.stack([0.5 * (B - 1.0), 0.1 * np.sin(2.0 * math.pi * x[..., 0])], axis=-1)
+    return prim_to_cons(rho, v, np.ones_like(rho), gamma)
+
+
+def khi_tri(M=16, degree=4, dissipation=1) -> Workload:
+    """2 M^2 curved triangles on [0,2]^2, Kelvin-Helmholtz instability."""
+    return Workload(f"khi_tri_M{M}_p{degree}", 2, M, 2.0, degree, make_warp_sinprod(2.0, 0.05),
+                    kelvin_helmholtz, 0, dissipation)
+
+
+def tgv_tet_mach(M=4, degree=4, Ma=0.1, dissipation=1) -> Workload:
+    """6 M^3 curved tetrahedra on [0,2pi]^3, Taylor-Green flow at Mach Ma."""
+    L = 2.0 * math.pi
+    return Workload(f"tgv_tet_M{M}_p{degree}_Ma{Ma}", 3, M, L, degree, make_warp_sinprod(L, 0.05),
+                    lambda x, gamma=GAMMA: taylor_green(x, Ma, gamma), 0, dissipation)
