@@ -3,13 +3,15 @@
 
 A step is one classical RK4 step on the workload (4 residual evaluations, each
 the whole path: entropy projection, flux differencing, facet correction,
-interface flux, weight-adjusted inverse; plus the stage combinations), with the
-state resident in HBM.  Prints one JSON line:
+interface flux, weight-adjusted inverse; the stage combinations are fused into
+the right-hand-side kernel's output), with the state resident in HBM.  Prints
+one JSON line:
 
   value     FP64 residual evaluations x DOF per second (DOF = elements x (d+2) x modes)
-  roofline  for the dominant kernel (the right-hand-side kernel K2): algorithmic
-            flops per launch / its average duration, from HIP events recorded
-            around every launch on its stream during the timed steps
+  roofline  for the dominant kernel (the right-hand-side kernel K2, with its
+            fused stage combination): algorithmic flops or bytes per launch,
+            whichever bound is binding, / its average duration, from HIP events
+            recorded around every launch on its stream during the timed steps
   cpu_baseline  the dense FP64 oracle on a bounded sample of the same workload
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
@@ -114,7 +116,7 @@ def run_gpu(name: str, steps: int, warmup: int, autotune: bool = True):
     k2_avg_s = k2_ms / nlaunch * 1e-3
     k1_avg_s = k1_ms / nlaunch * 1e-3
     fl = pm.k2_flops(d, p, wk.ecflux, wk.dissipation) * info.n_elements
-    by = pm.k2_bytes(d, p) * info.n_elements
+    by = pm.k2_rk_bytes(d, p) * info.n_elements
     t_fl = fl / (pm.PEAK_FP64_TFLOPS * 1e12)
     t_by = by / (pm.PEAK_HBM_GBS * 1e9)
     if t_fl >= t_by:
@@ -123,7 +125,7 @@ def run_gpu(name: str, steps: int, warmup: int, autotune: bool = True):
         roof = {"bound": "hbm", "achieved": by / k2_avg_s / 1e9, "peak": pm.PEAK_HBM_GBS, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["traffic"] = measured_traffic(name)
-    roof["kernel"] = "k_rhs (K2)"
+    roof["kernel"] = "k_rhs (K2, RK4 stage fused)"
     roof["algorithmic_flops_per_launch"] = fl
     roof["algorithmic_bytes_per_launch"] = by
     roof["avg_launch_ms"] = k2_avg_s * 1e3

@@ -648,8 +648,19 @@ static int64_t total_dof(const esd_plan* P) {
 
 // one residual evaluation; for a batched plan: K1 of every bucket, the
 // mixed-interface exterior values, then K2 of every bucket
-static int residual_any(const esd_plan* P, const double* u, double* dudt, void* ws, hipStream_t s) {
-  if (!P->batched) return esd::launch_residual(P, u, dudt, split_ws(P, ws), s);
+static esd::RkEpilogue shift(const esd::RkEpilogue& e, int64_t off) {
+  esd::RkEpilogue r = e;
+  if (r.acc) {
+    r.u += off;
+    r.acc += off;
+    r.U += off;
+  }
+  return r;
+}
+
+static int residual_any(const esd_plan* P, const double* u, double* dudt, void* ws, hipStream_t s,
+                        const esd::RkEpilogue& epi = esd::RkEpilogue()) {
+  if (!P->batched) return esd::launch_residual(P, u, dudt, split_ws(P, ws), s, epi);
   const int nb = (int)P->sub.size();
   if (P->timing) esd::timing_event(P, s);
   for (int b = 0; b < nb; ++b) {
@@ -664,7 +675,8 @@ static int residual_any(const esd_plan* P, const double* u, double* dudt, void* 
   }
   if (P->timing) esd::timing_event(P, s);
   for (int b = 0; b < nb; ++b) {
-    const int rc = esd::launch_rhs(P->sub[b], dudt + P->dof_off[b], split_ws(P->sub[b], (char*)ws + P->ws_off[b]), s);
+    const int rc = esd::launch_rhs(P->sub[b], dudt + P->dof_off[b], split_ws(P->sub[b], (char*)ws + P->ws_off[b]), s,
+                                   shift(epi, P->dof_off[b]));
     if (rc != 0) return rc;
   }
   if (P->timing) esd::timing_event(P, s);
@@ -683,11 +695,12 @@ esd_status esd_residual(const esd_plan* P, const double* u_dev, double* dudt_dev
   return ESD_OK;
 }
 
-// one RK4 step: four residual evaluations and stage combinations
+// one RK4 step: four residual evaluations, each right-hand-side kernel
+// combining its stage into the accumulator and the next stage's input
+// (classical RK4: u + dt/6 (k1 + 2 k2 + 2 k3 + k4))
 static int rk4_step(const esd_plan* P, double* u_dev, double dt, void* ws_dev, double* ckpt, hipStream_t s) {
   const int64_t n = total_dof(P);
   const size_t nb = align256((size_t)n * sizeof(double));
-  double* k = (double*)((char*)ws_dev + P->ws_bytes);
   double* U = (double*)((char*)ws_dev + P->ws_bytes + nb);
   double* acc = (double*)((char*)ws_dev + P->ws_bytes + 2 * nb);
   const double ca[4] = {dt / 6.0, dt / 3.0, dt / 3.0, dt / 6.0};
@@ -698,12 +711,15 @@ static int rk4_step(const esd_plan* P, double* u_dev, double dt, void* ws_dev, d
       const hipError_t e = hipMemcpyAsync(ckpt + (int64_t)stg * n, in, n * sizeof(double), hipMemcpyDeviceToDevice, s);
       if (e != hipSuccess) return (int)e;
     }
-    int rc = residual_any(P, in, k, ws_dev, s);
-    if (rc != 0) return rc;
-    if (stg < 3)
-      rc = esd::launch_rk_stage(acc, U, u_dev, k, ca[stg], cu[stg], stg == 0, n, s);
-    else
-      rc = esd::launch_axpy(u_dev, acc, ca[3], k, n, s);
+    esd::RkEpilogue epi;
+    epi.u = u_dev;
+    epi.acc = acc;
+    epi.U = U;
+    epi.ca = ca[stg];
+    epi.cu = cu[stg];
+    epi.first = stg == 0;
+    epi.last = stg == 3;
+    const int rc = residual_any(P, in, nullptr, ws_dev, s, epi);
     if (rc != 0) return rc;
   }
   return 0;

@@ -177,7 +177,7 @@ template <int DIM, int P, int FLUX>
 __global__ void __launch_bounds__((Launch<DIM, P>::BSMAX))
 k_rhs(const double* __restrict__ wt, const double* __restrict__ wfb, double* __restrict__ dudt,
       const double* __restrict__ gvol, const double* __restrict__ gfac, const int32_t* __restrict__ conn,
-      DevTables T, Scheme S, int64_t ne, int* flag, double* frec) {
+      DevTables T, Scheme S, int64_t ne, int* flag, double* frec, RkEpilogue epi) {
   using Sh = Shape<DIM, P>;
   constexpr int EPB = Launch<DIM, P>::EPB;
   constexpr int Q = Sh::Q, NC = Sh::NC, NQ = Sh::NQ, NP = Sh::NP, NQF = Sh::NQF, NFQ = Sh::NFQ, NGV = Sh::NGV;
@@ -377,19 +377,24 @@ k_rhs(const double* __restrict__ wt, const double* __restrict__ wfb, double* __r
   }
   __syncthreads();
   xform_Vt<DIM, P>(sR, T1, T2, sM, T, nec);
-  for (int o = tid; o < nec * NP; o += nth) dudt[e0 * NC * NP + o] = sM[o];
-}
-
-// ------------------------------------------------------------------ RK4 helpers
-__global__ void k_rk_stage(double* __restrict__ acc, double* __restrict__ U, const double* __restrict__ u,
-                           const double* __restrict__ k, double ca, double cu, int first, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const double ki = k[i], ui = u[i];
-    acc[i] = (first ? ui : acc[i]) + ca * ki;
-    if (U) U[i] = ui + cu * ki;
+  if (epi.acc == nullptr) {
+    for (int o = tid; o < nec * NP; o += nth) dudt[e0 * NC * NP + o] = sM[o];
+  } else if (!epi.last) {
+    for (int o = tid; o < nec * NP; o += nth) {
+      const int64_t i = e0 * NC * NP + o;
+      const double k = sM[o], ui = epi.u[i];
+      epi.acc[i] = (epi.first ? ui : epi.acc[i]) + epi.ca * k;
+      epi.U[i] = ui + epi.cu * k;
+    }
+  } else {
+    for (int o = tid; o < nec * NP; o += nth) {
+      const int64_t i = e0 * NC * NP + o;
+      epi.u[i] = epi.acc[i] + epi.ca * sM[o];
+    }
   }
 }
 
+// ------------------------------------------------------------------ vector helpers
 __global__ void k_axpy(double* __restrict__ y, const double* __restrict__ x, double a, const double* __restrict__ z,
                        int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -411,7 +416,8 @@ hipEvent_t timing_event(const esd_plan* pl, hipStream_t s) {
 }
 
 template <int DIM, int P>
-static int run_residual(const esd_plan* pl, const double* u, double* dudt, Workspace ws, hipStream_t s) {
+static int run_residual(const esd_plan* pl, const double* u, double* dudt, Workspace ws, hipStream_t s,
+                        const RkEpilogue& epi) {
   using L = Launch<DIM, P>;
   const int64_t nb = (pl->ne + L::EPB - 1) / L::EPB;
   if (pl->timing) timing_event(pl, s);
@@ -422,25 +428,25 @@ static int run_residual(const esd_plan* pl, const double* u, double* dudt, Works
   const int bs = pl->k2_block > 0 ? pl->k2_block : L::BS;
   if (pl->scheme.ecflux == FLUX_RANOCHA)
     hipLaunchKernelGGL((k_rhs<DIM, P, FLUX_RANOCHA>), dim3(nb), dim3(bs), 0, s, ws.wt, ws.wf, dudt, pl->d_gvol,
-                       pl->d_gfac, pl->d_conn, pl->tab, pl->scheme, pl->ne, pl->d_flag, ws.frec);
+                       pl->d_gfac, pl->d_conn, pl->tab, pl->scheme, pl->ne, pl->d_flag, ws.frec, epi);
   else
     hipLaunchKernelGGL((k_rhs<DIM, P, FLUX_CHANDRASHEKAR>), dim3(nb), dim3(bs), 0, s, ws.wt, ws.wf, dudt,
-                       pl->d_gvol, pl->d_gfac, pl->d_conn, pl->tab, pl->scheme, pl->ne, pl->d_flag, ws.frec);
+                       pl->d_gvol, pl->d_gfac, pl->d_conn, pl->tab, pl->scheme, pl->ne, pl->d_flag, ws.frec, epi);
   if (pl->timing) timing_event(pl, s);
   return (int)hipGetLastError();
 }
 
 template <int DIM, int P>
-static int run_rhs(const esd_plan* pl, double* dudt, Workspace ws, hipStream_t s) {
+static int run_rhs(const esd_plan* pl, double* dudt, Workspace ws, hipStream_t s, const RkEpilogue& epi) {
   using L = Launch<DIM, P>;
   const int64_t nb = (pl->ne + L::EPB - 1) / L::EPB;
   const int bs = pl->k2_block > 0 ? pl->k2_block : L::BS;
   if (pl->scheme.ecflux == FLUX_RANOCHA)
     hipLaunchKernelGGL((k_rhs<DIM, P, FLUX_RANOCHA>), dim3(nb), dim3(bs), 0, s, ws.wt, ws.wf, dudt, pl->d_gvol,
-                       pl->d_gfac, pl->d_conn, pl->tab, pl->scheme, pl->ne, pl->d_flag, ws.frec);
+                       pl->d_gfac, pl->d_conn, pl->tab, pl->scheme, pl->ne, pl->d_flag, ws.frec, epi);
   else
     hipLaunchKernelGGL((k_rhs<DIM, P, FLUX_CHANDRASHEKAR>), dim3(nb), dim3(bs), 0, s, ws.wt, ws.wf, dudt,
-                       pl->d_gvol, pl->d_gfac, pl->d_conn, pl->tab, pl->scheme, pl->ne, pl->d_flag, ws.frec);
+                       pl->d_gvol, pl->d_gfac, pl->d_conn, pl->tab, pl->scheme, pl->ne, pl->d_flag, ws.frec, epi);
   return (int)hipGetLastError();
 }
 
@@ -490,9 +496,10 @@ bool needs_facet_records(int dim, int p) {
   return false;
 }
 
-int launch_residual(const esd_plan* pl, const double* u, double* dudt, Workspace ws, hipStream_t s) {
+int launch_residual(const esd_plan* pl, const double* u, double* dudt, Workspace ws, hipStream_t s,
+                    const RkEpilogue& epi) {
 #define X(D, PP) \
-  if (pl->dim == D && pl->p == PP) return run_residual<D, PP>(pl, u, dudt, ws, s);
+  if (pl->dim == D && pl->p == PP) return run_residual<D, PP>(pl, u, dudt, ws, s, epi);
   ESD_TRI_DEGREES(X)
   ESD_TET_DEGREES(X)
 #undef X
@@ -515,9 +522,9 @@ int launch_entropy_projection(const esd_plan* pl, const double* u, Workspace ws,
   return -1;
 }
 
-int launch_rhs(const esd_plan* pl, double* dudt, Workspace ws, hipStream_t s) {
+int launch_rhs(const esd_plan* pl, double* dudt, Workspace ws, hipStream_t s, const RkEpilogue& epi) {
 #define X(D, PP) \
-  if (pl->dim == D && pl->p == PP) return run_rhs<D, PP>(pl, dudt, ws, s);
+  if (pl->dim == D && pl->p == PP) return run_rhs<D, PP>(pl, dudt, ws, s, epi);
   ESD_TRI_DEGREES(X)
   ESD_TET_DEGREES(X)
 #undef X
@@ -531,15 +538,6 @@ int launch_project(const esd_plan* pl, const double* un, double* u, hipStream_t 
   ESD_TET_DEGREES(X)
 #undef X
   return -1;
-}
-
-int launch_rk_stage(double* acc, double* U, const double* u, const double* k, double ca, double cu, int first,
-                    int64_t n, hipStream_t s) {
-  const int bs = 256;
-  int64_t nb = (n + bs - 1) / bs;
-  if (nb > 8192) nb = 8192;
-  hipLaunchKernelGGL(k_rk_stage, dim3(nb), dim3(bs), 0, s, acc, U, u, k, ca, cu, first, n);
-  return (int)hipGetLastError();
 }
 
 int launch_axpy(double* y, const double* x, double a, const double* z, int64_t n, hipStream_t s) {

@@ -28,6 +28,19 @@ struct DevTables {
   const double* xl;     // [Q]
 };
 
+// Classical RK4 stage combination fused into the right-hand-side kernel's
+// output (acc == nullptr: plain du~/dt output).  With k = du~/dt of the stage:
+//   stages 1-3:  acc = (first ? u : acc) + ca k,  U = u + cu k
+//   stage 4:     u = acc + ca k   (in place on the state)
+// All pointers address the same state layout as du~/dt.
+struct RkEpilogue {
+  double* u = nullptr;
+  double* acc = nullptr;
+  double* U = nullptr;
+  double ca = 0.0, cu = 0.0;
+  int first = 0, last = 0;
+};
+
 // Scheme constants passed to kernels.
 struct Scheme {
   double gamma;
@@ -119,11 +132,10 @@ struct esd_plan {
 namespace esd {
 // kernel launchers (kernels.hip); return hipError_t as int, or -1 for an
 // unsupported degree
-int launch_residual(const esd_plan* P, const double* u, double* dudt, Workspace ws, hipStream_t s);
+int launch_residual(const esd_plan* P, const double* u, double* dudt, Workspace ws, hipStream_t s,
+                    const RkEpilogue& epi = RkEpilogue());
 int launch_project(const esd_plan* P, const double* u_nodal, double* u, hipStream_t s);
 int launch_axpy(double* y, const double* x, double a, const double* z, int64_t n, hipStream_t s);
-int launch_rk_stage(double* acc, double* U, const double* u, const double* k, double ca, double cu,
-                    int first, int64_t n, hipStream_t s);
 int launch_entropy_projection(const esd_plan* P, const double* u, Workspace ws, hipStream_t s);
 // adjoint.hip
 int launch_vjp(const esd_plan* P, const double* u, const double* vbar, double* grad, Workspace ws,
@@ -132,7 +144,7 @@ int launch_adj_stage(double* acc, double* kb, const double* ubar, const double* 
                      int64_t n, hipStream_t s);
 int launch_scale(double* y, const double* x, double a, int64_t n, hipStream_t s);
 // K2 alone (K1 must have run for every element whose facet values it reads)
-int launch_rhs(const esd_plan* P, double* dudt, Workspace ws, hipStream_t s);
+int launch_rhs(const esd_plan* P, double* dudt, Workspace ws, hipStream_t s, const RkEpilogue& epi = RkEpilogue());
 // batch.hip: exterior facet values of mixed-degree interfaces of one bucket
 int launch_mixed_exterior(const esd_plan* bucket, const esd_plan* top, const double* ws_base, Workspace ws,
                           hipStream_t s);

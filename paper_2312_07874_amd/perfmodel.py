@@ -78,6 +78,15 @@ def k2_bytes(dim: int, p: int) -> int:
     return 8 * (NC * NP + 2 * NC * NFQ + (ngv - 1) * NQ + (dim + 1) * NFQ + NC * NP) + 4 * NFQ
 
 
+def k2_rk_bytes(dim: int, p: int) -> int:
+    """K2 inside an RK4 step, with the stage combination fused into its output:
+    instead of writing du~/dt it reads u and acc and writes acc and U (stage 1
+    skips the acc read, stage 4 reads acc and writes u), 3.25 state arrays on
+    average over the four stages in place of one."""
+    Q, NC, NQ, NP, NQF, NFQ = _sizes(dim, p)
+    return k2_bytes(dim, p) + (8 * NC * NP * 9) // 4
+
+
 def k1_bytes(dim: int, p: int) -> int:
     Q, NC, NQ, NP, NQF, NFQ = _sizes(dim, p)
     return 8 * (NC * NP + 2 * NQ + NC * NP + NC * NFQ)
