@@ -121,7 +121,7 @@ template <int DIM, int P, int FLUX>
 __global__ void __launch_bounds__((VjpLaunch<DIM, P>::BS))
 k_rhs_vjp(const double* __restrict__ wt, const double* __restrict__ wfb, const double* __restrict__ vbar,
           double* __restrict__ gpart, double* __restrict__ xbar, const double* __restrict__ gvol,
-          const double* __restrict__ gfac, const int32_t* __restrict__ conn, DevTables T, Scheme S, int64_t ne,
+          const double* __restrict__ gfac, const int32_t* __restrict__ conn, DevTables T0, Scheme S, int64_t ne,
           int* flag) {
   using Sh = Shape<DIM, P>;
   constexpr int EPB = Launch<DIM, P>::EPB;
@@ -133,6 +133,10 @@ k_rhs_vjp(const double* __restrict__ wt, const double* __restrict__ wfb, const d
   __shared__ double sF[EPB * 8 * NFQ];      // own facet node data; later R^T scratch
   __shared__ double sT[EPB * NC * NFQ];     // t_bar = R r_bar
   __shared__ double sXF[EPB * NC * NFQ];    // x_bar, then w_bar at own facet nodes
+  constexpr unsigned TM =
+      tab_mask<DIM, P, TAB_PSI | TAB_FACET>(8 * EPB * (Sh::SCR + 2 * NC * NQ + 8 * NFQ + 2 * NC * NFQ));
+  __shared__ double sTab[TM ? TabLds<DIM, P, TM>::SIZE : 1];
+  const DevTables T = stage_tables<DIM, P, TM>(T0, sTab);
   const int64_t e0 = (int64_t)blockIdx.x * EPB;
   const int nel = (int)((ne - e0) < EPB ? (ne - e0) : EPB);
   const int nec = nel * NC;
@@ -371,7 +375,7 @@ k_rhs_vjp(const double* __restrict__ wt, const double* __restrict__ wfb, const d
 template <int DIM, int P>
 __global__ void __launch_bounds__((VjpLaunch<DIM, P>::BS))
 k_projection_vjp(const double* __restrict__ u, double* g, const double* __restrict__ xbar,
-                 const double* __restrict__ gvol, const int32_t* __restrict__ conn, DevTables T, Scheme S,
+                 const double* __restrict__ gvol, const int32_t* __restrict__ conn, DevTables T0, Scheme S,
                  int64_t ne) {
   using Sh = Shape<DIM, P>;
   constexpr int EPB = Launch<DIM, P>::EPB;
@@ -381,6 +385,10 @@ k_projection_vjp(const double* __restrict__ u, double* g, const double* __restri
   __shared__ double sA[EPB * NC * NQ];
   __shared__ double sB[EPB * NC * NB];      // gathered facet cotangents, later u at the nodes
   __shared__ double sS[EPB * Sh::SCR];
+  constexpr unsigned TM =
+      tab_mask<DIM, P, TAB_PSI | TAB_FACET>(8 * EPB * (NC * NP + NC * NQ + NC * NB + Sh::SCR));
+  __shared__ double sTab[TM ? TabLds<DIM, P, TM>::SIZE : 1];
+  const DevTables T = stage_tables<DIM, P, TM>(T0, sTab);
   const int64_t e0 = (int64_t)blockIdx.x * EPB;
   const int nel = (int)((ne - e0) < EPB ? (ne - e0) : EPB);
   const int nec = nel * NC;

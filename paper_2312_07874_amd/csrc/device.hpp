@@ -107,13 +107,68 @@ __device__ __forceinline__ void decode_tri_mode(int P, int m, int& a1, int& a2) 
   a2 = m;
 }
 
+// ------------------------------------------------------------------ operator tables in LDS
+// The transforms and the facet extrapolation index psi2, psi3, I42 and the 1D
+// facet weights by a lane-dependent mode or node; as global loads each value
+// costs a vector-memory instruction (a texture-addresser pass over 64 lane
+// addresses), which made the transforms the largest part of both kernels.
+// Kernels copy these tables into LDS at their start (before their first
+// barrier) where LDS allows; psi1 stays in global memory: the transforms index
+// it uniformly, through scalar loads.
+constexpr int LDS_BYTES = 160 * 1024;
+enum : unsigned {
+  TAB_PSI = 1,     // psi2, psi3 (transforms)
+  TAB_FACET = 2,   // I42, lgm1, lgp1, gjm1 (facet extrapolation and lift)
+};
+template <int DIM, int P, unsigned M>
+struct TabLds {
+  static constexpr int Q = P + 1;
+  static constexpr int NPSI = (P + 1) * (P + 1) * Q;
+  static constexpr int SIZE = ((M & TAB_PSI) ? (DIM == 2 ? 1 : 2) * NPSI : 0) + ((M & TAB_FACET) ? Q * Q + 3 * Q : 0);
+};
+// the tables W if a kernel using base_bytes of LDS still fits with them, else none
+template <int DIM, int P, unsigned W>
+constexpr unsigned tab_mask(int base_bytes) {
+  return base_bytes + 8 * TabLds<DIM, P, W>::SIZE <= LDS_BYTES ? W : 0u;
+}
+
+// copies the tables M into buf (TabLds<DIM, P, M>::SIZE doubles of LDS) and
+// returns T with those pointers redirected; no barrier
+template <int DIM, int P, unsigned M>
+__device__ __forceinline__ DevTables stage_tables(const DevTables& T, double* buf) {
+  DevTables R = T;
+  if constexpr (M != 0) {
+    using L = TabLds<DIM, P, M>;
+    constexpr int Q = L::Q;
+    const int tid = threadIdx.x, nth = blockDim.x;
+    int off = 0;
+    auto copy = [&](const double* src, int n) {
+      for (int o = tid; o < n; o += nth) buf[off + o] = src[o];
+      const double* d = buf + off;
+      off += n;
+      return d;
+    };
+    if constexpr ((M & TAB_PSI) != 0) {
+      R.psi2 = copy(T.psi2, L::NPSI);
+      if constexpr (DIM == 3) R.psi3 = copy(T.psi3, L::NPSI);
+    }
+    if constexpr ((M & TAB_FACET) != 0) {
+      R.I42 = copy(T.I42, Q * Q);
+      R.lgm1 = copy(T.lgm1, Q);
+      R.lgp1 = copy(T.lgp1, Q);
+      R.gjm1 = copy(T.gjm1, Q);
+    }
+  }
+  return R;
+}
+
 // ------------------------------------------------------------------ sum-factorised PKD transforms
 // in/out arrays are [nel*NC][...] contiguous per (element, variable); all
 // threads of the block participate; each call ends with a barrier.  Every
 // thread produces a whole line of outputs from one set of LDS loads
 // (register blocking along the contracted direction).
 template <int DIM, int P>
-__device__ void xform_V(const double* uh, double* T1, double* T2, double* out, const DevTables& T, int nec) {
+__device__ __forceinline__ void xform_V(const double* uh, double* T1, double* T2, double* out, const DevTables& T, int nec) {
   using S = Shape<DIM, P>;
   constexpr int Q = S::Q;
   constexpr int XU = Q <= 7 ? Q : 1;   // unroll the contraction while its table fits scalar registers
@@ -218,7 +273,7 @@ __device__ void xform_V(const double* uh, double* T1, double* T2, double* out, c
 }
 
 template <int DIM, int P>
-__device__ void xform_Vt(const double* in, double* T1, double* T2, double* out, const DevTables& T, int nec) {
+__device__ __forceinline__ void xform_Vt(const double* in, double* T1, double* T2, double* out, const DevTables& T, int nec) {
   using S = Shape<DIM, P>;
   constexpr int Q = S::Q;
   constexpr int XU = Q <= 7 ? Q : 1;   // unroll the contraction while its table fits scalar registers

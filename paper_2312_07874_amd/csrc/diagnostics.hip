@@ -37,7 +37,7 @@ __device__ void block_sum(double* red, const double* acc, int nv) {
 template <int DIM, int P>
 __global__ void __launch_bounds__((Launch<DIM, P>::BS))
 k_diag_partials(const double* __restrict__ u, const double* __restrict__ dudt, const double* __restrict__ gvol,
-                double* __restrict__ part, DevTables T, Scheme S, int64_t ne) {
+                double* __restrict__ part, DevTables T0, Scheme S, int64_t ne) {
   using Sh = Shape<DIM, P>;
   constexpr int EPB = Launch<DIM, P>::EPB;
   constexpr int NC = Sh::NC, NQ = Sh::NQ, NP = Sh::NP, NGV = Sh::NGV, NO = NC + 2;
@@ -45,6 +45,10 @@ k_diag_partials(const double* __restrict__ u, const double* __restrict__ dudt, c
   __shared__ double sM[EPB * NC * NP];
   __shared__ double sU[EPB * NC * NQ];
   __shared__ double sS[EPB * Sh::SCR > RED ? EPB * Sh::SCR : RED];   // transform scratch, then reductions
+  constexpr int NS = EPB * Sh::SCR > RED ? EPB * Sh::SCR : RED;
+  constexpr unsigned TM = tab_mask<DIM, P, TAB_PSI>(8 * (EPB * NC * NP + EPB * NC * NQ + NS));
+  __shared__ double sTab[TM ? TabLds<DIM, P, TM>::SIZE : 1];
+  const DevTables T = stage_tables<DIM, P, TM>(T0, sTab);
   const int64_t e0 = (int64_t)blockIdx.x * EPB;
   const int nel = (int)((ne - e0) < EPB ? (ne - e0) : EPB);
   const int nec = nel * NC;

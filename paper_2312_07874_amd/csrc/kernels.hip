@@ -31,13 +31,16 @@ namespace esd {
 template <int DIM, int P, bool PROJECT_ONLY>
 __global__ void __launch_bounds__((Launch<DIM, P>::BSMAX))
 k_entropy_projection(const double* __restrict__ u, double* __restrict__ wt, double* __restrict__ wf,
-                     const double* __restrict__ gvol, DevTables T, Scheme S, int64_t ne, int* flag) {
+                     const double* __restrict__ gvol, DevTables T0, Scheme S, int64_t ne, int* flag) {
   using Sh = Shape<DIM, P>;
   constexpr int EPB = Launch<DIM, P>::EPB;
   constexpr int Q = Sh::Q, NC = Sh::NC, NQ = Sh::NQ, NP = Sh::NP, NQF = Sh::NQF, NFQ = Sh::NFQ, NGV = Sh::NGV;
   __shared__ double sM[EPB * NC * NP];
   __shared__ double sA[EPB * NC * NQ];
   __shared__ double sS[EPB * Sh::SCR];
+  constexpr unsigned TM = tab_mask<DIM, P, TAB_PSI | TAB_FACET>(8 * EPB * (NC * NP + NC * NQ + Sh::SCR));
+  __shared__ double sTab[TM ? TabLds<DIM, P, TM>::SIZE : 1];
+  const DevTables T = stage_tables<DIM, P, TM>(T0, sTab);
   const int64_t e0 = (int64_t)blockIdx.x * EPB;
   const int nel = (int)((ne - e0) < EPB ? (ne - e0) : EPB);
   const int nec = nel * NC;
@@ -177,7 +180,7 @@ template <int DIM, int P, int FLUX>
 __global__ void __launch_bounds__((Launch<DIM, P>::BSMAX))
 k_rhs(const double* __restrict__ wt, const double* __restrict__ wfb, double* __restrict__ dudt,
       const double* __restrict__ gvol, const double* __restrict__ gfac, const int32_t* __restrict__ conn,
-      DevTables T, Scheme S, int64_t ne, int* flag, double* frec, RkEpilogue epi) {
+      DevTables T0, Scheme S, int64_t ne, int* flag, double* frec, RkEpilogue epi) {
   using Sh = Shape<DIM, P>;
   constexpr int EPB = Launch<DIM, P>::EPB;
   constexpr int Q = Sh::Q, NC = Sh::NC, NQ = Sh::NQ, NP = Sh::NP, NQF = Sh::NQF, NFQ = Sh::NFQ, NGV = Sh::NGV;
@@ -189,6 +192,19 @@ k_rhs(const double* __restrict__ wt, const double* __restrict__ wfb, double* __r
   __shared__ double sR[EPB * NC * NQ];      // w at nodes, then r
   __shared__ double sF[FLDS ? EPB * 8 * NFQ : 1];   // own facet node records (LDS case)
   __shared__ double sT[EPB * NC * NFQ];     // C^T 1, then s = B J_f f* - C^T 1
+  // psi tables in LDS: tetrahedra keep them in the tail of sF beyond the modal
+  // staging, free during both transform phases (copied again once the facet
+  // records are dead), so the kernel's LDS and occupancy do not grow;
+  // triangles in an array of their own
+  constexpr int TPSI = TabLds<DIM, P, TAB_PSI>::SIZE;
+  constexpr bool TAB_SF = DIM == 3 && FLDS && 8 * NFQ >= NC * NP + TPSI;
+  static_assert(!TAB_SF || EPB == 1, "one element per workgroup when the tables share sF");
+  constexpr unsigned TM =
+      DIM == 2 ? tab_mask<DIM, P, TAB_PSI>(8 * (EPB * (Sh::SCR + NC * NQ + NC * NFQ) + (FLDS ? EPB * 8 * NFQ : 1)))
+               : (TAB_SF ? TAB_PSI : 0u);
+  __shared__ double sTab[DIM == 2 && TM ? TPSI : 1];
+  double* const tab_buf = TAB_SF ? sF + NC * NP : sTab;
+  const DevTables T = stage_tables<DIM, P, TM>(T0, tab_buf);
   static_assert(FLDS ? 8 * NFQ >= NC * NP : NFQ >= NP, "modal staging must fit the facet buffers");
   // modal w~ before the facet data exist, du~/dt after they are dead
   double* sM = FLDS ? sF : sT;
@@ -363,6 +379,7 @@ k_rhs(const double* __restrict__ wt, const double* __restrict__ wfb, double* __r
   }
   if (bad) atomicOr(flag, 1);
   __syncthreads();
+  if constexpr (TAB_SF) (void)stage_tables<DIM, P, TM>(T0, tab_buf);   // over the dead facet records
 
   // ---- r -= R^T s
   facet_lift<DIM, P>(sT, lift_scratch, T, nec, [&](int o, double d) { sR[o] -= d; });
