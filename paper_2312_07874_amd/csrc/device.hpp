@@ -172,6 +172,9 @@ __device__ __forceinline__ void xform_V(const double* uh, double* T1, double* T2
   using S = Shape<DIM, P>;
   constexpr int Q = S::Q;
   constexpr int XU = Q <= 7 ? Q : 1;   // unroll the contraction while its table fits scalar registers
+  // stages whose table is indexed per lane (read from LDS) unroll one degree
+  // further on tetrahedra (measured: K1 at p = 7 2.49 -> 2.19 ms; p = 8 unchanged)
+  constexpr int XL = (DIM == 3 && Q <= 8) ? Q : XU;
   const int tid = threadIdx.x, nth = blockDim.x;
   if constexpr (DIM == 2) {
     // T1[ec][a1][i2] = sum_a2 psi2[a1][a2][i2] u~[ec][(a1,a2)]
@@ -181,7 +184,7 @@ __device__ __forceinline__ void xform_V(const double* uh, double* T1, double* T2
       double acc[Q];
 #pragma unroll
       for (int i = 0; i < Q; ++i) acc[i] = 0.0;
-#pragma unroll XU
+#pragma unroll XL
       for (int a2 = 0; a2 <= P; ++a2) {
         if (a2 <= P - a1) {
           const double x = uh[ec * S::NP + mb + a2];
@@ -220,7 +223,7 @@ __device__ __forceinline__ void xform_V(const double* uh, double* T1, double* T2
       double acc[Q];
 #pragma unroll
       for (int i = 0; i < Q; ++i) acc[i] = 0.0;
-#pragma unroll XU
+#pragma unroll XL
       for (int a3 = 0; a3 <= P; ++a3) {
         if (a3 <= P - s) {
           const double x = uh[ec * S::NP + mb + a3];
@@ -240,7 +243,7 @@ __device__ __forceinline__ void xform_V(const double* uh, double* T1, double* T2
       double acc[Q];
 #pragma unroll
       for (int i = 0; i < Q; ++i) acc[i] = 0.0;
-#pragma unroll XU
+#pragma unroll XL
       for (int a2 = 0; a2 <= P; ++a2) {
         if (a2 <= P - a1) {
           const double x = T1[(ec * S::NPAIR + pb + a2) * Q + i3];
@@ -277,6 +280,9 @@ __device__ __forceinline__ void xform_Vt(const double* in, double* T1, double* T
   using S = Shape<DIM, P>;
   constexpr int Q = S::Q;
   constexpr int XU = Q <= 7 ? Q : 1;   // unroll the contraction while its table fits scalar registers
+  // stages whose table is indexed per lane (read from LDS) unroll one degree
+  // further on tetrahedra (measured: K1 at p = 7 2.49 -> 2.19 ms; p = 8 unchanged)
+  constexpr int XL = (DIM == 3 && Q <= 8) ? Q : XU;
   const int tid = threadIdx.x, nth = blockDim.x;
   if constexpr (DIM == 2) {
     // T1[ec][a1][i2] = sum_i1 psi1[a1][i1] in[ec][i1 + Q i2]
@@ -302,7 +308,7 @@ __device__ __forceinline__ void xform_Vt(const double* in, double* T1, double* T
       double acc[P + 1];
 #pragma unroll
       for (int a = 0; a <= P; ++a) acc[a] = 0.0;
-#pragma unroll XU
+#pragma unroll XL
       for (int i2 = 0; i2 < Q; ++i2) {
         const double x = T1[(ec * (P + 1) + a1) * Q + i2];
 #pragma unroll
@@ -337,7 +343,7 @@ __device__ __forceinline__ void xform_Vt(const double* in, double* T1, double* T
       double acc[P + 1];
 #pragma unroll
       for (int a = 0; a <= P; ++a) acc[a] = 0.0;
-#pragma unroll XU
+#pragma unroll XL
       for (int i2 = 0; i2 < Q; ++i2) {
         const double x = T2[(ec * (P + 1) + a1) * Q * Q + i2 + Q * i3];
 #pragma unroll
@@ -357,7 +363,7 @@ __device__ __forceinline__ void xform_Vt(const double* in, double* T1, double* T
       double acc[P + 1];
 #pragma unroll
       for (int a = 0; a <= P; ++a) acc[a] = 0.0;
-#pragma unroll XU
+#pragma unroll XL
       for (int i3 = 0; i3 < Q; ++i3) {
         const double x = T1[(ec * S::NPAIR + pr) * Q + i3];
 #pragma unroll
@@ -370,6 +376,33 @@ __device__ __forceinline__ void xform_Vt(const double* in, double* T1, double* T
     __syncthreads();
   }
 }
+
+// ------------------------------------------------------------------ loads issued ahead of their use
+// Values of a block-strided loop over n items (o = tid, tid + nth, ...) for
+// this thread's first PF iterations, loaded before the phases that precede
+// their use so that their latency overlaps that work.
+template <int PF>
+struct Ahead {
+  double v[PF];
+  template <typename Load>
+  __device__ __forceinline__ void load(int n, Load ld) {
+#pragma unroll
+    for (int it = 0; it < PF; ++it) {
+      const int o = (int)threadIdx.x + it * (int)blockDim.x;
+      v[it] = o < n ? ld(o) : 0.0;
+    }
+  }
+  // body(o, value of o) over the whole loop; iterations past PF load directly
+  template <typename Load, typename Body>
+  __device__ __forceinline__ void each(int n, Load ld, Body body) const {
+#pragma unroll
+    for (int it = 0; it < PF; ++it) {
+      const int o = (int)threadIdx.x + it * (int)blockDim.x;
+      if (o < n) body(o, v[it]);
+    }
+    for (int o = (int)threadIdx.x + PF * (int)blockDim.x; o < n; o += blockDim.x) body(o, ld(o));
+  }
+};
 
 // ------------------------------------------------------------------ node data in LDS
 // node data layout in LDS: [8][stride] = rho, ln rho, b = rho/p, ln b, p, v1, v2, v3

@@ -55,12 +55,19 @@ k_entropy_projection(const double* __restrict__ u, double* __restrict__ wt, doub
       sA[(el * NC + c) * NQ + k] = wJ * u[(e0 * NQ) * NC + o];
     }
     __syncthreads();
-  } else {
+  }
+  // w J and w/J at this thread's nodes, used after the first transforms
+  auto ld_wJ = [&](int o) { return gvol[((e0 + o / NQ) * NGV + NGV - 2) * NQ + o % NQ]; };
+  auto ld_wi = [&](int o) { return gvol[((e0 + o / NQ) * NGV + NGV - 1) * NQ + o % NQ]; };
+  Ahead<2> aJ, aI;
+  if constexpr (!PROJECT_ONLY) aJ.load(nel * NQ, ld_wJ);
+  aI.load(nel * NQ, ld_wi);
+  if constexpr (!PROJECT_ONLY) {
     for (int o = tid; o < nec * NP; o += nth) sM[o] = u[e0 * NC * NP + o];
     __syncthreads();
     xform_V<DIM, P>(sM, T1, T2, sA, T, nec);
     // entropy variables times w J at every volume node
-    for (int o = tid; o < nel * NQ; o += nth) {
+    aJ.each(nel * NQ, ld_wJ, [&](int o, double wJ) {
       const int k = o % NQ, el = o / NQ;
       double* a = sA + el * NC * NQ;
       const double rho = a[k];
@@ -73,21 +80,21 @@ k_entropy_projection(const double* __restrict__ u, double* __restrict__ wt, doub
       const double p = (S.gamma - 1.0) * (a[(DIM + 1) * NQ + k] - 0.5 * rho * v2);
       if (!(rho > 0.0) || !(p > 0.0) || !isfinite(rho) || !isfinite(p)) atomicOr(flag, 1);
       const double s = log(p) - S.gamma * log(rho);
-      const double wJ = gvol[((e0 + el) * NGV + NGV - 2) * NQ + k];
       a[k] = wJ * ((S.gamma - s) * S.gm1_inv - 0.5 * rho * v2 / p);
 #pragma unroll
       for (int i = 0; i < DIM; ++i) a[(1 + i) * NQ + k] = wJ * (rho * v[i] / p);
       a[(DIM + 1) * NQ + k] = wJ * (-rho / p);
-    }
+    });
     __syncthreads();
   }
   // weight-adjusted projection: V^T (w/J) V V^T (w J W)
   xform_Vt<DIM, P>(sA, T1, T2, sM, T, nec);
   xform_V<DIM, P>(sM, T1, T2, sA, T, nec);
-  for (int o = tid; o < nec * NQ; o += nth) {
-    const int k = o % NQ, el = o / (NC * NQ);
-    sA[o] *= gvol[((e0 + el) * NGV + NGV - 1) * NQ + k];
-  }
+  aI.each(nel * NQ, ld_wi, [&](int o, double wi) {
+    const int k = o % NQ, el = o / NQ;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) sA[(el * NC + c) * NQ + k] *= wi;
+  });
   __syncthreads();
   xform_Vt<DIM, P>(sA, T1, T2, sM, T, nec);
   for (int o = tid; o < nec * NP; o += nth) wt[e0 * NC * NP + o] = sM[o];
@@ -380,6 +387,13 @@ k_rhs(const double* __restrict__ wt, const double* __restrict__ wfb, double* __r
   if (bad) atomicOr(flag, 1);
   __syncthreads();
   if constexpr (TAB_SF) (void)stage_tables<DIM, P, TM>(T0, tab_buf);   // over the dead facet records
+  auto ld_wi = [&](int o) { return gvol[((e0 + o / NQ) * NGV + NGV - 1) * NQ + o % NQ]; };
+  auto ld_u = [&](int o) { return epi.u[e0 * NC * NP + o]; };
+  auto ld_acc = [&](int o) { return epi.acc[e0 * NC * NP + o]; };
+  Ahead<2> aI, aU, aA;
+  aI.load(nel * NQ, ld_wi);
+  if (epi.acc != nullptr && !epi.last) aU.load(nec * NP, ld_u);
+  if (epi.acc != nullptr && !epi.first) aA.load(nec * NP, ld_acc);
 
   // ---- r -= R^T s
   facet_lift<DIM, P>(sT, lift_scratch, T, nec, [&](int o, double d) { sR[o] -= d; });
@@ -388,26 +402,44 @@ k_rhs(const double* __restrict__ wt, const double* __restrict__ wfb, double* __r
   // ---- du~/dt = V^T (w/J) V V^T r
   xform_Vt<DIM, P>(sR, T1, T2, sM, T, nec);
   xform_V<DIM, P>(sM, T1, T2, sR, T, nec);
-  for (int o = tid; o < nec * NQ; o += nth) {
-    const int k = o % NQ, le = o / (NC * NQ);
-    sR[o] *= gvol[((e0 + le) * NGV + NGV - 1) * NQ + k];
-  }
+  aI.each(nel * NQ, ld_wi, [&](int o, double wi) {
+    const int k = o % NQ, el = o / NQ;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) sR[(el * NC + c) * NQ + k] *= wi;
+  });
   __syncthreads();
   xform_Vt<DIM, P>(sR, T1, T2, sM, T, nec);
   if (epi.acc == nullptr) {
     for (int o = tid; o < nec * NP; o += nth) dudt[e0 * NC * NP + o] = sM[o];
   } else if (!epi.last) {
-    for (int o = tid; o < nec * NP; o += nth) {
-      const int64_t i = e0 * NC * NP + o;
-      const double k = sM[o], ui = epi.u[i];
-      epi.acc[i] = (epi.first ? ui : epi.acc[i]) + epi.ca * k;
-      epi.U[i] = ui + epi.cu * k;
+    if (epi.first) {
+      aU.each(nec * NP, ld_u, [&](int o, double ui) {
+        const int64_t i = e0 * NC * NP + o;
+        const double k = sM[o];
+        epi.acc[i] = ui + epi.ca * k;
+        epi.U[i] = ui + epi.cu * k;
+      });
+    } else {
+      // both arrays ahead: walk the iterations by hand
+#pragma unroll
+      for (int it = 0; it < 2; ++it) {
+        const int o = tid + it * nth;
+        if (o < nec * NP) {
+          const int64_t i = e0 * NC * NP + o;
+          const double k = sM[o];
+          epi.acc[i] = aA.v[it] + epi.ca * k;
+          epi.U[i] = aU.v[it] + epi.cu * k;
+        }
+      }
+      for (int o = tid + 2 * nth; o < nec * NP; o += nth) {
+        const int64_t i = e0 * NC * NP + o;
+        const double k = sM[o], ui = epi.u[i];
+        epi.acc[i] = epi.acc[i] + epi.ca * k;
+        epi.U[i] = ui + epi.cu * k;
+      }
     }
   } else {
-    for (int o = tid; o < nec * NP; o += nth) {
-      const int64_t i = e0 * NC * NP + o;
-      epi.u[i] = epi.acc[i] + epi.ca * sM[o];
-    }
+    aA.each(nec * NP, ld_acc, [&](int o, double ai) { epi.u[e0 * NC * NP + o] = ai + epi.ca * sM[o]; });
   }
 }
 
