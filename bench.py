@@ -95,28 +95,34 @@ def run_gpu(name: str, steps: int, warmup: int, autotune: bool = True):
     blocks = plan.tuning()
     blocks_k1 = plan.tuning_k1()
     dt = 1e-4
-    for _ in range(warmup):
-        plan.rk4(u, dt, 1)
+    if warmup:
+        plan.rk4(u, dt, warmup)
     torch.cuda.synchronize()
     plan.sync_status()
     plan.set_timing(True)
     plan.get_timing()
     torch.cuda.synchronize()
+    # the timed steps: one call (one projection of u, then per stage one kernel
+    # that forms the stage combination and projects the next stage input)
     t0 = time.perf_counter()
-    for _ in range(steps):
-        plan.rk4(u, dt, 1)
+    plan.rk4(u, dt, steps)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     plan.set_timing(False)
     k1_ms, k2_ms, nlaunch = plan.get_timing()
     plan.sync_status()
+    fused = plan.tuning_fused()
     info = plan.info
     n_res = 4 * steps
     d, p = wk.dim, wk.degree
     k2_avg_s = k2_ms / nlaunch * 1e-3
-    k1_avg_s = k1_ms / nlaunch * 1e-3
+    res_k1_ms, res_k2_ms = time_residual_kernels(plan, u)
+    # the dominant kernel of a stage: K2 forming the stage combination, and,
+    # with fused stages, projecting the next stage input
     fl = pm.k2_flops(d, p, wk.ecflux, wk.dissipation) * info.n_elements
-    by = pm.k2_rk_bytes(d, p) * info.n_elements
+    if fused:
+        fl += pm.k1_flops(d, p) * info.n_elements
+    by = (pm.k2_next_bytes(d, p) if fused else pm.k2_rk_bytes(d, p)) * info.n_elements
     t_fl = fl / (pm.PEAK_FP64_TFLOPS * 1e12)
     t_by = by / (pm.PEAK_HBM_GBS * 1e9)
     if t_fl >= t_by:
@@ -125,7 +131,8 @@ def run_gpu(name: str, steps: int, warmup: int, autotune: bool = True):
         roof = {"bound": "hbm", "achieved": by / k2_avg_s / 1e9, "peak": pm.PEAK_HBM_GBS, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["traffic"] = measured_traffic(name)
-    roof["kernel"] = "k_rhs (K2, RK4 stage fused)"
+    roof["kernel"] = ("k_rhs<..., true> (RK4 stage: right-hand side, stage combination, next projection)" if fused
+                      else "k_rhs<..., false> (RK4 stage: right-hand side and stage combination; K1 separate)")
     roof["algorithmic_flops_per_launch"] = fl
     roof["algorithmic_bytes_per_launch"] = by
     roof["avg_launch_ms"] = k2_avg_s * 1e3
@@ -138,18 +145,38 @@ def run_gpu(name: str, steps: int, warmup: int, autotune: bool = True):
         "dof": info.n_dof,
         "value": n_res * info.n_dof / elapsed,
         "ms_per_step": elapsed / steps * 1e3,
-        "ms_per_residual_k1_k2": (k1_ms + k2_ms) / nlaunch,
-        "k1_avg_ms": k1_avg_s * 1e3,
-        "k2_avg_ms": k2_avg_s * 1e3,
+        "rk4_stages_fused": fused,
+        "ms_per_stage_kernel": k2_avg_s * 1e3,
+        "ms_per_stage_k1": k1_ms / nlaunch,
+        "ms_per_residual_k1_k2": res_k1_ms + res_k2_ms,
+        "k1_avg_ms": res_k1_ms,
+        "k2_avg_ms": res_k2_ms,
         "flux_pairs_per_s": n_res * info.flux_pairs_paper / elapsed,
         "flux_pairs_distinct_per_s": n_res * info.flux_pairs_distinct / elapsed,
         "roofline": roof,
-        "k1_flop_rate_tflops": pm.k1_flops(d, p) * info.n_elements / k1_avg_s / 1e12,
+        "k1_flop_rate_tflops": pm.k1_flops(d, p) * info.n_elements / res_k1_ms / 1e9,
         "vjp": vjp,
         "k2_block_autotuned": blocks[0],
         "k1_block_autotuned": blocks_k1[0],
         "ms_per_step_graph": graph_ms,
     }
+
+
+def time_residual_kernels(plan, u, reps: int = 5):
+    """K1 and K2 of the plain residual (esd_residual), from HIP events around
+    each launch: (K1 ms, K2 ms) averages."""
+    import torch
+
+    out = torch.empty_like(u)
+    plan.residual(u, out)
+    torch.cuda.synchronize()
+    plan.set_timing(True)
+    plan.get_timing()
+    for _ in range(reps):
+        plan.residual(u, out)
+    k1, k2, n = plan.get_timing()
+    plan.set_timing(False)
+    return k1 / n, k2 / n
 
 
 def time_graph_steps(plan, u, dt, steps):
@@ -211,19 +238,19 @@ def run_batched(steps: int, warmup: int):
     plan.sync_status()
     blocks = plan.autotune(u)
     dt = 1e-4
-    for _ in range(warmup):
-        plan.rk4(u, dt, 1)
+    if warmup:
+        plan.rk4(u, dt, warmup)
     torch.cuda.synchronize()
     plan.set_timing(True)
     plan.get_timing()
     t0 = time.perf_counter()
-    for _ in range(steps):
-        plan.rk4(u, dt, 1)
+    plan.rk4(u, dt, steps)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     plan.set_timing(False)
-    k1_ms, k2_ms, nres = plan.get_timing()
+    stage_k1_ms, stage_ms, nstage = plan.get_timing()
     plan.sync_status()
+    res_k1_ms, res_k2_ms = time_residual_kernels(plan, u)
     graph_ms = time_graph_steps(plan, u, dt, steps)
     n_res = 4 * steps
     return {
@@ -233,9 +260,11 @@ def run_batched(steps: int, warmup: int):
         "buckets": [[b["degree"], int(b["n_elements"])] for b in plan.buckets],
         "value": n_res * plan.info.n_dof / elapsed,
         "ms_per_step": elapsed / steps * 1e3,
-        "ms_per_residual_k1_k2": (k1_ms + k2_ms) / nres,
-        "k1_and_interfaces_avg_ms": k1_ms / nres,
-        "k2_all_buckets_avg_ms": k2_ms / nres,
+        "rk4_stages_fused": plan.tuning_fused(),
+        "ms_per_stage_all_buckets": (stage_k1_ms + stage_ms) / nstage,
+        "ms_per_residual_k1_k2": res_k1_ms + res_k2_ms,
+        "k1_and_interfaces_avg_ms": res_k1_ms,
+        "k2_all_buckets_avg_ms": res_k2_ms,
         "flux_pairs_per_s": n_res * plan.info.flux_pairs_paper / elapsed,
         "k2_blocks_autotuned": blocks,
         "ms_per_step_graph": graph_ms,
@@ -316,6 +345,8 @@ def main():
                    "step": "one classical RK4 step (4 residual evaluations + stage combinations)"},
         "flux_pairs_per_s": main_res["flux_pairs_per_s"],
         "flux_pairs_distinct_per_s": main_res["flux_pairs_distinct_per_s"],
+        "rk4_stages_fused": main_res["rk4_stages_fused"],
+        "ms_per_stage_kernel": main_res["ms_per_stage_kernel"],
         "ms_per_residual_k1_k2": main_res["ms_per_residual_k1_k2"],
         "ms_per_step_graph": main_res["ms_per_step_graph"],
         "k1_avg_ms": main_res["k1_avg_ms"],

@@ -184,24 +184,39 @@ esd_status esd_residual(const esd_plan* plan, const double* u_dev, double* dudt_
                         void* ws_dev, void* stream);
 
 /* nsteps steps of classical four-stage Runge-Kutta with step dt, in place on
- * u_dev.  ws_dev holds info.rk4_workspace_bytes.  If stage_ckpt_dev is not NULL
- * it receives the four stage inputs U1..U4 of every step, [4*nsteps][n_dof]. */
+ * u_dev.  ws_dev holds info.rk4_workspace_bytes (two residual workspaces and
+ * three state-sized buffers).  Every stage is the residual (K1 entropy
+ * projection, K2 right-hand side) with the stage combination formed by K2.
+ * With fused stages (esd_plan_set_fused) and no checkpoints, the call projects
+ * u once and then runs every stage as one right-hand-side launch per bucket
+ * that also projects the next stage input, alternating between the two
+ * residual workspaces.  If stage_ckpt_dev is not NULL it receives the four
+ * stage inputs U1..U4 of every step, [4*nsteps][n_dof] (stages then unfused). */
 esd_status esd_rk4(const esd_plan* plan, double* u_dev, double dt, int32_t nsteps,
                    void* ws_dev, double* stage_ckpt_dev, void* stream);
 
 /* RK4 execution: without checkpoints and with timing off, esd_rk4 captures one
- * step (every residual launch and stage combination) into a HIP graph on the
+ * step (its four stage launches per bucket) into a HIP graph on the
  * plan's own stream at the first call for a given (u_dev, ws_dev, dt), and
  * replays it nsteps times, ordered after the caller's stream by events.
  * esd_plan_set_graphs(plan, 0) launches every kernel individually instead. */
 esd_status esd_plan_set_graphs(esd_plan* plan, int32_t enable);
 
+/* Whether esd_rk4 fuses each stage's right-hand side with the next stage's
+ * entropy projection (one launch per stage and bucket instead of two; the
+ * projection then runs at the right-hand-side kernel's occupancy).  Default:
+ * fused for triangles; esd_plan_autotune keeps the faster of the two. */
+esd_status esd_plan_set_fused(esd_plan* plan, int32_t enable);
+
 /* Chooses the block sizes of the right-hand-side kernel (K2) and of the
  * entropy-projection kernel (K1) for every bucket by timing the candidates
- * (multiples of 64 up to their compiled bound) on the state u_dev; ws_dev holds
- * info.rk4_workspace_bytes.  Synchronises.  The choice is kept by the plan and
- * reported by esd_plan_get_tuning: k2_block[bucket], and, when capacity allows
- * 2 n_buckets entries, the K1 block sizes in k2_block[n_buckets + bucket]. */
+ * (multiples of 64 up to their compiled bound) on the state u_dev, then
+ * whether RK4 stages are fused (esd_plan_set_fused) by timing a step both ways
+ * on a copy of u_dev; ws_dev holds info.rk4_workspace_bytes.  Synchronises.
+ * The choice is kept by the plan and reported by esd_plan_get_tuning:
+ * k2_block[bucket], and, when capacity allows 2 n_buckets entries, the K1 block
+ * sizes in k2_block[n_buckets + bucket], and with one more entry the fusion
+ * flag (1 fused) in k2_block[2 n_buckets]. */
 esd_status esd_plan_autotune(esd_plan* plan, const double* u_dev, void* ws_dev, void* stream);
 esd_status esd_plan_get_tuning(const esd_plan* plan, int32_t* k2_block, int32_t capacity);
 
@@ -247,10 +262,11 @@ esd_status esd_diagnostics(const esd_plan* plan, const double* u_dev, double* ou
 esd_status esd_sync_status(const esd_plan* plan, void* stream);
 
 /* Kernel timing for measurement: when enabled, every K1 (entropy projection)
- * and K2 (right-hand side) launch of esd_residual / esd_rk4 is bracketed by
- * HIP events on the stream it is launched on.  esd_plan_get_timing
- * synchronises, returns the summed milliseconds and launch counts since the
- * last reset, and resets them.  Timing is off by default. */
+ * and K2 (right-hand side) launch of esd_residual is bracketed by HIP events
+ * on the stream it is launched on, and so is every stage of esd_rk4 (counted
+ * as K2, its fused kernels including the next projection, with K1 time 0).
+ * esd_plan_get_timing synchronises, returns the summed milliseconds and launch
+ * counts since the last reset, and resets them.  Timing is off by default. */
 esd_status esd_plan_set_timing(esd_plan* plan, int32_t enable);
 esd_status esd_plan_get_timing(esd_plan* plan, double* k1_ms, double* k2_ms, int64_t* launches);
 

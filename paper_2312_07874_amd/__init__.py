@@ -88,6 +88,7 @@ EXPORTS = {
     "esd_diagnostics": (_c, [_vp, _vp, ctypes.POINTER(ctypes.c_double), _vp, _vp]),
     "esd_sync_status": (_c, [_vp, _vp]),
     "esd_plan_set_graphs": (_c, [_vp, ctypes.c_int32]),
+    "esd_plan_set_fused": (_c, [_vp, ctypes.c_int32]),
     "esd_plan_autotune": (_c, [_vp, _vp, _vp, _vp]),
     "esd_plan_get_tuning": (_c, [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]),
     "esd_plan_set_timing": (_c, [_vp, ctypes.c_int32]),
@@ -259,6 +260,10 @@ class Plan:
     def set_graphs(self, enable: bool):
         _check(_lib.esd_plan_set_graphs(self._h, 1 if enable else 0), "esd_plan_set_graphs")
 
+    def set_fused(self, enable: bool):
+        """RK4 stages as one launch that also projects the next stage input."""
+        _check(_lib.esd_plan_set_fused(self._h, int(bool(enable))), "esd_plan_set_fused")
+
     def autotune(self, u):
         """Times the right-hand-side block-size candidates of every bucket on u
         and keeps the fastest; returns the chosen block sizes."""
@@ -277,6 +282,13 @@ class Plan:
     def tuning_k1(self):
         self.tuning()
         return self._k1_blocks
+
+    def tuning_fused(self) -> bool:
+        """Whether RK4 stages are fused (as set at creation, by autotune or set_fused)."""
+        nb = len(getattr(self, "buckets", [None]))
+        buf = (ctypes.c_int32 * (2 * nb + 1))()
+        _check(_lib.esd_plan_get_tuning(self._h, buf, 2 * nb + 1), "esd_plan_get_tuning")
+        return bool(buf[2 * nb])
 
     def set_timing(self, enable: bool):
         _check(_lib.esd_plan_set_timing(self._h, 1 if enable else 0), "esd_plan_set_timing")

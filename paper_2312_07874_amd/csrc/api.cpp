@@ -139,7 +139,8 @@ esd_status create_single(const esd_mesh_desc* mesh, const esd_scheme_desc* schem
     P->frec_bytes = esd::needs_facet_records(P->dim, P->p)
                         ? align256((size_t)P->ne * 8 * R.NFQ * sizeof(double)) : 0;
     P->ws_bytes = align256(ndof * sizeof(double)) + fbytes + P->frec_bytes;
-    P->rk_ws_bytes = P->ws_bytes + 3 * align256(ndof * sizeof(double));
+    P->rk_ws_bytes = 2 * P->ws_bytes + 3 * align256(ndof * sizeof(double));
+    P->fuse_next = P->dim == 2;
     P->vjp_ws_bytes = P->ws_bytes + fbytes;
     P->rk_vjp_ws_bytes = P->vjp_ws_bytes + 3 * align256(ndof * sizeof(double));
     if (P->host_only) {
@@ -427,7 +428,8 @@ esd_status esd_plan_create_batched(const esd_batch_desc* d, const esd_scheme_des
     P->ne = first.back();
     const size_t ndof = (size_t)P->dof_off.back();
     P->ws_bytes = ws;
-    P->rk_ws_bytes = ws + 3 * align256(ndof * sizeof(double));
+    P->rk_ws_bytes = 2 * ws + 3 * align256(ndof * sizeof(double));
+    P->fuse_next = dim == 2;
     P->vjp_ws_bytes = P->rk_vjp_ws_bytes = 0;
     if (!host_only) {
       if (hipGetDevice(&P->device) != hipSuccess) return bail(ESD_EHIP, "no HIP device");
@@ -725,11 +727,100 @@ static int rk4_step(const esd_plan* P, double* u_dev, double dt, void* ws_dev, d
   return 0;
 }
 
+// entropy projection of u into the residual workspace ws (K1 of every bucket
+// and, for a batched plan, the mixed-interface exterior values)
+static int project_all(const esd_plan* P, const double* u, void* ws, hipStream_t s) {
+  if (!P->batched) return esd::launch_entropy_projection(P, u, split_ws(P, ws), s);
+  const int nb = (int)P->sub.size();
+  for (int b = 0; b < nb; ++b) {
+    const int rc = esd::launch_entropy_projection(P->sub[b], u + P->dof_off[b],
+                                                  split_ws(P->sub[b], (char*)ws + P->ws_off[b]), s);
+    if (rc != 0) return rc;
+  }
+  for (int b = 0; b < nb; ++b) {
+    const int rc = esd::launch_mixed_exterior(P->sub[b], P, (const double*)ws,
+                                              split_ws(P->sub[b], (char*)ws + P->ws_off[b]), s);
+    if (rc != 0) return rc;
+  }
+  return 0;
+}
+
+// one RK4 stage as right-hand-side kernels that also project the next stage
+// input: reads the projection in cur, writes the next one to nxt
+static int fused_stage(const esd_plan* P, void* cur, void* nxt, const esd::RkEpilogue& epi, hipStream_t s) {
+  if (P->timing) {
+    esd::timing_event(P, s);
+    esd::timing_event(P, s);
+  }
+  if (!P->batched) {
+    esd::RkEpilogue e = epi;
+    const esd::Workspace wn = split_ws(P, nxt);
+    e.wt_next = wn.wt;
+    e.wf_next = wn.wf;
+    const int rc = esd::launch_rhs(P, nullptr, split_ws(P, cur), s, e);
+    if (rc != 0) return rc;
+  } else {
+    const int nb = (int)P->sub.size();
+    for (int b = 0; b < nb; ++b) {
+      esd::RkEpilogue e = shift(epi, P->dof_off[b]);
+      const esd::Workspace wn = split_ws(P->sub[b], (char*)nxt + P->ws_off[b]);
+      e.wt_next = wn.wt;
+      e.wf_next = wn.wf;
+      const int rc = esd::launch_rhs(P->sub[b], nullptr, split_ws(P->sub[b], (char*)cur + P->ws_off[b]), s, e);
+      if (rc != 0) return rc;
+    }
+    for (int b = 0; b < nb; ++b) {
+      const int rc = esd::launch_mixed_exterior(P->sub[b], P, (const double*)nxt,
+                                                split_ws(P->sub[b], (char*)nxt + P->ws_off[b]), s);
+      if (rc != 0) return rc;
+    }
+  }
+  if (P->timing) esd::timing_event(P, s);
+  return 0;
+}
+
+// one RK4 step from the projection of u held in the first residual workspace
+// (A); the stages alternate between A and a second one (B) at the end of the
+// RK workspace, and the last stage leaves the projection of the new u in A
+static int rk4_step_fused(const esd_plan* P, double* u_dev, double dt, void* ws_dev, hipStream_t s) {
+  const int64_t n = total_dof(P);
+  const size_t nb = align256((size_t)n * sizeof(double));
+  double* acc = (double*)((char*)ws_dev + P->ws_bytes + 2 * nb);
+  void* A = ws_dev;
+  void* B = (char*)ws_dev + P->ws_bytes + 3 * nb;
+  const double ca[4] = {dt / 6.0, dt / 3.0, dt / 3.0, dt / 6.0};
+  const double cu[4] = {0.5 * dt, 0.5 * dt, dt, 0.0};
+  for (int stg = 0; stg < 4; ++stg) {
+    esd::RkEpilogue epi;
+    epi.u = u_dev;
+    epi.acc = acc;
+    epi.ca = ca[stg];
+    epi.cu = cu[stg];
+    epi.first = stg == 0;
+    epi.last = stg == 3;
+    const int rc = fused_stage(P, stg % 2 == 0 ? A : B, stg % 2 == 0 ? B : A, epi, s);
+    if (rc != 0) return rc;
+  }
+  return 0;
+}
+
+// nsteps RK4 steps launched kernel by kernel, fused or not as the plan says
+static int rk4_eager(const esd_plan* P, double* u_dev, double dt, int nsteps, void* ws_dev, hipStream_t s) {
+  if (P->fuse_next) {
+    int rc = project_all(P, u_dev, ws_dev, s);
+    for (int step = 0; step < nsteps && rc == 0; ++step) rc = rk4_step_fused(P, u_dev, dt, ws_dev, s);
+    return rc;
+  }
+  int rc = 0;
+  for (int step = 0; step < nsteps && rc == 0; ++step) rc = rk4_step(P, u_dev, dt, ws_dev, nullptr, s);
+  return rc;
+}
+
 // the instantiated graph of one RK4 step for (u, ws, dt), captured on the
 // plan's own stream at first use
 static esd_status step_graph(const esd_plan* P, double* u_dev, double dt, void* ws_dev, hipGraphExec_t* exec) {
   for (const auto& g : P->graphs)
-    if (g.u == u_dev && g.ws == ws_dev && g.dt == dt) {
+    if (g.u == u_dev && g.ws == ws_dev && g.dt == dt && g.fused == P->fuse_next) {
       *exec = g.exec;
       return ESD_OK;
     }
@@ -740,7 +831,8 @@ static esd_status step_graph(const esd_plan* P, double* u_dev, double dt, void* 
   }
   hipGraph_t graph = nullptr;
   HIP_TRY(hipStreamBeginCapture(P->gstream, hipStreamCaptureModeThreadLocal));
-  const int rc = rk4_step(P, u_dev, dt, ws_dev, nullptr, P->gstream);
+  const int rc = P->fuse_next ? rk4_step_fused(P, u_dev, dt, ws_dev, P->gstream)
+                              : rk4_step(P, u_dev, dt, ws_dev, nullptr, P->gstream);
   const hipError_t ec = hipStreamEndCapture(P->gstream, &graph);
   if (rc != 0 || ec != hipSuccess) {
     if (graph) (void)hipGraphDestroy(graph);
@@ -754,7 +846,7 @@ static esd_status step_graph(const esd_plan* P, double* u_dev, double dt, void* 
     (void)hipGraphExecDestroy(P->graphs.front().exec);
     P->graphs.erase(P->graphs.begin());
   }
-  P->graphs.push_back({u_dev, ws_dev, dt, ex});
+  P->graphs.push_back({u_dev, ws_dev, dt, P->fuse_next, ex});
   *exec = ex;
   return ESD_OK;
 }
@@ -767,7 +859,26 @@ esd_status esd_rk4(const esd_plan* P, double* u_dev, double dt, int32_t nsteps, 
   if (((uintptr_t)ws_dev) % 256 != 0) return fail(ESD_EINVAL, "workspace not 256-byte aligned");
   hipStream_t s = (hipStream_t)stream;
   const int64_t n = total_dof(P);
-  if (!stage_ckpt_dev && !P->timing && P->use_graphs && nsteps > 0) {
+  auto launch_rc = [](int rc) {
+    if (rc < 0) return fail(ESD_EUNSUPPORTED, "degree not built");
+    return fail(ESD_EHIP, std::string("RK4 launch failed: ") + hipGetErrorString((hipError_t)rc));
+  };
+  if (stage_ckpt_dev) {
+    // stage inputs checkpointed for the adjoint: residual and stage kernels one by one
+    for (int step = 0; step < nsteps; ++step) {
+      const int rc = rk4_step(P, u_dev, dt, ws_dev, stage_ckpt_dev + (int64_t)4 * step * n, s);
+      if (rc != 0) return launch_rc(rc);
+    }
+    return ESD_OK;
+  }
+  if (nsteps == 0) return ESD_OK;
+  if (!P->timing && P->use_graphs) {
+    // with fused stages the step starts from the projection of u in the first
+    // residual workspace: project once, then replay
+    if (P->fuse_next) {
+      const int rc = project_all(P, u_dev, ws_dev, s);
+      if (rc != 0) return launch_rc(rc);
+    }
     hipGraphExec_t ex = nullptr;
     st = step_graph(P, u_dev, dt, ws_dev, &ex);
     if (st != ESD_OK) return st;
@@ -779,11 +890,13 @@ esd_status esd_rk4(const esd_plan* P, double* u_dev, double dt, int32_t nsteps, 
     HIP_TRY(hipStreamWaitEvent(s, P->gev[1], 0));
     return ESD_OK;
   }
-  for (int step = 0; step < nsteps; ++step) {
-    const int rc = rk4_step(P, u_dev, dt, ws_dev, stage_ckpt_dev ? stage_ckpt_dev + (int64_t)4 * step * n : nullptr, s);
-    if (rc < 0) return fail(ESD_EUNSUPPORTED, "degree not built");
-    if (rc != 0) return fail(ESD_EHIP, std::string("RK4 launch failed: ") + hipGetErrorString((hipError_t)rc));
-  }
+  const int rc = rk4_eager(P, u_dev, dt, nsteps, ws_dev, s);
+  return rc == 0 ? ESD_OK : launch_rc(rc);
+}
+
+esd_status esd_plan_set_fused(esd_plan* P, int32_t enable) {
+  if (!P) return fail(ESD_EINVAL, "plan is NULL");
+  P->fuse_next = enable != 0;
   return ESD_OK;
 }
 
@@ -842,6 +955,30 @@ esd_status esd_plan_autotune(esd_plan* P, const double* u_dev, void* ws_dev, voi
       (which == 2 ? B->k2_block : B->k1_block) = best_bs;
     }
   }
+  // RK4 stages fused or not: one step of each after one untimed, with dt = 0
+  // (the same work) on a copy of u in the first state-sized buffer
+  if (rc == 0) {
+    const int64_t n = total_dof(P);
+    float best = 1e30f;
+    bool best_f = P->fuse_next;
+    for (int f = 1; f >= 0 && rc == 0; --f) {
+      P->fuse_next = f != 0;
+      HIP_TRY(hipMemcpyAsync(dudt, u_dev, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
+      rc = rk4_eager(P, dudt, 0.0, 1, ws_dev, s);
+      if (rc != 0) break;
+      HIP_TRY(hipEventRecord(e0, s));
+      rc = rk4_eager(P, dudt, 0.0, 2, ws_dev, s);
+      HIP_TRY(hipEventRecord(e1, s));
+      HIP_TRY(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best) {
+        best = ms;
+        best_f = f != 0;
+      }
+    }
+    P->fuse_next = best_f;
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   P->timing = timing;
@@ -862,6 +999,7 @@ esd_status esd_plan_get_tuning(const esd_plan* P, int32_t* k2_block, int32_t cap
     k2_block[b] = B->k2_block > 0 ? B->k2_block : esd::rhs_block_candidates(B->dim, B->p)[0];
     if (capacity >= 2 * nbk) k2_block[nbk + b] = B->k1_block > 0 ? B->k1_block : esd::rhs_block_candidates(B->dim, B->p)[0];
   }
+  if (capacity > 2 * nbk) k2_block[2 * nbk] = P->fuse_next ? 1 : 0;
   return ESD_OK;
 }
 

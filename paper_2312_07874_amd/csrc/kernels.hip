@@ -28,13 +28,87 @@
 namespace esd {
 
 // ------------------------------------------------------------------ K1: entropy projection
+// w~ = V^T (w/J) V V^T b for b = (w J W) at the volume nodes in sA [nel*NC][NQ]
+// (eqs. entropy_expansion, matvec_entropy_projection); result in sM; aI holds
+// w/J at this thread's first nodes.  Ends with a barrier.
+template <int DIM, int P>
+__device__ __forceinline__ void weight_adjusted_projection(double* sM, double* sA, double* sS, const DevTables& T,
+                                                           const double* __restrict__ gvol, int64_t e0, int nel,
+                                                           const Ahead<2>& aI) {
+  using Sh = Shape<DIM, P>;
+  constexpr int EPB = Launch<DIM, P>::EPB;
+  constexpr int NC = Sh::NC, NQ = Sh::NQ, NGV = Sh::NGV;
+  const int nec = nel * NC;
+  double* T1 = sS;
+  double* T2 = sS + EPB * Sh::T1;
+  auto ld_wi = [&](int o) { return gvol[((e0 + o / NQ) * NGV + NGV - 1) * NQ + o % NQ]; };
+  xform_Vt<DIM, P>(sA, T1, T2, sM, T, nec);
+  xform_V<DIM, P>(sM, T1, T2, sA, T, nec);
+  aI.each(nel * NQ, ld_wi, [&](int o, double wi) {
+    const int k = o % NQ, el = o / NQ;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) sA[(el * NC + c) * NQ + k] *= wi;
+  });
+  __syncthreads();
+  xform_Vt<DIM, P>(sA, T1, T2, sM, T, nec);
+}
+
+// Entropy projection of a block of elements whose modal state u~ is in sM
+// [nel*NC][NP] (after a barrier): u = V u~, b = w J W(u), w~ by the
+// weight-adjusted projection, written to wt, and the facet values R V w~
+// (eqs. r_2d, r_3d) to wf.  aJ and aI hold w J and w/J at this thread's first
+// nodes.  Uses sA [nel*NC][NQ] and the transform scratch sS.
+template <int DIM, int P>
+__device__ __forceinline__ void project_block(double* sM, double* sA, double* sS, const DevTables& T,
+                                              const double* __restrict__ gvol, const Scheme& S, int64_t e0,
+                                              int nel, int* flag, double* __restrict__ wt, double* __restrict__ wf,
+                                              const Ahead<2>& aJ, const Ahead<2>& aI) {
+  using Sh = Shape<DIM, P>;
+  constexpr int EPB = Launch<DIM, P>::EPB;
+  constexpr int NC = Sh::NC, NQ = Sh::NQ, NP = Sh::NP, NFQ = Sh::NFQ, NGV = Sh::NGV;
+  const int nec = nel * NC;
+  const int tid = threadIdx.x, nth = blockDim.x;
+  double* T1 = sS;
+  double* T2 = sS + EPB * Sh::T1;
+  auto ld_wJ = [&](int o) { return gvol[((e0 + o / NQ) * NGV + NGV - 2) * NQ + o % NQ]; };
+  xform_V<DIM, P>(sM, T1, T2, sA, T, nec);
+  // entropy variables times w J at every volume node
+  bool bad = false;
+  aJ.each(nel * NQ, ld_wJ, [&](int o, double wJ) {
+    const int k = o % NQ, el = o / NQ;
+    double* a = sA + el * NC * NQ;
+    const double rho = a[k];
+    double v2 = 0.0, v[DIM];
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) {
+      v[i] = a[(1 + i) * NQ + k] / rho;
+      v2 += v[i] * v[i];
+    }
+    const double p = (S.gamma - 1.0) * (a[(DIM + 1) * NQ + k] - 0.5 * rho * v2);
+    bad |= !(rho > 0.0) || !(p > 0.0) || !isfinite(rho) || !isfinite(p);
+    const double s = log(p) - S.gamma * log(rho);
+    a[k] = wJ * ((S.gamma - s) * S.gm1_inv - 0.5 * rho * v2 / p);
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) a[(1 + i) * NQ + k] = wJ * (rho * v[i] / p);
+    a[(DIM + 1) * NQ + k] = wJ * (-rho / p);
+  });
+  if (bad) atomicOr(flag, 1);
+  __syncthreads();
+  weight_adjusted_projection<DIM, P>(sM, sA, sS, T, gvol, e0, nel, aI);
+  for (int o = tid; o < nec * NP; o += nth) wt[e0 * NC * NP + o] = sM[o];
+  // facet values of the projected entropy variables, w^z = R^z V w~
+  xform_V<DIM, P>(sM, T1, T2, sA, T, nec);
+  double* wfe = wf + e0 * NC * NFQ;
+  facet_values<DIM, P>(sA, sS, T, nec, [&](int o, double v) { wfe[o] = v; });
+}
+
 template <int DIM, int P, bool PROJECT_ONLY>
 __global__ void __launch_bounds__((Launch<DIM, P>::BSMAX))
 k_entropy_projection(const double* __restrict__ u, double* __restrict__ wt, double* __restrict__ wf,
                      const double* __restrict__ gvol, DevTables T0, Scheme S, int64_t ne, int* flag) {
   using Sh = Shape<DIM, P>;
   constexpr int EPB = Launch<DIM, P>::EPB;
-  constexpr int Q = Sh::Q, NC = Sh::NC, NQ = Sh::NQ, NP = Sh::NP, NQF = Sh::NQF, NFQ = Sh::NFQ, NGV = Sh::NGV;
+  constexpr int NC = Sh::NC, NQ = Sh::NQ, NP = Sh::NP, NGV = Sh::NGV;
   __shared__ double sM[EPB * NC * NP];
   __shared__ double sA[EPB * NC * NQ];
   __shared__ double sS[EPB * Sh::SCR];
@@ -45,9 +119,12 @@ k_entropy_projection(const double* __restrict__ u, double* __restrict__ wt, doub
   const int nel = (int)((ne - e0) < EPB ? (ne - e0) : EPB);
   const int nec = nel * NC;
   const int tid = threadIdx.x, nth = blockDim.x;
-  double* T1 = sS;
-  double* T2 = sS + EPB * Sh::T1;
+  // w J and w/J at this thread's nodes, used after the first transforms
+  auto ld_wJ = [&](int o) { return gvol[((e0 + o / NQ) * NGV + NGV - 2) * NQ + o % NQ]; };
+  auto ld_wi = [&](int o) { return gvol[((e0 + o / NQ) * NGV + NGV - 1) * NQ + o % NQ]; };
+  Ahead<2> aJ, aI;
   if constexpr (PROJECT_ONLY) {
+    aI.load(nel * NQ, ld_wi);
     // u holds nodal values [e][node][var]; b = w J u
     for (int o = tid; o < nel * NQ * NC; o += nth) {
       const int c = o % NC, k = (o / NC) % NQ, el = o / (NC * NQ);
@@ -55,55 +132,14 @@ k_entropy_projection(const double* __restrict__ u, double* __restrict__ wt, doub
       sA[(el * NC + c) * NQ + k] = wJ * u[(e0 * NQ) * NC + o];
     }
     __syncthreads();
-  }
-  // w J and w/J at this thread's nodes, used after the first transforms
-  auto ld_wJ = [&](int o) { return gvol[((e0 + o / NQ) * NGV + NGV - 2) * NQ + o % NQ]; };
-  auto ld_wi = [&](int o) { return gvol[((e0 + o / NQ) * NGV + NGV - 1) * NQ + o % NQ]; };
-  Ahead<2> aJ, aI;
-  if constexpr (!PROJECT_ONLY) aJ.load(nel * NQ, ld_wJ);
-  aI.load(nel * NQ, ld_wi);
-  if constexpr (!PROJECT_ONLY) {
+    weight_adjusted_projection<DIM, P>(sM, sA, sS, T, gvol, e0, nel, aI);
+    for (int o = tid; o < nec * NP; o += nth) wt[e0 * NC * NP + o] = sM[o];
+  } else {
+    aJ.load(nel * NQ, ld_wJ);
+    aI.load(nel * NQ, ld_wi);
     for (int o = tid; o < nec * NP; o += nth) sM[o] = u[e0 * NC * NP + o];
     __syncthreads();
-    xform_V<DIM, P>(sM, T1, T2, sA, T, nec);
-    // entropy variables times w J at every volume node
-    aJ.each(nel * NQ, ld_wJ, [&](int o, double wJ) {
-      const int k = o % NQ, el = o / NQ;
-      double* a = sA + el * NC * NQ;
-      const double rho = a[k];
-      double v2 = 0.0, v[DIM];
-#pragma unroll
-      for (int i = 0; i < DIM; ++i) {
-        v[i] = a[(1 + i) * NQ + k] / rho;
-        v2 += v[i] * v[i];
-      }
-      const double p = (S.gamma - 1.0) * (a[(DIM + 1) * NQ + k] - 0.5 * rho * v2);
-      if (!(rho > 0.0) || !(p > 0.0) || !isfinite(rho) || !isfinite(p)) atomicOr(flag, 1);
-      const double s = log(p) - S.gamma * log(rho);
-      a[k] = wJ * ((S.gamma - s) * S.gm1_inv - 0.5 * rho * v2 / p);
-#pragma unroll
-      for (int i = 0; i < DIM; ++i) a[(1 + i) * NQ + k] = wJ * (rho * v[i] / p);
-      a[(DIM + 1) * NQ + k] = wJ * (-rho / p);
-    });
-    __syncthreads();
-  }
-  // weight-adjusted projection: V^T (w/J) V V^T (w J W)
-  xform_Vt<DIM, P>(sA, T1, T2, sM, T, nec);
-  xform_V<DIM, P>(sM, T1, T2, sA, T, nec);
-  aI.each(nel * NQ, ld_wi, [&](int o, double wi) {
-    const int k = o % NQ, el = o / NQ;
-#pragma unroll
-    for (int c = 0; c < NC; ++c) sA[(el * NC + c) * NQ + k] *= wi;
-  });
-  __syncthreads();
-  xform_Vt<DIM, P>(sA, T1, T2, sM, T, nec);
-  for (int o = tid; o < nec * NP; o += nth) wt[e0 * NC * NP + o] = sM[o];
-  if constexpr (PROJECT_ONLY) return;
-  else {
-    // facet values of the projected entropy variables, w^z = R^z V w~
-    xform_V<DIM, P>(sM, T1, T2, sA, T, nec);
-    double* wfe = wf + e0 * NC * NFQ;
-    facet_values<DIM, P>(sA, sS, T, nec, [&](int o, double v) { wfe[o] = v; });
+    project_block<DIM, P>(sM, sA, sS, T, gvol, S, e0, nel, flag, wt, wf, aJ, aI);
   }
 }
 
@@ -183,7 +219,7 @@ __device__ __forceinline__ void facet_task(const Node<DIM>& Vi, const double* gn
 }
 
 // ------------------------------------------------------------------ K2: right-hand side
-template <int DIM, int P, int FLUX>
+template <int DIM, int P, int FLUX, bool NEXT>
 __global__ void __launch_bounds__((Launch<DIM, P>::BSMAX))
 k_rhs(const double* __restrict__ wt, const double* __restrict__ wfb, double* __restrict__ dudt,
       const double* __restrict__ gvol, const double* __restrict__ gfac, const int32_t* __restrict__ conn,
@@ -199,17 +235,22 @@ k_rhs(const double* __restrict__ wt, const double* __restrict__ wfb, double* __r
   __shared__ double sR[EPB * NC * NQ];      // w at nodes, then r
   __shared__ double sF[FLDS ? EPB * 8 * NFQ : 1];   // own facet node records (LDS case)
   __shared__ double sT[EPB * NC * NFQ];     // C^T 1, then s = B J_f f* - C^T 1
-  // psi tables in LDS: tetrahedra keep them in the tail of sF beyond the modal
-  // staging, free during both transform phases (copied again once the facet
-  // records are dead), so the kernel's LDS and occupancy do not grow;
-  // triangles in an array of their own
-  constexpr int TPSI = TabLds<DIM, P, TAB_PSI>::SIZE;
-  constexpr bool TAB_SF = DIM == 3 && FLDS && 8 * NFQ >= NC * NP + TPSI;
-  static_assert(!TAB_SF || EPB == 1, "one element per workgroup when the tables share sF");
+  // operator tables in LDS: tetrahedra keep them in the tail of sF beyond the
+  // modal staging, free during both transform phases (copied again once the
+  // facet records are dead), so the kernel's LDS and occupancy do not grow;
+  // triangles in an array of their own.  The transforms read psi; the
+  // projection of the next stage also reads the facet tables.  The facet
+  // correction and interface phases, which run while sF holds the facet
+  // records, read their tables from T0.
+  constexpr unsigned WANT = NEXT ? (TAB_PSI | TAB_FACET) : TAB_PSI;
+  constexpr bool FIT_ALL = DIM == 3 && FLDS && 8 * NFQ >= NC * NP + TabLds<DIM, P, WANT>::SIZE;
+  constexpr bool FIT_PSI = DIM == 3 && FLDS && 8 * NFQ >= NC * NP + TabLds<DIM, P, TAB_PSI>::SIZE;
   constexpr unsigned TM =
-      DIM == 2 ? tab_mask<DIM, P, TAB_PSI>(8 * (EPB * (Sh::SCR + NC * NQ + NC * NFQ) + (FLDS ? EPB * 8 * NFQ : 1)))
-               : (TAB_SF ? TAB_PSI : 0u);
-  __shared__ double sTab[DIM == 2 && TM ? TPSI : 1];
+      DIM == 2 ? tab_mask<DIM, P, WANT>(8 * (EPB * (Sh::SCR + NC * NQ + NC * NFQ) + (FLDS ? EPB * 8 * NFQ : 1)))
+               : (FIT_ALL ? WANT : (FIT_PSI ? TAB_PSI : 0u));
+  constexpr bool TAB_SF = DIM == 3 && TM != 0;
+  static_assert(!TAB_SF || EPB == 1, "one element per workgroup when the tables share sF");
+  __shared__ double sTab[DIM == 2 && TM ? TabLds<DIM, P, TM>::SIZE : 1];
   double* const tab_buf = TAB_SF ? sF + NC * NP : sTab;
   const DevTables T = stage_tables<DIM, P, TM>(T0, tab_buf);
   static_assert(FLDS ? 8 * NFQ >= NC * NP : NFQ >= NP, "modal staging must fit the facet buffers");
@@ -309,7 +350,7 @@ k_rhs(const double* __restrict__ wt, const double* __restrict__ wfb, double* __r
       const int b2 = t % Q, b1 = t / Q;     // b2 fastest: neighbouring lanes hit different facet nodes
       i = b1 + Q * b2;
       const Node<DIM> Vi = load_node<DIM>(sNe, NQ, i);
-      const double w1 = T.wl[b1], w2 = T.wl[b2];
+      const double w1 = T0.wl[b1], w2 = T0.wl[b2];
       double gA[2], gB[2], gC[2];
 #pragma unroll
       for (int m = 0; m < 2; ++m) {
@@ -319,16 +360,16 @@ k_rhs(const double* __restrict__ wt, const double* __restrict__ wfb, double* __r
         gB[m] = -g1;                                     // facet 3: nhat = (-1, 0)
         gC[m] = -2.0 * g[(4 + m) * NQ + i] / w1;         // facet 1: nhat = (0, -1)
       }
-      facet_task<DIM, P, FLUX>(Vi, gA, sFe, sTe, gf, 1 * NQF + b2, T.lgp1[b1] * T.wf[1 * NQF + b2], S, racc);
-      facet_task<DIM, P, FLUX>(Vi, gB, sFe, sTe, gf, 2 * NQF + b2, T.lgm1[b1] * T.wf[2 * NQF + b2], S, racc);
-      facet_task<DIM, P, FLUX>(Vi, gC, sFe, sTe, gf, 0 * NQF + b1, T.lgm1[b2] * T.wf[0 * NQF + b1], S, racc);
+      facet_task<DIM, P, FLUX>(Vi, gA, sFe, sTe, gf, 1 * NQF + b2, T0.lgp1[b1] * T0.wf[1 * NQF + b2], S, racc);
+      facet_task<DIM, P, FLUX>(Vi, gB, sFe, sTe, gf, 2 * NQF + b2, T0.lgm1[b1] * T0.wf[2 * NQF + b2], S, racc);
+      facet_task<DIM, P, FLUX>(Vi, gC, sFe, sTe, gf, 0 * NQF + b1, T0.lgm1[b2] * T0.wf[0 * NQF + b1], S, racc);
     } else {
       const int b3 = t % Q, b2 = (t / Q) % Q, b1 = t / (Q * Q);
       i = b1 + Q * (b2 + Q * b3);
       const Node<DIM> Vi = load_node<DIM>(sNe, NQ, i);
-      const double inv23 = 1.0 / (T.wl[b2] * T.wj[b3]);
-      const double inv13 = 1.0 / (T.wl[b1] * T.wj[b3]);
-      const double inv12 = 1.0 / (T.wl[b1] * T.wl[b2] * (1.0 - T.xl[b2]));
+      const double inv23 = 1.0 / (T0.wl[b2] * T0.wj[b3]);
+      const double inv13 = 1.0 / (T0.wl[b1] * T0.wj[b3]);
+      const double inv12 = 1.0 / (T0.wl[b1] * T0.wl[b2] * (1.0 - T0.xl[b2]));
       double gA[3], gB[3], gC[3], gD[3];
 #pragma unroll
       for (int m = 0; m < 3; ++m) {
@@ -340,17 +381,17 @@ k_rhs(const double* __restrict__ wt, const double* __restrict__ wfb, double* __r
         gD[m] = -8.0 * g[(12 + m) * NQ + i] * inv12;     // facet 4: nhat = (0,0,-1)
       }
       const int j23 = b2 + Q * b3;
-      facet_task<DIM, P, FLUX>(Vi, gA, sFe, sTe, gf, 1 * NQF + j23, T.lgp1[b1] * T.wf[1 * NQF + j23], S, racc);
-      facet_task<DIM, P, FLUX>(Vi, gB, sFe, sTe, gf, 2 * NQF + j23, T.lgm1[b1] * T.wf[2 * NQF + j23], S, racc);
+      facet_task<DIM, P, FLUX>(Vi, gA, sFe, sTe, gf, 1 * NQF + j23, T0.lgp1[b1] * T0.wf[1 * NQF + j23], S, racc);
+      facet_task<DIM, P, FLUX>(Vi, gB, sFe, sTe, gf, 2 * NQF + j23, T0.lgm1[b1] * T0.wf[2 * NQF + j23], S, racc);
       const int j13 = b1 + Q * b3;
-      facet_task<DIM, P, FLUX>(Vi, gC, sFe, sTe, gf, 0 * NQF + j13, T.lgm1[b2] * T.wf[0 * NQF + j13], S, racc);
-      const double cz = T.gjm1[b3];
+      facet_task<DIM, P, FLUX>(Vi, gC, sFe, sTe, gf, 0 * NQF + j13, T0.lgm1[b2] * T0.wf[0 * NQF + j13], S, racc);
+      const double cz = T0.gjm1[b3];
 #pragma unroll
       for (int m = 0; m < Q; ++m) {
         int a2 = m + b2 + b3;                 // rotated so that neighbouring lanes hit different facet nodes
         a2 = a2 % Q;
         const int j = 3 * NQF + b1 + Q * a2;
-        facet_task<DIM, P, FLUX>(Vi, gD, sFe, sTe, gf, j, cz * T.I42[a2 * Q + b2] * T.wf[j], S, racc);
+        facet_task<DIM, P, FLUX>(Vi, gD, sFe, sTe, gf, j, cz * T0.I42[a2 * Q + b2] * T0.wf[j], S, racc);
       }
     }
     double* r = sR + el * NC * NQ;
@@ -377,7 +418,7 @@ k_rhs(const double* __restrict__ wt, const double* __restrict__ wfb, double* __r
     double F[NC];
     interface_flux<DIM, FLUX>(Um, Up, nJ, gfac[(e * (DIM + 1) + DIM) * NFQ + j], S.gamma, S.gm1_inv,
                               S.dissipation, F);
-    const double wj = T.wf[j];
+    const double wj = T0.wf[j];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       double* t = sT + (le * NC + c) * NFQ + j;
@@ -386,12 +427,17 @@ k_rhs(const double* __restrict__ wt, const double* __restrict__ wfb, double* __r
   }
   if (bad) atomicOr(flag, 1);
   __syncthreads();
-  if constexpr (TAB_SF) (void)stage_tables<DIM, P, TM>(T0, tab_buf);   // over the dead facet records
+  if constexpr (TAB_SF) {
+    (void)stage_tables<DIM, P, TM>(T0, tab_buf);   // over the dead facet records
+    // the lift below reads the facet tables when they are staged
+    if constexpr ((TM & TAB_FACET) != 0) __syncthreads();
+  }
   auto ld_wi = [&](int o) { return gvol[((e0 + o / NQ) * NGV + NGV - 1) * NQ + o % NQ]; };
   auto ld_u = [&](int o) { return epi.u[e0 * NC * NP + o]; };
   auto ld_acc = [&](int o) { return epi.acc[e0 * NC * NP + o]; };
-  Ahead<2> aI, aU, aA;
+  Ahead<2> aI, aU, aA, aJ;
   aI.load(nel * NQ, ld_wi);
+  if constexpr (NEXT) aJ.load(nel * NQ, [&](int o) { return gvol[((e0 + o / NQ) * NGV + NGV - 2) * NQ + o % NQ]; });
   if (epi.acc != nullptr && !epi.last) aU.load(nec * NP, ld_u);
   if (epi.acc != nullptr && !epi.first) aA.load(nec * NP, ld_acc);
 
@@ -409,6 +455,12 @@ k_rhs(const double* __restrict__ wt, const double* __restrict__ wfb, double* __r
   });
   __syncthreads();
   xform_Vt<DIM, P>(sR, T1, T2, sM, T, nec);
+  // the next stage input U (or the new state at stage 4) goes to HBM, or, when
+  // this kernel also projects it, stays in sM
+  auto put_next = [&](int o, int64_t i, double v) {
+    if constexpr (NEXT) sM[o] = v;
+    else epi.U[i] = v;
+  };
   if (epi.acc == nullptr) {
     for (int o = tid; o < nec * NP; o += nth) dudt[e0 * NC * NP + o] = sM[o];
   } else if (!epi.last) {
@@ -417,7 +469,7 @@ k_rhs(const double* __restrict__ wt, const double* __restrict__ wfb, double* __r
         const int64_t i = e0 * NC * NP + o;
         const double k = sM[o];
         epi.acc[i] = ui + epi.ca * k;
-        epi.U[i] = ui + epi.cu * k;
+        put_next(o, i, ui + epi.cu * k);
       });
     } else {
       // both arrays ahead: walk the iterations by hand
@@ -428,18 +480,27 @@ k_rhs(const double* __restrict__ wt, const double* __restrict__ wfb, double* __r
           const int64_t i = e0 * NC * NP + o;
           const double k = sM[o];
           epi.acc[i] = aA.v[it] + epi.ca * k;
-          epi.U[i] = aU.v[it] + epi.cu * k;
+          put_next(o, i, aU.v[it] + epi.cu * k);
         }
       }
       for (int o = tid + 2 * nth; o < nec * NP; o += nth) {
         const int64_t i = e0 * NC * NP + o;
         const double k = sM[o], ui = epi.u[i];
         epi.acc[i] = epi.acc[i] + epi.ca * k;
-        epi.U[i] = ui + epi.cu * k;
+        put_next(o, i, ui + epi.cu * k);
       }
     }
   } else {
-    aA.each(nec * NP, ld_acc, [&](int o, double ai) { epi.u[e0 * NC * NP + o] = ai + epi.ca * sM[o]; });
+    aA.each(nec * NP, ld_acc, [&](int o, double ai) {
+      const double un = ai + epi.ca * sM[o];
+      epi.u[e0 * NC * NP + o] = un;
+      if constexpr (NEXT) sM[o] = un;
+    });
+  }
+  if constexpr (NEXT) {
+    // entropy projection of the next stage input, into the other workspace
+    __syncthreads();
+    project_block<DIM, P>(sM, sR, sN, T, gvol, S, e0, nel, flag, epi.wt_next, epi.wf_next, aJ, aI);
   }
 }
 
@@ -465,6 +526,23 @@ hipEvent_t timing_event(const esd_plan* pl, hipStream_t s) {
 }
 
 template <int DIM, int P>
+static void launch_k2(const esd_plan* pl, double* dudt, Workspace ws, hipStream_t s, const RkEpilogue& epi, int64_t nb,
+                      int bs) {
+  const bool next = epi.wt_next != nullptr;
+#define K2_ARGS \
+  dim3(nb), dim3(bs), 0, s, ws.wt, ws.wf, dudt, pl->d_gvol, pl->d_gfac, pl->d_conn, pl->tab, pl->scheme, pl->ne, \
+      pl->d_flag, ws.frec, epi
+  if (pl->scheme.ecflux == FLUX_RANOCHA) {
+    if (next) hipLaunchKernelGGL((k_rhs<DIM, P, FLUX_RANOCHA, true>), K2_ARGS);
+    else hipLaunchKernelGGL((k_rhs<DIM, P, FLUX_RANOCHA, false>), K2_ARGS);
+  } else {
+    if (next) hipLaunchKernelGGL((k_rhs<DIM, P, FLUX_CHANDRASHEKAR, true>), K2_ARGS);
+    else hipLaunchKernelGGL((k_rhs<DIM, P, FLUX_CHANDRASHEKAR, false>), K2_ARGS);
+  }
+#undef K2_ARGS
+}
+
+template <int DIM, int P>
 static int run_residual(const esd_plan* pl, const double* u, double* dudt, Workspace ws, hipStream_t s,
                         const RkEpilogue& epi) {
   using L = Launch<DIM, P>;
@@ -475,12 +553,7 @@ static int run_residual(const esd_plan* pl, const double* u, double* dudt, Works
                      pl->d_gvol, pl->tab, pl->scheme, pl->ne, pl->d_flag);
   if (pl->timing) timing_event(pl, s);
   const int bs = pl->k2_block > 0 ? pl->k2_block : L::BS;
-  if (pl->scheme.ecflux == FLUX_RANOCHA)
-    hipLaunchKernelGGL((k_rhs<DIM, P, FLUX_RANOCHA>), dim3(nb), dim3(bs), 0, s, ws.wt, ws.wf, dudt, pl->d_gvol,
-                       pl->d_gfac, pl->d_conn, pl->tab, pl->scheme, pl->ne, pl->d_flag, ws.frec, epi);
-  else
-    hipLaunchKernelGGL((k_rhs<DIM, P, FLUX_CHANDRASHEKAR>), dim3(nb), dim3(bs), 0, s, ws.wt, ws.wf, dudt,
-                       pl->d_gvol, pl->d_gfac, pl->d_conn, pl->tab, pl->scheme, pl->ne, pl->d_flag, ws.frec, epi);
+  launch_k2<DIM, P>(pl, dudt, ws, s, epi, nb, bs);
   if (pl->timing) timing_event(pl, s);
   return (int)hipGetLastError();
 }
@@ -490,12 +563,7 @@ static int run_rhs(const esd_plan* pl, double* dudt, Workspace ws, hipStream_t s
   using L = Launch<DIM, P>;
   const int64_t nb = (pl->ne + L::EPB - 1) / L::EPB;
   const int bs = pl->k2_block > 0 ? pl->k2_block : L::BS;
-  if (pl->scheme.ecflux == FLUX_RANOCHA)
-    hipLaunchKernelGGL((k_rhs<DIM, P, FLUX_RANOCHA>), dim3(nb), dim3(bs), 0, s, ws.wt, ws.wf, dudt, pl->d_gvol,
-                       pl->d_gfac, pl->d_conn, pl->tab, pl->scheme, pl->ne, pl->d_flag, ws.frec, epi);
-  else
-    hipLaunchKernelGGL((k_rhs<DIM, P, FLUX_CHANDRASHEKAR>), dim3(nb), dim3(bs), 0, s, ws.wt, ws.wf, dudt,
-                       pl->d_gvol, pl->d_gfac, pl->d_conn, pl->tab, pl->scheme, pl->ne, pl->d_flag, ws.frec, epi);
+  launch_k2<DIM, P>(pl, dudt, ws, s, epi, nb, bs);
   return (int)hipGetLastError();
 }
 

@@ -33,10 +33,15 @@ struct DevTables {
 //   stages 1-3:  acc = (first ? u : acc) + ca k,  U = u + cu k
 //   stage 4:     u = acc + ca k   (in place on the state)
 // All pointers address the same state layout as du~/dt.
+// With wt_next set, the kernel also projects the next stage input (U, or the
+// new u at stage 4) of its elements, kept in LDS instead of U, into wt_next and
+// wf_next (the other of two residual workspaces).
 struct RkEpilogue {
   double* u = nullptr;
   double* acc = nullptr;
   double* U = nullptr;
+  double* wt_next = nullptr;
+  double* wf_next = nullptr;
   double ca = 0.0, cu = 0.0;
   int first = 0, last = 0;
 };
@@ -115,12 +120,17 @@ struct esd_plan {
   // RK4 steps replayed from a captured graph (no checkpoints, no timing)
   // (the cache below is filled by const compute calls, hence mutable)
   bool use_graphs = true;
+  // RK4 stages as right-hand-side kernels that also project the next stage
+  // input (else K1 and K2 per stage); set at creation (triangles), by
+  // esd_plan_autotune (the faster on the device) or esd_plan_set_fused
+  bool fuse_next = false;
   mutable hipStream_t gstream = nullptr;
   mutable hipEvent_t gev[2] = {nullptr, nullptr};
   struct GraphEntry {
     const void* u;
     const void* ws;
     double dt;
+    bool fused;
     hipGraphExec_t exec;
   };
   mutable std::vector<GraphEntry> graphs;

@@ -79,12 +79,24 @@ def k2_bytes(dim: int, p: int) -> int:
 
 
 def k2_rk_bytes(dim: int, p: int) -> int:
-    """K2 inside an RK4 step, with the stage combination fused into its output:
+    """K2 inside an RK4 step with the stage combination formed by its output:
     instead of writing du~/dt it reads u and acc and writes acc and U (stage 1
     skips the acc read, stage 4 reads acc and writes u), 3.25 state arrays on
     average over the four stages in place of one."""
     Q, NC, NQ, NP, NQF, NFQ = _sizes(dim, p)
     return k2_bytes(dim, p) + (8 * NC * NP * 9) // 4
+
+
+def k2_next_bytes(dim: int, p: int) -> int:
+    """The RK4 stage kernel: K2 whose output is the stage combination and which
+    then projects the next stage input of its elements (K1's work on data
+    already in LDS).  Against the plain residual it moves, per element, 2.5
+    state arrays on average over the four stages instead of du~/dt (stage 1:
+    u read, acc written; stages 2-3: u and acc read, acc written; stage 4: acc
+    read, u written), plus the projection's w J read and w~ and facet values
+    written."""
+    Q, NC, NQ, NP, NQF, NFQ = _sizes(dim, p)
+    return k2_bytes(dim, p) + (8 * NC * NP * 3) // 2 + 8 * (NC * NP + NC * NFQ + NQ)
 
 
 def k1_bytes(dim: int, p: int) -> int:

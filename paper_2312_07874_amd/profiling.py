@@ -7,7 +7,9 @@ Two commands, both reading the CSV files rocprofv3 writes with
       HBM bytes of K2 from a ``--pmc FETCH_SIZE`` and a ``--pmc WRITE_SIZE`` run
       of ``bench.py --workload WORKLOAD --steps 1 --warmup 0 --no-autotune
       --extra "" --no-batched --calibrate-copy``.  The first four K2 dispatches
-      of such a run are the four stages of the timed RK4 step; their counters
+      of such a run are the four stage kernels of the timed RK4 step (right-hand
+      side and stage combination, with fused stages also the next projection);
+      their counters
       are averaged and scaled by what the same counters read on the closing
       1 GiB device-to-device copy.  The result goes into profiles/traffic.json
       with a hash of the kernel sources (bench.py reports it only while they
@@ -89,7 +91,8 @@ def traffic(workload, fetch_csv, write_csv):
         "write_scale": write_scale,
         "read_bytes_per_launch": statistics.fmean(fk) * 1024.0 * fetch_scale,
         "write_bytes_per_launch": statistics.fmean(wk) * 1024.0 * write_scale,
-        "algorithmic_bytes_per_launch": pm.k2_rk_bytes(wl.dim, wl.degree) * ne,
+        "algorithmic_bytes_per_launch": (pm.k2_next_bytes(wl.dim, wl.degree) if _short(k2f[0][1]).endswith("true>")
+                                         else pm.k2_rk_bytes(wl.dim, wl.degree)) * ne,
     }
     try:
         with open(TRAFFIC_FILE) as fh:

@@ -81,6 +81,57 @@ def test_autotune_keeps_the_residual():
     blocks = plan.autotune(u)
     after = plan.residual(u)
     plan.sync_status()
-    log(f"autotuned right-hand-side block: {blocks}")
+    log(f"autotuned right-hand-side block: {blocks}, fused RK4 stages: {plan.tuning_fused()}")
     assert blocks[0] % 64 == 0 and 64 <= blocks[0] <= 512
     _close(after, before, "residual after autotune")
+
+
+def _fused_matches_stage_by_stage(plan, u0, dt):
+    """esd_rk4 without checkpoints, with fused stages (one projection per call,
+    then per stage one kernel forming the stage combination and projecting the
+    next stage input, alternating two workspaces) and without, against esd_rk4
+    with stage checkpoints (stages unfused), eager and graph, over several
+    steps and across calls."""
+    n = u0.numel()
+    ref = u0.clone()
+    ckpt = torch.empty((4 * 4, n), dtype=torch.float64, device="cuda")
+    plan.rk4(ref, dt, 4, ckpt=ckpt)
+    for fused in (True, False):
+        plan.set_fused(fused)
+        assert plan.tuning_fused() == fused
+        for graphs in (False, True):
+            plan.set_graphs(graphs)
+            one = u0.clone()
+            plan.rk4(one, dt, 4)
+            two = u0.clone()
+            plan.rk4(two, dt, 1)
+            plan.rk4(two, dt, 3)
+            torch.cuda.synchronize()
+            plan.sync_status()
+            _close(one, ref, f"4 steps (fused {fused}, graphs {graphs}) vs checkpointed")
+            _close(two, ref, f"1 + 3 steps (fused {fused}, graphs {graphs}) vs checkpointed")
+        # the checkpointed stage inputs agree with the first step
+        u1 = u0.clone()
+        plan.set_graphs(False)
+        plan.rk4(u1, dt, 1)
+        _close(ckpt[4].reshape(u0.shape), u1, f"stage-1 input of step 2 (fused {fused})")
+
+
+def test_fused_rk4_single_plans():
+    for wk in (wl.random_tri(M=4, degree=5, seed=3), wl.random_tet(M=3, degree=4, seed=5)):
+        plan = gpu_plan(wk)
+        x = plan.node_coords().cpu().numpy()
+        u0 = plan.project(torch.tensor(wk.state(x), device="cuda").contiguous())
+        log(f"{wk.name}")
+        _fused_matches_stage_by_stage(plan, u0, 2e-3)
+
+
+def test_fused_rk4_batched_plan():
+    import paper_2312_07874_amd as esd
+    L = 2 * math.pi
+    m = wl.split_box_mesh(3, 3, L)
+    deg = wl.mixed_degrees(m.n_elements, 11, 1, 6)
+    plan = esd.BatchedPlan(3, [(m.elem_vertex_ids, m.elem_vertex_coords, deg)], wl.make_warp_sinprod(L, 0.05))
+    x = plan.node_coords().cpu().numpy()
+    u0 = plan.project(torch.tensor(wl.RandomSmooth(3, L, 4)(x), device="cuda").reshape(plan.nodal_shape).contiguous())
+    _fused_matches_stage_by_stage(plan, u0, 2e-3)

@@ -104,7 +104,7 @@ def test_workspace_sizes_and_host_only_rejection():
     ndof_b = a256(i.n_dof * 8)
     fac_b = a256(i.n_elements * i.n_vars * i.n_facets * i.n_facet_nodes * 8)
     assert i.workspace_bytes == ndof_b + fac_b
-    assert i.rk4_workspace_bytes == i.workspace_bytes + 3 * ndof_b
+    assert i.rk4_workspace_bytes == 2 * i.workspace_bytes + 3 * ndof_b
     assert i.vjp_workspace_bytes == i.workspace_bytes + fac_b
     assert i.rk4_vjp_workspace_bytes == i.vjp_workspace_bytes + 3 * ndof_b
     L = esd._lib
