@@ -288,7 +288,10 @@ k_rhs_vjp(const double* __restrict__ wt, const double* __restrict__ wfb, const d
       facet_task_vjp<DIM, P, FLUX>(Vi, gC, sFe, sTe, sXFe, gf, 0 * NQF + j13, T.lgm1[b2] * T.wf[0 * NQF + j13], S,
                                    rbi, Vib);
       const double cz = T.gjm1[b3];
-#pragma unroll
+      // kept rolled: unrolled, the pair adjoints of all Q partners stay live
+      // (tet VGPRs 388-512 with spills at p = 8; rolled about 225, which
+      // doubles the waves per SIMD where LDS allows: p = 4 1.67 vs 2.27 ms)
+#pragma unroll 1
       for (int m = 0; m < Q; ++m) {
         int a2 = m + b2 + b3;
         a2 = a2 % Q;
