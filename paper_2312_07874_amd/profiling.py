@@ -15,6 +15,11 @@ Two commands, both reading the CSV files rocprofv3 writes with
       with a hash of the kernel sources (bench.py reports it only while they
       are unchanged).
 
+  python -m paper_2312_07874_amd.profiling counters CSV [CSV ...]
+      Any ``--pmc`` counters of a ``--steps 1 --warmup 0 --no-autotune`` bench
+      run: per counter, the mean over the four stage kernels of the timed RK4
+      step and over the entropy-projection launches, as a markdown table.
+
   python -m paper_2312_07874_amd.profiling stats TRACE_CSV [KERNEL_PREFIX]
       Per-block-size launch count and average duration of a kernel from a
       ``--kernel-trace`` run (default prefix ``esd::k_rhs<``), as a markdown table.
@@ -112,6 +117,32 @@ def traffic(workload, fetch_csv, write_csv):
           f"{meas / rec['algorithmic_bytes_per_launch']:.2f} |")
 
 
+def counters(paths):
+    k2, k1 = {}, {}
+    names = {}
+    for path in paths:
+        seen = {}
+        for r in sorted(_rows(path), key=lambda r: int(r["Dispatch_Id"])):
+            name = _short(r["Kernel_Name"])
+            c = r["Counter_Name"]
+            v = float(r["Counter_Value"])
+            if name.startswith(K2_PREFIX):
+                n = seen.setdefault((c, "k2"), 0)
+                if n < 4:
+                    k2.setdefault(c, []).append(v)
+                    names["k2"] = name
+                seen[(c, "k2")] = n + 1
+            elif name.startswith("esd::k_entropy_projection<") and name.endswith("false>"):
+                k1.setdefault(c, []).append(v)
+                names["k1"] = name
+    print(f"| counter | `{names.get('k2', 'K2')}` (4 stages) | `{names.get('k1', 'K1')}` |")
+    print("|---|---|---|")
+    for c in k2:
+        a = statistics.fmean(k2[c])
+        b = statistics.fmean(k1[c]) if c in k1 else float("nan")
+        print(f"| {c} | {a:.4g} | {b:.4g} |")
+
+
 def stats(trace_csv, prefix=K2_PREFIX):
     by = {}
     for r in _rows(trace_csv):
@@ -131,6 +162,8 @@ def main(argv):
     if len(argv) >= 4 and argv[0] == "traffic":
         sys.path.insert(0, ROOT)
         traffic(argv[1], argv[2], argv[3])
+    elif len(argv) >= 2 and argv[0] == "counters":
+        counters(argv[1:])
     elif len(argv) >= 2 and argv[0] == "stats":
         stats(argv[1], *(argv[2:3]))
     else:
