@@ -211,7 +211,7 @@ esd_status esd_plan_set_fused(esd_plan* plan, int32_t enable);
 /* Chooses the block sizes of the right-hand-side kernel (K2) and of the
  * entropy-projection kernel (K1) for every bucket by timing the candidates
  * (multiples of 64 up to their compiled bound) on the state u_dev, then
- * whether RK4 stages are fused (esd_plan_set_fused) by timing a step both ways
+ * whether RK4 stages are fused (esd_plan_set_fused) by timing steps both ways
  * on a copy of u_dev; ws_dev holds info.rk4_workspace_bytes.  Synchronises.
  * The choice is kept by the plan and reported by esd_plan_get_tuning:
  * k2_block[bucket], and, when capacity allows 2 n_buckets entries, the K1 block

@@ -955,19 +955,22 @@ esd_status esd_plan_autotune(esd_plan* P, const double* u_dev, void* ws_dev, voi
       (which == 2 ? B->k2_block : B->k1_block) = best_bs;
     }
   }
-  // RK4 stages fused or not: one step of each after one untimed, with dt = 0
-  // (the same work) on a copy of u in the first state-sized buffer
+  // RK4 stages fused or not: four steps of each in one call (the fused call's
+  // one projection of u then weighs a quarter step) after one untimed, with
+  // dt = 0 (the same work) on a copy of u in the first state-sized buffer, run
+  // as esd_rk4 runs them (graph replays unless graphs are off)
+  esd_status trial = ESD_OK;
   if (rc == 0) {
     const int64_t n = total_dof(P);
     float best = 1e30f;
     bool best_f = P->fuse_next;
-    for (int f = 1; f >= 0 && rc == 0; --f) {
+    for (int f = 1; f >= 0 && trial == ESD_OK; --f) {
       P->fuse_next = f != 0;
       HIP_TRY(hipMemcpyAsync(dudt, u_dev, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
-      rc = rk4_eager(P, dudt, 0.0, 1, ws_dev, s);
-      if (rc != 0) break;
+      trial = esd_rk4(P, dudt, 0.0, 1, ws_dev, nullptr, stream);
+      if (trial != ESD_OK) break;
       HIP_TRY(hipEventRecord(e0, s));
-      rc = rk4_eager(P, dudt, 0.0, 2, ws_dev, s);
+      trial = esd_rk4(P, dudt, 0.0, 4, ws_dev, nullptr, stream);
       HIP_TRY(hipEventRecord(e1, s));
       HIP_TRY(hipEventSynchronize(e1));
       float ms = 0.f;
@@ -985,6 +988,7 @@ esd_status esd_plan_autotune(esd_plan* P, const double* u_dev, void* ws_dev, voi
   // graphs captured before the change keep the old launch shape
   for (auto& g : P->graphs) (void)hipGraphExecDestroy(g.exec);
   P->graphs.clear();
+  if (trial != ESD_OK) return trial;   // its message is already set
   if (rc < 0) return fail(ESD_EUNSUPPORTED, "degree not built");
   if (rc != 0) return fail(ESD_EHIP, std::string("autotune launch failed: ") + hipGetErrorString((hipError_t)rc));
   return ESD_OK;

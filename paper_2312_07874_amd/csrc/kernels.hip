@@ -198,7 +198,7 @@ __device__ __forceinline__ void vol_task(const double* sN, const double* __restr
 }
 
 // One facet-correction pair (eq. facet_correction): C = coef f#(u_i, u^z_j, (gn_i + nJ_j)/2);
-// r_i -= C (registers), t_j += C (LDS atomics).
+// r_i -= C (registers), s_j -= C (LDS atomics; s_j starts as the interface term).
 template <int DIM, int P, int FLUX>
 __device__ __forceinline__ void facet_task(const Node<DIM>& Vi, const double* gn_i, const double* sF, double* sT,
                                            const double* __restrict__ gf, int j, double coef, const Scheme& S,
@@ -214,7 +214,7 @@ __device__ __forceinline__ void facet_task(const Node<DIM>& Vi, const double* gn
   for (int c = 0; c < NC; ++c) {
     const double C = coef * F[c];
     racc[c] -= C;
-    atomicAdd(&sT[c * NFQ + j], C);
+    atomicAdd(&sT[c * NFQ + j], -C);
   }
 }
 
@@ -280,16 +280,33 @@ k_rhs(const double* __restrict__ wt, const double* __restrict__ wfb, double* __r
     bad |= !from_entropy<DIM>(w, S.gamma, S.gm1_inv, nd);
     store_node<DIM>(sN + el * Sh::SCR, NQ, k, nd);
   }
+  // own facet node records, and the interface flux (eqs. num_flux,
+  // entropy_stable) against the neighbour's facet state: s starts as
+  // B J_f f* at the facet nodes, the facet correction subtracts C^T 1
   for (int o = tid; o < nel * NFQ; o += nth) {
     const int j = o % NFQ, el = o / NFQ;
-    double w[NC];
+    const int64_t e = e0 + el;
+    const int32_t addr = conn[e * NFQ + j];
+    double w[NC], wn[NC];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) w[c] = wfb[((e0 + el) * NC + c) * NFQ + j];
-    Node<DIM> nd;
-    bad |= !from_entropy<DIM>(w, S.gamma, S.gm1_inv, nd);
-    store_node<DIM>(fr + el * 8 * NFQ, NFQ, j, nd);
+    for (int c = 0; c < NC; ++c) {
+      w[c] = wfb[(e * NC + c) * NFQ + j];
+      wn[c] = wfb[addr + c * NFQ];
+    }
+    double nJ[DIM];
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) nJ[i] = gfac[(e * (DIM + 1) + i) * NFQ + j];
+    const double Jf = gfac[(e * (DIM + 1) + DIM) * NFQ + j];
+    Node<DIM> Um, Up;
+    bad |= !from_entropy<DIM>(w, S.gamma, S.gm1_inv, Um);
+    bad |= !from_entropy<DIM>(wn, S.gamma, S.gm1_inv, Up);
+    store_node<DIM>(fr + el * 8 * NFQ, NFQ, j, Um);
+    double F[NC];
+    interface_flux<DIM, FLUX>(Um, Up, nJ, Jf, S.gamma, S.gm1_inv, S.dissipation, F);
+    const double wj = T0.wf[j];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) sT[(el * NC + c) * NFQ + j] = wj * F[c];
   }
-  for (int o = tid; o < nec * NFQ; o += nth) sT[o] = 0.0;
   if (bad) atomicOr(flag, 1);
   __syncthreads();
 
@@ -299,7 +316,6 @@ k_rhs(const double* __restrict__ wt, const double* __restrict__ wfb, double* __r
   //      evaluated once and every task does the same work.  r_a accumulates in
   //      registers, r_b through LDS atomics.
   for (int o = tid; o < nec * NQ; o += nth) sR[o] = 0.0;
-  for (int o = tid; o < nec * NFQ; o += nth) sT[o] = 0.0;
   __syncthreads();
   {
     constexpr int TPE = DIM * NQ;           // volume tasks per element
@@ -400,33 +416,6 @@ k_rhs(const double* __restrict__ wt, const double* __restrict__ wfb, double* __r
   }
   __syncthreads();
 
-  // ---- interface flux and s = B J_f f* - C^T 1
-  bad = false;
-  for (int o = tid; o < nel * NFQ; o += nth) {
-    const int j = o % NFQ, le = o / NFQ;
-    const int64_t e = e0 + le;
-    const Node<DIM> Um = load_node<DIM>(fr + le * 8 * NFQ, NFQ, j);
-    const int32_t addr = conn[e * NFQ + j];
-    double w[NC];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) w[c] = wfb[addr + c * NFQ];
-    Node<DIM> Up;
-    bad |= !from_entropy<DIM>(w, S.gamma, S.gm1_inv, Up);
-    double nJ[DIM];
-#pragma unroll
-    for (int i = 0; i < DIM; ++i) nJ[i] = gfac[(e * (DIM + 1) + i) * NFQ + j];
-    double F[NC];
-    interface_flux<DIM, FLUX>(Um, Up, nJ, gfac[(e * (DIM + 1) + DIM) * NFQ + j], S.gamma, S.gm1_inv,
-                              S.dissipation, F);
-    const double wj = T0.wf[j];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      double* t = sT + (le * NC + c) * NFQ + j;
-      *t = wj * F[c] - *t;
-    }
-  }
-  if (bad) atomicOr(flag, 1);
-  __syncthreads();
   if constexpr (TAB_SF) {
     (void)stage_tables<DIM, P, TM>(T0, tab_buf);   // over the dead facet records
     // the lift below reads the facet tables when they are staged
