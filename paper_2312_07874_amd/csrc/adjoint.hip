@@ -133,8 +133,17 @@ k_rhs_vjp(const double* __restrict__ wt, const double* __restrict__ wfb, const d
   __shared__ double sF[EPB * 8 * NFQ];      // own facet node data; later R^T scratch
   __shared__ double sT[EPB * NC * NFQ];     // t_bar = R r_bar
   __shared__ double sXF[EPB * NC * NFQ];    // x_bar, then w_bar at own facet nodes
-  constexpr unsigned TM =
-      tab_mask<DIM, P, TAB_PSI | TAB_FACET>(8 * EPB * (Sh::SCR + 2 * NC * NQ + 8 * NFQ + 2 * NC * NFQ));
+  // staged tables only where they do not lower the workgroups per CU: this
+  // kernel is bound by its pair adjoints, not by the transforms, and runs at
+  // about 2 waves per SIMD (about 225 VGPRs), which caps the workgroups per CU
+  // at 8 waves' worth (measured at tet p = 6: VJP 8.17 -> 6.28 ms without the
+  // tables, 1 -> 2 workgroups per CU; at p = 4 the tables stay)
+  constexpr int VB = 8 * EPB * (Sh::SCR + 2 * NC * NQ + 8 * NFQ + 2 * NC * NFQ);
+  constexpr int VT = 8 * TabLds<DIM, P, TAB_PSI | TAB_FACET>::SIZE;
+  constexpr int CAP = 8 / ((VjpLaunch<DIM, P>::BS + 63) / 64);
+  constexpr int WG_T = LDS_BYTES / (VB + VT) < CAP ? LDS_BYTES / (VB + VT) : CAP;
+  constexpr int WG_N = LDS_BYTES / VB < CAP ? LDS_BYTES / VB : CAP;
+  constexpr unsigned TM = WG_T >= WG_N ? tab_mask<DIM, P, TAB_PSI | TAB_FACET>(VB) : 0u;
   __shared__ double sTab[TM ? TabLds<DIM, P, TM>::SIZE : 1];
   const DevTables T = stage_tables<DIM, P, TM>(T0, sTab);
   const int64_t e0 = (int64_t)blockIdx.x * EPB;
