@@ -271,6 +271,61 @@ def run_batched(steps: int, warmup: int):
     }
 
 
+def run_adjoint(nsteps: int = 20):
+    """The gradient workload: tgv tet M12 p6 (10,368 curved tetrahedra), nsteps
+    RK4 steps forward with the stage inputs checkpointed, then the discrete
+    adjoint of those steps for a seeded random cotangent of the final state;
+    times against the same steps without checkpoints, and the checkpoint memory."""
+    import torch
+
+    import paper_2312_07874_amd as esd
+
+    wk = wl.tgv_tet(M=12, degree=6)
+    plan = esd.Plan.from_workload(wk)
+    x = plan.node_coords().cpu().numpy()
+    u0 = plan.project(torch.tensor(wk.state(x), device="cuda").contiguous())
+    plan.autotune(u0)
+    dt = 1e-3
+    ckpt = torch.empty((4 * nsteps,) + tuple(u0.shape), dtype=torch.float64, device="cuda")
+    g = torch.Generator(device="cuda").manual_seed(1)
+    ubar0 = torch.randn(tuple(u0.shape), generator=g, dtype=torch.float64, device="cuda")
+    # warm-up of every path
+    plan.rk4(u0.clone(), dt, 1)
+    plan.rk4(u0.clone(), dt, 1, ckpt=ckpt[:4])
+    plan.rk4_vjp(ckpt[:4], dt, 1, ubar0.clone())
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+    u = u0.clone()
+    ev[0].record()
+    plan.rk4(u, dt, nsteps)
+    ev[1].record()
+    u = u0.clone()
+    ev[2].record()
+    plan.rk4(u, dt, nsteps, ckpt=ckpt)
+    ev[3].record()
+    ubar = ubar0.clone()
+    ev[4].record()
+    plan.rk4_vjp(ckpt, dt, nsteps, ubar)
+    ev[5].record()
+    torch.cuda.synchronize()
+    plan.sync_status()
+    fwd = ev[0].elapsed_time(ev[1])
+    fwd_ck = ev[2].elapsed_time(ev[3])
+    adj = ev[4].elapsed_time(ev[5])
+    return {
+        "workload": f"{wk.name} gradient over {nsteps} RK4 steps",
+        "elements": plan.info.n_elements,
+        "dof": plan.info.n_dof,
+        "forward_ms": fwd,
+        "forward_checkpointed_ms": fwd_ck,
+        "adjoint_ms": adj,
+        "gradient_over_forward": (fwd_ck + adj) / fwd,
+        "adjoint_over_forward": adj / fwd,
+        "checkpoint_bytes": ckpt.numel() * 8,
+        "rk4_stages_fused": plan.tuning_fused(),
+    }
+
+
 def cpu_baseline(name: str, budget_s: float):
     """The oracle (dense FP64, PyTorch CPU) timed on a bounded element sample."""
     import torch
@@ -309,6 +364,7 @@ def main():
                     help="comma-separated additional workloads reported under 'extra' ('' for none)")
     ap.add_argument("--extra-steps", type=int, default=3)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched mixed-degree workload")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the 20-step gradient workload")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default block sizes")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="finish with a plain 1 GiB device-to-device copy (counter calibration for profiles)")
@@ -326,6 +382,8 @@ def main():
             extra.append(run_gpu(name, args.extra_steps, 1, not args.no_autotune))
     if not args.no_batched:
         extra.append(run_batched(args.extra_steps, 1))
+    if not args.no_adjoint:
+        extra.append(run_adjoint())
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.workload, args.cpu_seconds)
     out = {
         "metric": METRIC,

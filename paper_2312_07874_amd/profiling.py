@@ -6,7 +6,7 @@ Two commands, both reading the CSV files rocprofv3 writes with
   python -m paper_2312_07874_amd.profiling traffic WORKLOAD FETCH_CSV WRITE_CSV
       HBM bytes of K2 from a ``--pmc FETCH_SIZE`` and a ``--pmc WRITE_SIZE`` run
       of ``bench.py --workload WORKLOAD --steps 1 --warmup 0 --no-autotune
-      --extra "" --no-batched --calibrate-copy``.  The first four K2 dispatches
+      --extra "" --no-batched --no-adjoint --calibrate-copy``.  The first four K2 dispatches
       of such a run are the four stage kernels of the timed RK4 step (right-hand
       side and stage combination, with fused stages also the next projection);
       their counters
