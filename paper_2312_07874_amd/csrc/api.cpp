@@ -170,6 +170,7 @@ esd_status create_single(const esd_mesh_desc* mesh, const esd_scheme_desc* schem
     add(R.wl);
     add(R.wj);
     add(R.xl);
+    add(R.psiM);
     esd_status st = upload(&P->d_tables, tb);
     if (st != ESD_OK) {
       free_device(P);
@@ -178,7 +179,7 @@ esd_status create_single(const esd_mesh_desc* mesh, const esd_scheme_desc* schem
     }
     const double* b = P->d_tables;
     P->tab = {b + off[0], b + off[1], b + off[2], b + off[3], b + off[4],  b + off[5],
-              b + off[6], b + off[7], b + off[8], b + off[9], b + off[10], b + off[11]};
+              b + off[6], b + off[7], b + off[8], b + off[9], b + off[10], b + off[11], b + off[12]};
     // geometry
     st = upload(&P->d_gvol, pack_gvol(*P));
     const int NFQ = R.NFQ, NQF = R.NQF, dim = P->dim, NF = R.NF;

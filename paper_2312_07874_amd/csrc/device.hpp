@@ -119,17 +119,35 @@ constexpr int LDS_BYTES = 160 * 1024;
 enum : unsigned {
   TAB_PSI = 1,     // psi2, psi3 (transforms)
   TAB_FACET = 2,   // I42, lgm1, lgp1, gjm1 (facet extrapolation and lift)
+  TAB_PSIM = 4,    // psiM (the composed stage of V V^T)
 };
 template <int DIM, int P, unsigned M>
 struct TabLds {
   static constexpr int Q = P + 1;
   static constexpr int NPSI = (P + 1) * (P + 1) * Q;
-  static constexpr int SIZE = ((M & TAB_PSI) ? (DIM == 2 ? 1 : 2) * NPSI : 0) + ((M & TAB_FACET) ? Q * Q + 3 * Q : 0);
+  static constexpr int SIZE = ((M & TAB_PSI) ? (DIM == 2 ? 1 : 2) * NPSI : 0) + ((M & TAB_FACET) ? Q * Q + 3 * Q : 0) +
+                              ((M & TAB_PSIM) ? (P + 1) * Q * Q : 0);
 };
 // the tables W if a kernel using base_bytes of LDS still fits with them, else none
 template <int DIM, int P, unsigned W>
 constexpr unsigned tab_mask(int base_bytes) {
   return base_bytes + 8 * TabLds<DIM, P, W>::SIZE <= LDS_BYTES ? W : 0u;
+}
+
+// whether staging the tables W1 instead of W0 keeps the number of workgroups
+// per CU, for a kernel using base_bytes of LDS besides them whose waves allow
+// at most cap workgroups per CU
+template <int DIM, int P, unsigned W0, unsigned W1>
+constexpr bool tab_keeps_wgs(int base_bytes, int cap) {
+  const int b0 = base_bytes + 8 * TabLds<DIM, P, W0>::SIZE, b1 = base_bytes + 8 * TabLds<DIM, P, W1>::SIZE;
+  const int g0 = LDS_BYTES / b0 < cap ? LDS_BYTES / b0 : cap, g1 = LDS_BYTES / b1 < cap ? LDS_BYTES / b1 : cap;
+  return b1 <= LDS_BYTES && g1 >= g0;
+}
+// workgroups per CU that the waves of a default-sized block allow at 4 waves
+// per SIMD (kernels at <= 128 VGPRs; an upper bound otherwise)
+template <int DIM, int P>
+constexpr int wave_cap() {
+  return 16 / ((Launch<DIM, P>::BS + 63) / 64) > 0 ? 16 / ((Launch<DIM, P>::BS + 63) / 64) : 1;
 }
 
 // copies the tables M into buf (TabLds<DIM, P, M>::SIZE doubles of LDS) and
@@ -152,6 +170,7 @@ __device__ __forceinline__ DevTables stage_tables(const DevTables& T, double* bu
       R.psi2 = copy(T.psi2, L::NPSI);
       if constexpr (DIM == 3) R.psi3 = copy(T.psi3, L::NPSI);
     }
+    if constexpr ((M & TAB_PSIM) != 0) R.psiM = copy(T.psiM, (P + 1) * Q * Q);
     if constexpr ((M & TAB_FACET) != 0) {
       R.I42 = copy(T.I42, Q * Q);
       R.lgm1 = copy(T.lgm1, Q);
@@ -164,14 +183,24 @@ __device__ __forceinline__ DevTables stage_tables(const DevTables& T, double* bu
 
 // ------------------------------------------------------------------ sum-factorised PKD transforms
 // in/out arrays are [nel*NC][...] contiguous per (element, variable); all
-// threads of the block participate; each call ends with a barrier.  Every
-// thread produces a whole line of outputs from one set of LDS loads
-// (register blocking along the contracted direction).
+// threads of the block participate.  Every thread produces a whole line of
+// outputs from one set of LDS loads (register blocking along the contracted
+// direction).  The stages below end without a barrier; the transforms put one
+// after each.
+//
+// Stage layouts: triangles T1 [ec][a1][i2]; tetrahedra T1 [ec][(a1,a2)][i3],
+// T2 [ec][a1][i2 + Q i3].
+template <int P>
+struct Unroll {
+  static constexpr int Q = P + 1;
+  static constexpr int XU = Q <= 7 ? Q : 1;   // contraction unrolled while its table fits scalar registers
+};
+
+// V, first stage: the modes of the last direction to its nodes
 template <int DIM, int P>
-__device__ __forceinline__ void xform_V(const double* uh, double* T1, double* T2, double* out, const DevTables& T, int nec) {
+__device__ __forceinline__ void v_first(const double* uh, double* T1, const DevTables& T, int nec) {
   using S = Shape<DIM, P>;
-  constexpr int Q = S::Q;
-  constexpr int XU = Q <= 7 ? Q : 1;   // unroll the contraction while its table fits scalar registers
+  constexpr int Q = S::Q, XU = Unroll<P>::XU;
   // stages whose table is indexed per lane (read from LDS) unroll one degree
   // further on tetrahedra (measured: K1 at p = 7 2.49 -> 2.19 ms; p = 8 unchanged)
   constexpr int XL = (DIM == 3 && Q <= 8) ? Q : XU;
@@ -184,7 +213,7 @@ __device__ __forceinline__ void xform_V(const double* uh, double* T1, double* T2
       double acc[Q];
 #pragma unroll
       for (int i = 0; i < Q; ++i) acc[i] = 0.0;
-#pragma unroll XL
+#pragma unroll XU
       for (int a2 = 0; a2 <= P; ++a2) {
         if (a2 <= P - a1) {
           const double x = uh[ec * S::NP + mb + a2];
@@ -196,23 +225,6 @@ __device__ __forceinline__ void xform_V(const double* uh, double* T1, double* T2
 #pragma unroll
       for (int i = 0; i < Q; ++i) T1[(ec * (P + 1) + a1) * Q + i] = acc[i];
     }
-    __syncthreads();
-    // out[ec][i1 + Q i2] = sum_a1 psi1[a1][i1] T1[ec][a1][i2]
-    for (int o = tid; o < nec * Q; o += nth) {
-      const int i2 = o % Q, ec = o / Q;
-      double acc[Q];
-#pragma unroll
-      for (int i = 0; i < Q; ++i) acc[i] = 0.0;
-#pragma unroll XU
-      for (int a1 = 0; a1 <= P; ++a1) {
-        const double x = T1[(ec * (P + 1) + a1) * Q + i2];
-#pragma unroll
-        for (int i = 0; i < Q; ++i) acc[i] += T.psi1[a1 * Q + i] * x;
-      }
-#pragma unroll
-      for (int i = 0; i < Q; ++i) out[ec * S::NQ + i + Q * i2] = acc[i];
-    }
-    __syncthreads();
   } else {
     // T1[ec][pr][i3] = sum_a3 psi3[s][a3][i3] u~[ec][(a1,a2,a3)]
     for (int o = tid; o < nec * S::NPAIR; o += nth) {
@@ -235,72 +247,116 @@ __device__ __forceinline__ void xform_V(const double* uh, double* T1, double* T2
 #pragma unroll
       for (int i = 0; i < Q; ++i) T1[(ec * S::NPAIR + pr) * Q + i] = acc[i];
     }
-    __syncthreads();
-    // T2[ec][a1][i2 + Q i3] = sum_a2 psi2[a1][a2][i2] T1[ec][(a1,a2)][i3]
-    for (int o = tid; o < nec * (P + 1) * Q; o += nth) {
-      const int i3 = o % Q, a1 = (o / Q) % (P + 1), ec = o / (Q * (P + 1));
-      const int pb = pair_index(P, a1, 0);
-      double acc[Q];
-#pragma unroll
-      for (int i = 0; i < Q; ++i) acc[i] = 0.0;
-#pragma unroll XL
-      for (int a2 = 0; a2 <= P; ++a2) {
-        if (a2 <= P - a1) {
-          const double x = T1[(ec * S::NPAIR + pb + a2) * Q + i3];
-          const double* ps = T.psi2 + (a1 * (P + 1) + a2) * Q;
-#pragma unroll
-          for (int i = 0; i < Q; ++i) acc[i] += ps[i] * x;
-        }
-      }
-#pragma unroll
-      for (int i = 0; i < Q; ++i) T2[(ec * (P + 1) + a1) * Q * Q + i + Q * i3] = acc[i];
-    }
-    __syncthreads();
-    // out[ec][i1 + Q i2 + Q^2 i3] = sum_a1 psi1[a1][i1] T2[ec][a1][i2 + Q i3]
-    for (int o = tid; o < nec * Q * Q; o += nth) {
-      const int i23 = o % (Q * Q), ec = o / (Q * Q);
-      double acc[Q];
-#pragma unroll
-      for (int i = 0; i < Q; ++i) acc[i] = 0.0;
-#pragma unroll XU
-      for (int a1 = 0; a1 <= P; ++a1) {
-        const double x = T2[(ec * (P + 1) + a1) * Q * Q + i23];
-#pragma unroll
-        for (int i = 0; i < Q; ++i) acc[i] += T.psi1[a1 * Q + i] * x;
-      }
-#pragma unroll
-      for (int i = 0; i < Q; ++i) out[ec * S::NQ + i + Q * i23] = acc[i];
-    }
-    __syncthreads();
   }
 }
 
+// V, middle stage of tetrahedra: T2[ec][a1][i2 + Q i3] = sum_a2 psi2[a1][a2][i2] T1[ec][(a1,a2)][i3]
+template <int P>
+__device__ __forceinline__ void v_second(const double* T1, double* T2, const DevTables& T, int nec) {
+  using S = Shape<3, P>;
+  constexpr int Q = S::Q, XL = Q <= 8 ? Q : Unroll<P>::XU;
+  const int tid = threadIdx.x, nth = blockDim.x;
+  for (int o = tid; o < nec * (P + 1) * Q; o += nth) {
+    const int i3 = o % Q, a1 = (o / Q) % (P + 1), ec = o / (Q * (P + 1));
+    const int pb = pair_index(P, a1, 0);
+    double acc[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) acc[i] = 0.0;
+#pragma unroll XL
+    for (int a2 = 0; a2 <= P; ++a2) {
+      if (a2 <= P - a1) {
+        const double x = T1[(ec * S::NPAIR + pb + a2) * Q + i3];
+        const double* ps = T.psi2 + (a1 * (P + 1) + a2) * Q;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) acc[i] += ps[i] * x;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i) T2[(ec * (P + 1) + a1) * Q * Q + i + Q * i3] = acc[i];
+  }
+}
+
+// V, last stage: sum over a1 with psi1 into the nodes (Tin is T1 on
+// triangles, T2 on tetrahedra)
 template <int DIM, int P>
-__device__ __forceinline__ void xform_Vt(const double* in, double* T1, double* T2, double* out, const DevTables& T, int nec) {
+__device__ __forceinline__ void v_last(const double* Tin, double* out, const DevTables& T, int nec) {
   using S = Shape<DIM, P>;
-  constexpr int Q = S::Q;
-  constexpr int XU = Q <= 7 ? Q : 1;   // unroll the contraction while its table fits scalar registers
-  // stages whose table is indexed per lane (read from LDS) unroll one degree
-  // further on tetrahedra (measured: K1 at p = 7 2.49 -> 2.19 ms; p = 8 unchanged)
+  constexpr int Q = S::Q, XU = Unroll<P>::XU;
+  constexpr int L = DIM == 2 ? Q : Q * Q;   // lines of the last stage per (element, variable)
+  const int tid = threadIdx.x, nth = blockDim.x;
+  // out[ec][i1 + Q l] = sum_a1 psi1[a1][i1] Tin[ec][a1][l]
+  for (int o = tid; o < nec * L; o += nth) {
+    const int l = o % L, ec = o / L;
+    double acc[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) acc[i] = 0.0;
+#pragma unroll XU
+    for (int a1 = 0; a1 <= P; ++a1) {
+      const double x = Tin[(ec * (P + 1) + a1) * L + l];
+#pragma unroll
+      for (int i = 0; i < Q; ++i) acc[i] += T.psi1[a1 * Q + i] * x;
+    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i) out[ec * S::NQ + i + Q * l] = acc[i];
+  }
+}
+
+// V^T, first stage: sum over i1 with psi1 (out is T1 on triangles, T2 on tetrahedra)
+template <int DIM, int P>
+__device__ __forceinline__ void vt_first(const double* in, double* Tout, const DevTables& T, int nec) {
+  using S = Shape<DIM, P>;
+  constexpr int Q = S::Q, XU = Unroll<P>::XU;
+  constexpr int L = DIM == 2 ? Q : Q * Q;
+  const int tid = threadIdx.x, nth = blockDim.x;
+  // Tout[ec][a1][l] = sum_i1 psi1[a1][i1] in[ec][i1 + Q l]
+  for (int o = tid; o < nec * L; o += nth) {
+    const int l = o % L, ec = o / L;
+    double acc[P + 1];
+#pragma unroll
+    for (int a = 0; a <= P; ++a) acc[a] = 0.0;
+#pragma unroll XU
+    for (int i1 = 0; i1 < Q; ++i1) {
+      const double x = in[ec * S::NQ + i1 + Q * l];
+#pragma unroll
+      for (int a = 0; a <= P; ++a) acc[a] += T.psi1[a * Q + i1] * x;
+    }
+#pragma unroll
+    for (int a = 0; a <= P; ++a) Tout[(ec * (P + 1) + a) * L + l] = acc[a];
+  }
+}
+
+// V^T, middle stage of tetrahedra: T1[ec][(a1,a2)][i3] = sum_i2 psi2[a1][a2][i2] T2[ec][a1][i2 + Q i3]
+template <int P>
+__device__ __forceinline__ void vt_second(const double* T2, double* T1, const DevTables& T, int nec) {
+  using S = Shape<3, P>;
+  constexpr int Q = S::Q, XL = Q <= 8 ? Q : Unroll<P>::XU;
+  const int tid = threadIdx.x, nth = blockDim.x;
+  for (int o = tid; o < nec * (P + 1) * Q; o += nth) {
+    const int i3 = o % Q, a1 = (o / Q) % (P + 1), ec = o / (Q * (P + 1));
+    const int pb = pair_index(P, a1, 0);
+    double acc[P + 1];
+#pragma unroll
+    for (int a = 0; a <= P; ++a) acc[a] = 0.0;
+#pragma unroll XL
+    for (int i2 = 0; i2 < Q; ++i2) {
+      const double x = T2[(ec * (P + 1) + a1) * Q * Q + i2 + Q * i3];
+#pragma unroll
+      for (int a = 0; a <= P; ++a) acc[a] += T.psi2[(a1 * (P + 1) + a) * Q + i2] * x;
+    }
+#pragma unroll
+    for (int a = 0; a <= P; ++a)
+      if (a <= P - a1) T1[(ec * S::NPAIR + pb + a) * Q + i3] = acc[a];
+  }
+}
+
+// V^T, last stage: the nodes of the last direction to its modes
+template <int DIM, int P>
+__device__ __forceinline__ void vt_last(const double* T1, double* out, const DevTables& T, int nec) {
+  using S = Shape<DIM, P>;
+  constexpr int Q = S::Q, XU = Unroll<P>::XU;
   constexpr int XL = (DIM == 3 && Q <= 8) ? Q : XU;
   const int tid = threadIdx.x, nth = blockDim.x;
   if constexpr (DIM == 2) {
-    // T1[ec][a1][i2] = sum_i1 psi1[a1][i1] in[ec][i1 + Q i2]
-    for (int o = tid; o < nec * Q; o += nth) {
-      const int i2 = o % Q, ec = o / Q;
-      double acc[P + 1];
-#pragma unroll
-      for (int a = 0; a <= P; ++a) acc[a] = 0.0;
-#pragma unroll XU
-      for (int i1 = 0; i1 < Q; ++i1) {
-        const double x = in[ec * S::NQ + i1 + Q * i2];
-#pragma unroll
-        for (int a = 0; a <= P; ++a) acc[a] += T.psi1[a * Q + i1] * x;
-      }
-#pragma unroll
-      for (int a = 0; a <= P; ++a) T1[(ec * (P + 1) + a) * Q + i2] = acc[a];
-    }
-    __syncthreads();
     // out[ec][(a1,a2)] = sum_i2 psi2[a1][a2][i2] T1[ec][a1][i2]
     for (int o = tid; o < nec * (P + 1); o += nth) {
       const int a1 = o % (P + 1), ec = o / (P + 1);
@@ -308,7 +364,7 @@ __device__ __forceinline__ void xform_Vt(const double* in, double* T1, double* T
       double acc[P + 1];
 #pragma unroll
       for (int a = 0; a <= P; ++a) acc[a] = 0.0;
-#pragma unroll XL
+#pragma unroll XU
       for (int i2 = 0; i2 < Q; ++i2) {
         const double x = T1[(ec * (P + 1) + a1) * Q + i2];
 #pragma unroll
@@ -318,42 +374,7 @@ __device__ __forceinline__ void xform_Vt(const double* in, double* T1, double* T
       for (int a = 0; a <= P; ++a)
         if (a <= P - a1) out[ec * S::NP + mb + a] = acc[a];
     }
-    __syncthreads();
   } else {
-    // T2[ec][a1][i2 + Q i3] = sum_i1 psi1[a1][i1] in[ec][i1 + Q i2 + Q^2 i3]
-    for (int o = tid; o < nec * Q * Q; o += nth) {
-      const int i23 = o % (Q * Q), ec = o / (Q * Q);
-      double acc[P + 1];
-#pragma unroll
-      for (int a = 0; a <= P; ++a) acc[a] = 0.0;
-#pragma unroll XU
-      for (int i1 = 0; i1 < Q; ++i1) {
-        const double x = in[ec * S::NQ + i1 + Q * i23];
-#pragma unroll
-        for (int a = 0; a <= P; ++a) acc[a] += T.psi1[a * Q + i1] * x;
-      }
-#pragma unroll
-      for (int a = 0; a <= P; ++a) T2[(ec * (P + 1) + a) * Q * Q + i23] = acc[a];
-    }
-    __syncthreads();
-    // T1[ec][(a1,a2)][i3] = sum_i2 psi2[a1][a2][i2] T2[ec][a1][i2 + Q i3]
-    for (int o = tid; o < nec * (P + 1) * Q; o += nth) {
-      const int i3 = o % Q, a1 = (o / Q) % (P + 1), ec = o / (Q * (P + 1));
-      const int pb = pair_index(P, a1, 0);
-      double acc[P + 1];
-#pragma unroll
-      for (int a = 0; a <= P; ++a) acc[a] = 0.0;
-#pragma unroll XL
-      for (int i2 = 0; i2 < Q; ++i2) {
-        const double x = T2[(ec * (P + 1) + a1) * Q * Q + i2 + Q * i3];
-#pragma unroll
-        for (int a = 0; a <= P; ++a) acc[a] += T.psi2[(a1 * (P + 1) + a) * Q + i2] * x;
-      }
-#pragma unroll
-      for (int a = 0; a <= P; ++a)
-        if (a <= P - a1) T1[(ec * S::NPAIR + pb + a) * Q + i3] = acc[a];
-    }
-    __syncthreads();
     // out[ec][(a1,a2,a3)] = sum_i3 psi3[s][a3][i3] T1[ec][(a1,a2)][i3]
     for (int o = tid; o < nec * S::NPAIR; o += nth) {
       const int pr = o % S::NPAIR, ec = o / S::NPAIR;
@@ -373,8 +394,92 @@ __device__ __forceinline__ void xform_Vt(const double* in, double* T1, double* T
       for (int a = 0; a <= P; ++a)
         if (a <= P - s) out[ec * S::NP + mb + a] = acc[a];
     }
-    __syncthreads();
   }
+}
+
+// u = V u~ at the volume nodes (eq. modal_to_nodal, Sec. 5.2); ends with a barrier
+template <int DIM, int P>
+__device__ __forceinline__ void xform_V(const double* uh, double* T1, double* T2, double* out, const DevTables& T,
+                                        int nec) {
+  v_first<DIM, P>(uh, T1, T, nec);
+  __syncthreads();
+  if constexpr (DIM == 3) {
+    v_second<P>(T1, T2, T, nec);
+    __syncthreads();
+    v_last<DIM, P>(T2, out, T, nec);
+  } else {
+    v_last<DIM, P>(T1, out, T, nec);
+  }
+  __syncthreads();
+}
+
+// V^T applied to nodal fields; ends with a barrier
+template <int DIM, int P>
+__device__ __forceinline__ void xform_Vt(const double* in, double* T1, double* T2, double* out, const DevTables& T,
+                                         int nec) {
+  if constexpr (DIM == 3) {
+    vt_first<DIM, P>(in, T2, T, nec);
+    __syncthreads();
+    vt_second<P>(T2, T1, T, nec);
+  } else {
+    vt_first<DIM, P>(in, T1, T, nec);
+  }
+  __syncthreads();
+  vt_last<DIM, P>(T1, out, T, nec);
+  __syncthreads();
+}
+
+// V V^T applied to nodal fields (in may equal out).  V^T's last stage and V's
+// first contract the same direction (eta2 of triangles, eta3 of tetrahedra)
+// with the same table; on each line of that direction their composition is
+// the Q x Q matrix psiM[a] = sum_b psi[a][b] psi[a][b]^T (b over the line's
+// modes, a = a1 on triangles, a1 + a2 on tetrahedra), applied in place by the
+// thread owning the line: one stage and one barrier fewer.  Ends with a barrier.
+template <int DIM, int P>
+__device__ __forceinline__ void xform_VVt(const double* in, double* T1, double* T2, double* out, const DevTables& T,
+                                          int nec) {
+  using S = Shape<DIM, P>;
+  constexpr int Q = S::Q;
+  constexpr int NL = DIM == 2 ? P + 1 : S::NPAIR;   // lines of the composed direction per (element, variable)
+  const int tid = threadIdx.x, nth = blockDim.x;
+  if constexpr (DIM == 3) {
+    vt_first<DIM, P>(in, T2, T, nec);
+    __syncthreads();
+    vt_second<P>(T2, T1, T, nec);
+  } else {
+    vt_first<DIM, P>(in, T1, T, nec);
+  }
+  __syncthreads();
+  for (int o = tid; o < nec * NL; o += nth) {
+    const int line = o % NL;
+    int a = line;
+    if constexpr (DIM == 3) {
+      int a1, a2;
+      decode_pair(P, line, a1, a2);
+      a = a1 + a2;
+    }
+    double* t = T1 + (int64_t)o * Q;
+    double x[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) x[i] = t[i];
+    const double* m = T.psiM + a * Q * Q;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 0; k < Q; ++k) acc += m[i * Q + k] * x[k];
+      t[i] = acc;
+    }
+  }
+  __syncthreads();
+  if constexpr (DIM == 3) {
+    v_second<P>(T1, T2, T, nec);
+    __syncthreads();
+    v_last<DIM, P>(T2, out, T, nec);
+  } else {
+    v_last<DIM, P>(T1, out, T, nec);
+  }
+  __syncthreads();
 }
 
 // ------------------------------------------------------------------ loads issued ahead of their use

@@ -278,6 +278,20 @@ RefTables build_ref_tables(int dim, int p) {
       for (int a3 = 0; a3 <= p; ++a3) R.psi3[(s * P1 + a3) * Q + i] = 2.0 * ipow(1.0 - R.xj[i], s) * tmp[a3];
     }
   }
+  // V V^T along the direction V^T contracts last and V first (eta2 of
+  // triangles, eta3 of tetrahedra): per line index a (a1, or a1 + a2), the sum
+  // over that line's modes b <= p - a of psi[a][b][i] psi[a][b][k]
+  R.psiM.assign(P1 * Q * Q, 0.0);
+  {
+    const std::vector<double>& ps = dim == 2 ? R.psi2 : R.psi3;
+    for (int a = 0; a <= p; ++a)
+      for (int i = 0; i < Q; ++i)
+        for (int k = 0; k < Q; ++k) {
+          double acc = 0.0;
+          for (int b = 0; b <= p - a; ++b) acc += ps[(a * P1 + b) * Q + i] * ps[(a * P1 + b) * Q + k];
+          R.psiM[(a * Q + i) * Q + k] = acc;
+        }
+  }
   Lagrange1D LG(R.xl), GJ(R.xj);
   R.lgm1.resize(Q);
   R.lgp1.resize(Q);

@@ -33,6 +33,7 @@ struct RefTables {
   int dim = 0, p = 0, Q = 0, NQ = 0, NP = 0, NF = 0, NQF = 0, NFQ = 0;
   std::vector<double> xl, wl, xj, wj;        // LG and GJ(1,0) nodes / weights
   std::vector<double> psi1, psi2, psi3;      // PKD principal functions at the line nodes
+  std::vector<double> psiM;                  // [P+1][Q][Q] psi2 (tri) / psi3 (tet) line compositions, sum_b psi[a][b] psi[a][b]^T
   std::vector<double> lgm1, lgp1, gjm1;      // l(-1), l(+1) on LG; l(-1) on GJ
   std::vector<double> I42;                   // [j][k] = l^LG_k(eta^GJ_j)
   std::vector<double> A;                     // [5][Q][Q] skew line matrices

@@ -30,8 +30,9 @@ namespace esd {
 // ------------------------------------------------------------------ K1: entropy projection
 // w~ = V^T (w/J) V V^T b for b = (w J W) at the volume nodes in sA [nel*NC][NQ]
 // (eqs. entropy_expansion, matvec_entropy_projection); result in sM; aI holds
-// w/J at this thread's first nodes.  Ends with a barrier.
-template <int DIM, int P>
+// w/J at this thread's first nodes; VVT: V V^T as one composed transform (its
+// table staged).  Ends with a barrier.
+template <int DIM, int P, bool VVT>
 __device__ __forceinline__ void weight_adjusted_projection(double* sM, double* sA, double* sS, const DevTables& T,
                                                            const double* __restrict__ gvol, int64_t e0, int nel,
                                                            const Ahead<2>& aI) {
@@ -42,8 +43,12 @@ __device__ __forceinline__ void weight_adjusted_projection(double* sM, double* s
   double* T1 = sS;
   double* T2 = sS + EPB * Sh::T1;
   auto ld_wi = [&](int o) { return gvol[((e0 + o / NQ) * NGV + NGV - 1) * NQ + o % NQ]; };
-  xform_Vt<DIM, P>(sA, T1, T2, sM, T, nec);
-  xform_V<DIM, P>(sM, T1, T2, sA, T, nec);
+  if constexpr (VVT) {
+    xform_VVt<DIM, P>(sA, T1, T2, sA, T, nec);
+  } else {
+    xform_Vt<DIM, P>(sA, T1, T2, sM, T, nec);
+    xform_V<DIM, P>(sM, T1, T2, sA, T, nec);
+  }
   aI.each(nel * NQ, ld_wi, [&](int o, double wi) {
     const int k = o % NQ, el = o / NQ;
 #pragma unroll
@@ -58,7 +63,7 @@ __device__ __forceinline__ void weight_adjusted_projection(double* sM, double* s
 // weight-adjusted projection, written to wt, and the facet values R V w~
 // (eqs. r_2d, r_3d) to wf.  aJ and aI hold w J and w/J at this thread's first
 // nodes.  Uses sA [nel*NC][NQ] and the transform scratch sS.
-template <int DIM, int P>
+template <int DIM, int P, bool VVT>
 __device__ __forceinline__ void project_block(double* sM, double* sA, double* sS, const DevTables& T,
                                               const double* __restrict__ gvol, const Scheme& S, int64_t e0,
                                               int nel, int* flag, double* __restrict__ wt, double* __restrict__ wf,
@@ -94,7 +99,7 @@ __device__ __forceinline__ void project_block(double* sM, double* sA, double* sS
   });
   if (bad) atomicOr(flag, 1);
   __syncthreads();
-  weight_adjusted_projection<DIM, P>(sM, sA, sS, T, gvol, e0, nel, aI);
+  weight_adjusted_projection<DIM, P, VVT>(sM, sA, sS, T, gvol, e0, nel, aI);
   for (int o = tid; o < nec * NP; o += nth) wt[e0 * NC * NP + o] = sM[o];
   // facet values of the projected entropy variables, w^z = R^z V w~
   xform_V<DIM, P>(sM, T1, T2, sA, T, nec);
@@ -112,7 +117,12 @@ k_entropy_projection(const double* __restrict__ u, double* __restrict__ wt, doub
   __shared__ double sM[EPB * NC * NP];
   __shared__ double sA[EPB * NC * NQ];
   __shared__ double sS[EPB * Sh::SCR];
-  constexpr unsigned TM = tab_mask<DIM, P, TAB_PSI | TAB_FACET>(8 * EPB * (NC * NP + NC * NQ + Sh::SCR));
+  constexpr int KB = 8 * EPB * (NC * NP + NC * NQ + Sh::SCR);
+  // the composed V V^T table only where it keeps the workgroups per CU
+  constexpr unsigned TM = tab_keeps_wgs<DIM, P, TAB_PSI | TAB_FACET, TAB_PSI | TAB_FACET | TAB_PSIM>(KB, wave_cap<DIM, P>())
+                              ? (TAB_PSI | TAB_FACET | TAB_PSIM)
+                              : tab_mask<DIM, P, TAB_PSI | TAB_FACET>(KB);
+  constexpr bool VVT = (TM & TAB_PSIM) != 0;
   __shared__ double sTab[TM ? TabLds<DIM, P, TM>::SIZE : 1];
   const DevTables T = stage_tables<DIM, P, TM>(T0, sTab);
   const int64_t e0 = (int64_t)blockIdx.x * EPB;
@@ -132,14 +142,14 @@ k_entropy_projection(const double* __restrict__ u, double* __restrict__ wt, doub
       sA[(el * NC + c) * NQ + k] = wJ * u[(e0 * NQ) * NC + o];
     }
     __syncthreads();
-    weight_adjusted_projection<DIM, P>(sM, sA, sS, T, gvol, e0, nel, aI);
+    weight_adjusted_projection<DIM, P, VVT>(sM, sA, sS, T, gvol, e0, nel, aI);
     for (int o = tid; o < nec * NP; o += nth) wt[e0 * NC * NP + o] = sM[o];
   } else {
     aJ.load(nel * NQ, ld_wJ);
     aI.load(nel * NQ, ld_wi);
     for (int o = tid; o < nec * NP; o += nth) sM[o] = u[e0 * NC * NP + o];
     __syncthreads();
-    project_block<DIM, P>(sM, sA, sS, T, gvol, S, e0, nel, flag, wt, wf, aJ, aI);
+    project_block<DIM, P, VVT>(sM, sA, sS, T, gvol, S, e0, nel, flag, wt, wf, aJ, aI);
   }
 }
 
@@ -242,13 +252,17 @@ k_rhs(const double* __restrict__ wt, const double* __restrict__ wfb, double* __r
   // projection of the next stage also reads the facet tables.  The facet
   // correction and interface phases, which run while sF holds the facet
   // records, read their tables from T0.
-  constexpr unsigned WANT = NEXT ? (TAB_PSI | TAB_FACET) : TAB_PSI;
-  constexpr bool FIT_ALL = DIM == 3 && FLDS && 8 * NFQ >= NC * NP + TabLds<DIM, P, WANT>::SIZE;
-  constexpr bool FIT_PSI = DIM == 3 && FLDS && 8 * NFQ >= NC * NP + TabLds<DIM, P, TAB_PSI>::SIZE;
+  constexpr unsigned W0 = NEXT ? (TAB_PSI | TAB_FACET) : TAB_PSI;
+  constexpr unsigned W1 = W0 | TAB_PSIM;   // with the composed stage of V V^T
+  constexpr int ROOM = (DIM == 3 && FLDS) ? 8 * NFQ - NC * NP : -1;   // doubles free in sF's tail
+  constexpr int KB = 8 * (EPB * (Sh::SCR + NC * NQ + NC * NFQ) + (FLDS ? EPB * 8 * NFQ : 1));
   constexpr unsigned TM =
-      DIM == 2 ? tab_mask<DIM, P, WANT>(8 * (EPB * (Sh::SCR + NC * NQ + NC * NFQ) + (FLDS ? EPB * 8 * NFQ : 1)))
-               : (FIT_ALL ? WANT : (FIT_PSI ? TAB_PSI : 0u));
+      DIM == 2 ? (tab_keeps_wgs<DIM, P, W0, W1>(KB, wave_cap<DIM, P>()) ? W1 : tab_mask<DIM, P, W0>(KB))
+               : (TabLds<DIM, P, W1>::SIZE <= ROOM   ? W1
+                  : TabLds<DIM, P, W0>::SIZE <= ROOM ? W0
+                  : TabLds<DIM, P, TAB_PSI>::SIZE <= ROOM ? TAB_PSI : 0u);
   constexpr bool TAB_SF = DIM == 3 && TM != 0;
+  constexpr bool VVT = (TM & TAB_PSIM) != 0;
   static_assert(!TAB_SF || EPB == 1, "one element per workgroup when the tables share sF");
   __shared__ double sTab[DIM == 2 && TM ? TabLds<DIM, P, TM>::SIZE : 1];
   double* const tab_buf = TAB_SF ? sF + NC * NP : sTab;
@@ -435,8 +449,12 @@ k_rhs(const double* __restrict__ wt, const double* __restrict__ wfb, double* __r
   __syncthreads();
 
   // ---- du~/dt = V^T (w/J) V V^T r
-  xform_Vt<DIM, P>(sR, T1, T2, sM, T, nec);
-  xform_V<DIM, P>(sM, T1, T2, sR, T, nec);
+  if constexpr (VVT) {
+    xform_VVt<DIM, P>(sR, T1, T2, sR, T, nec);
+  } else {
+    xform_Vt<DIM, P>(sR, T1, T2, sM, T, nec);
+    xform_V<DIM, P>(sM, T1, T2, sR, T, nec);
+  }
   aI.each(nel * NQ, ld_wi, [&](int o, double wi) {
     const int k = o % NQ, el = o / NQ;
 #pragma unroll
@@ -489,7 +507,7 @@ k_rhs(const double* __restrict__ wt, const double* __restrict__ wfb, double* __r
   if constexpr (NEXT) {
     // entropy projection of the next stage input, into the other workspace
     __syncthreads();
-    project_block<DIM, P>(sM, sR, sN, T, gvol, S, e0, nel, flag, epi.wt_next, epi.wf_next, aJ, aI);
+    project_block<DIM, P, VVT>(sM, sR, sN, T, gvol, S, e0, nel, flag, epi.wt_next, epi.wf_next, aJ, aI);
   }
 }
 

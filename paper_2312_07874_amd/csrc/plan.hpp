@@ -26,6 +26,7 @@ struct DevTables {
   const double* wl;     // [Q]
   const double* wj;     // [Q]
   const double* xl;     // [Q]
+  const double* psiM;   // [P+1][Q][Q] line compositions of V V^T
 };
 
 // Classical RK4 stage combination fused into the right-hand-side kernel's
