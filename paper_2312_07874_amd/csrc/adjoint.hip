@@ -143,7 +143,12 @@ k_rhs_vjp(const double* __restrict__ wt, const double* __restrict__ wfb, const d
   constexpr int CAP = 8 / ((VjpLaunch<DIM, P>::BS + 63) / 64);
   constexpr int WG_T = LDS_BYTES / (VB + VT) < CAP ? LDS_BYTES / (VB + VT) : CAP;
   constexpr int WG_N = LDS_BYTES / VB < CAP ? LDS_BYTES / VB : CAP;
-  constexpr unsigned TM = WG_T >= WG_N ? tab_mask<DIM, P, TAB_PSI | TAB_FACET>(VB) : 0u;
+  constexpr unsigned T0M = WG_T >= WG_N ? tab_mask<DIM, P, TAB_PSI | TAB_FACET>(VB) : 0u;
+  // with the composed V V^T table where that keeps the workgroups per CU too
+  constexpr unsigned TM =
+      T0M != 0 && tab_keeps_wgs<DIM, P, TAB_PSI | TAB_FACET, TAB_PSI | TAB_FACET | TAB_PSIM>(VB, CAP)
+          ? (TAB_PSI | TAB_FACET | TAB_PSIM)
+          : T0M;
   __shared__ double sTab[TM ? TabLds<DIM, P, TM>::SIZE : 1];
   const DevTables T = stage_tables<DIM, P, TM>(T0, sTab);
   const int64_t e0 = (int64_t)blockIdx.x * EPB;
@@ -162,8 +167,12 @@ k_rhs_vjp(const double* __restrict__ wt, const double* __restrict__ wfb, const d
     sR[o] *= gvol[((e0 + le) * NGV + NGV - 1) * NQ + k];
   }
   __syncthreads();
-  xform_Vt<DIM, P>(sR, T1, T2, sX, T, nec);
-  xform_V<DIM, P>(sX, T1, T2, sR, T, nec);
+  if constexpr ((TM & TAB_PSIM) != 0) {
+    xform_VVt<DIM, P>(sR, T1, T2, sR, T, nec);
+  } else {
+    xform_Vt<DIM, P>(sR, T1, T2, sX, T, nec);
+    xform_V<DIM, P>(sX, T1, T2, sR, T, nec);
+  }
 
   // ---- forward node states: w = V w~ at volume nodes, own facet values
   for (int o = tid; o < nec * NP; o += nth) sX[o] = wt[e0 * NC * NP + o];
@@ -397,8 +406,11 @@ k_projection_vjp(const double* __restrict__ u, double* g, const double* __restri
   __shared__ double sA[EPB * NC * NQ];
   __shared__ double sB[EPB * NC * NB];      // gathered facet cotangents, later u at the nodes
   __shared__ double sS[EPB * Sh::SCR];
+  constexpr int KB = 8 * EPB * (NC * NP + NC * NQ + NC * NB + Sh::SCR);
   constexpr unsigned TM =
-      tab_mask<DIM, P, TAB_PSI | TAB_FACET>(8 * EPB * (NC * NP + NC * NQ + NC * NB + Sh::SCR));
+      tab_keeps_wgs<DIM, P, TAB_PSI | TAB_FACET, TAB_PSI | TAB_FACET | TAB_PSIM>(KB, wave_cap<DIM, P>())
+          ? (TAB_PSI | TAB_FACET | TAB_PSIM)
+          : tab_mask<DIM, P, TAB_PSI | TAB_FACET>(KB);
   __shared__ double sTab[TM ? TabLds<DIM, P, TM>::SIZE : 1];
   const DevTables T = stage_tables<DIM, P, TM>(T0, sTab);
   const int64_t e0 = (int64_t)blockIdx.x * EPB;
@@ -429,8 +441,12 @@ k_projection_vjp(const double* __restrict__ u, double* g, const double* __restri
     sA[o] *= gvol[((e0 + le) * NGV + NGV - 1) * NQ + k];
   }
   __syncthreads();
-  xform_Vt<DIM, P>(sA, T1, T2, sM, T, nec);
-  xform_V<DIM, P>(sM, T1, T2, sA, T, nec);
+  if constexpr ((TM & TAB_PSIM) != 0) {
+    xform_VVt<DIM, P>(sA, T1, T2, sA, T, nec);
+  } else {
+    xform_Vt<DIM, P>(sA, T1, T2, sM, T, nec);
+    xform_V<DIM, P>(sM, T1, T2, sA, T, nec);
+  }
   for (int o = tid; o < nec * NQ; o += nth) {
     const int k = o % NQ, le = o / (NC * NQ);
     sA[o] *= gvol[((e0 + le) * NGV + NGV - 2) * NQ + k];

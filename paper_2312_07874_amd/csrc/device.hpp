@@ -463,7 +463,9 @@ __device__ __forceinline__ void xform_VVt(const double* in, double* T1, double* 
 #pragma unroll
     for (int i = 0; i < Q; ++i) x[i] = t[i];
     const double* m = T.psiM + a * Q * Q;
-#pragma unroll
+    // rows rolled above Q = 7: unrolled, the compiler keeps all Q^2 table
+    // values in registers
+#pragma unroll Unroll<P>::XU
     for (int i = 0; i < Q; ++i) {
       double acc = 0.0;
 #pragma unroll
