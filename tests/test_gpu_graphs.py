@@ -126,6 +126,19 @@ def test_fused_rk4_single_plans():
         _fused_matches_stage_by_stage(plan, u0, 2e-3)
 
 
+@pytest.mark.parametrize("dim,p", [(2, 9), (2, 10), (3, 9), (3, 10)])
+def test_fused_rk4_high_degree(dim, p):
+    """The fused stage kernel where K2 keeps its tables in the facet-record
+    buffer's tail (tet p = 9), keeps its facet records in the workspace
+    (tet p = 10) or runs three triangles per workgroup (tri p >= 8)."""
+    wk = wl.random_tri(M=3, degree=p, seed=11) if dim == 2 else wl.random_tet(M=3, degree=p, seed=13)
+    plan = gpu_plan(wk)
+    x = plan.node_coords().cpu().numpy()
+    u0 = plan.project(torch.tensor(wk.state(x), device="cuda").contiguous())
+    log(f"{wk.name}")
+    _fused_matches_stage_by_stage(plan, u0, 1e-3)
+
+
 def test_fused_rk4_batched_plan():
     import paper_2312_07874_amd as esd
     L = 2 * math.pi
