@@ -5,7 +5,8 @@ residual (pinned by finite differences and the dot-product identity in
 test_oracle_vjp).  Small meshes are compared in full with the same seeded
 state and cotangent; benchmark-size meshes on sampled elements (the oracle
 differentiates their 1-ring); the library's own VJP is also checked against
-central differences of its own residual at full size, and the discrete RK4
+central differences of its own residual at full size and at tet p = 6-8
+(entropy-conservative flux, where the residual is smooth), and the discrete RK4
 adjoint against the oracle's autograd through its RK4 and against central
 differences of a kinetic-energy objective after 20 steps on 10,368 curved
 tetrahedra at p = 6."""
@@ -151,6 +152,49 @@ def test_vjp_matches_central_differences_full_size():
         log(f"direction {k}: fd {fd:.12e} adjoint {ad:.12e} rel {abs(fd - ad) / abs(ad):.2e}")
         assert abs(fd - ad) <= 1e-6 * abs(ad)
     plan.sync_status()
+
+
+@pytest.mark.parametrize("p", [6, 7, 8])
+def test_vjp_matches_central_differences_high_degree(p):
+    """The same identity on a small curved tetrahedral mesh at p = 6-8 (the
+    adjoint kernels' LDS-table and composed-transform variants there), library
+    only.  The interface flux is the entropy-conservative one: with the Davis
+    wave speed (a maximum of two states that nearly agree on a smooth field)
+    the residual has kinks, and central differences there stall near 1e-5
+    relative at any h, while the smooth residual converges as h^2 (about 1e-9
+    relative at h = 1e-6).  The dissipative branch is checked against the
+    oracle below."""
+    wk = wl.random_tet(M=3, degree=p, seed=40 + p, dissipation=0)
+    plan = gpu_plan(wk)
+    x = plan.node_coords().cpu().numpy()
+    u = plan.project(torch.tensor(wk.state(x), device="cuda").contiguous())
+    vbar = cotangent(tuple(u.shape), 41).cuda()
+    g = plan.vjp(u, vbar)
+    h = 1e-6
+    for k in range(3):
+        d = cotangent(tuple(u.shape), 200 + k).cuda()
+        fp = (plan.residual((u + h * d).contiguous()) * vbar).sum()
+        fm = (plan.residual((u - h * d).contiguous()) * vbar).sum()
+        fd = float((fp - fm) / (2 * h))
+        ad = float((g * d).sum())
+        log(f"p {p} direction {k}: fd {fd:.12e} adjoint {ad:.12e} rel {abs(fd - ad) / abs(ad):.2e}")
+        assert abs(fd - ad) <= 1e-6 * abs(ad)
+    plan.sync_status()
+
+
+def test_vjp_parity_tet_p7_lax_friedrichs_sampled():
+    """Tet p = 7 with the Davis dissipation against the oracle on 4 sampled
+    elements (above the degrees the full-mesh comparisons reach)."""
+    wk = wl.random_tet(M=3, degree=7, seed=13)
+    prob = oracle_problem(wk)
+    ut = oracle_state(prob, wk)
+    vbar = cotangent(ut.shape, 29)
+    plan = gpu_plan(wk)
+    out = plan.vjp(ut.cuda().contiguous(), vbar.cuda().contiguous()).cpu()
+    plan.sync_status()
+    el = np.random.default_rng(5).choice(prob.ne, 4, replace=False)
+    ref = oracle_vjp_pair(prob, ut, vbar, el)
+    assert_close(out[el], ref, wk.name)
 
 
 def test_residual_autograd_function():
