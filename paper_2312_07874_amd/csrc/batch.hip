@@ -19,34 +19,72 @@ namespace esd {
 // the neighbour's w~ (at most 5 x 286 values) is staged in LDS.
 constexpr int MIX_MAX_NP = 286;   // PKD modes of a degree-10 tetrahedron
 
-// NC (variables) fixed at compile time and the contraction unrolled by 8, so
-// that several matrix rows are in flight per thread (measured on the batch of
-// 35,904 tetrahedra: 2.5 -> 0.8 ms per residual for this kernel)
+// NC (variables) fixed at compile time and the contraction unrolled, so that
+// several matrix rows are in flight per thread (measured on the batch of 35,904
+// tetrahedra: 2.5 -> 0.8 ms per residual for this kernel).  A facet of few
+// nodes (nqf <= 42: tetrahedra up to p = 5, every triangle) leaves most of the
+// 128 lanes idle and one lane walking all np modes; there the lanes split into
+// S = 128 / nqf >= 3 slices, slice s summing the modes k = s, s + S, ..., and
+// the slices' partial sums are added in LDS.  Same batch, per launch: buckets
+// of p = 2..5 80 -> 50-72 us; p = 6, 7 (one lane per node) 78 -> 88 us, the
+// same with two slices, so not the split (the partial-sum array adds 5 KB of
+// LDS per workgroup); p = 8..10 unchanged; 0.83 -> 0.76 ms per residual.
+constexpr int MIX_BLOCK = 128;
+
 template <int NC>
-__global__ void __launch_bounds__(128)
+__global__ void __launch_bounds__(MIX_BLOCK)
 k_mixed_exterior(const int32_t* __restrict__ tasks, const double* __restrict__ ws_base,
                  const int64_t* __restrict__ wt_off, const double* __restrict__ mats,
                  const int64_t* __restrict__ mat_off, double* __restrict__ wext, int nfq, int nqf) {
   __shared__ double sW[5 * MIX_MAX_NP];
+  __shared__ double sR[NC * MIX_BLOCK];
   const int32_t* t = tasks + 8 * (int64_t)blockIdx.x;
   const int slot = t[0], face = t[1], nbb = t[2], nbs = t[3], mat = t[4], np = t[6];
   const double* wtn = ws_base + wt_off[nbb] + (int64_t)nbs * NC * np;
-  for (int o = threadIdx.x; o < NC * np; o += blockDim.x) sW[o] = wtn[o];
+  for (int o = threadIdx.x; o < NC * np; o += MIX_BLOCK) sW[o] = wtn[o];
   __syncthreads();
   const double* IT = mats + mat_off[mat];
   double* dst = wext + (int64_t)slot * NC * nfq + face * nqf;
-  for (int j = threadIdx.x; j < nqf; j += blockDim.x) {
-    double acc[NC];
+  if (3 * nqf > MIX_BLOCK) {
+    for (int j = threadIdx.x; j < nqf; j += MIX_BLOCK) {
+      double acc[NC];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+      for (int c = 0; c < NC; ++c) acc[c] = 0.0;
 #pragma unroll 8
-    for (int k = 0; k < np; ++k) {
+      for (int k = 0; k < np; ++k) {
+        const double a = IT[(int64_t)k * nqf + j];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[c] += a * sW[c * np + k];
+      }
+#pragma unroll
+      for (int c = 0; c < NC; ++c) dst[c * nfq + j] = acc[c];
+    }
+    return;
+  }
+  // nqf <= 42: thread = (slice s, node j), s < S = MIX_BLOCK / nqf
+  const int S = MIX_BLOCK / nqf;
+  const int s = threadIdx.x / nqf, j = threadIdx.x - s * nqf;
+  double acc[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+  if (s < S) {
+#pragma unroll 4
+    for (int k = s; k < np; k += S) {
       const double a = IT[(int64_t)k * nqf + j];
 #pragma unroll
       for (int c = 0; c < NC; ++c) acc[c] += a * sW[c * np + k];
     }
+  }
 #pragma unroll
-    for (int c = 0; c < NC; ++c) dst[c * nfq + j] = acc[c];
+  for (int c = 0; c < NC; ++c) sR[c * MIX_BLOCK + threadIdx.x] = acc[c];
+  __syncthreads();
+  if (threadIdx.x < nqf) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      double v = 0.0;
+      for (int r = 0; r < S; ++r) v += sR[c * MIX_BLOCK + r * nqf + threadIdx.x];
+      dst[c * nfq + threadIdx.x] = v;
+    }
   }
 }
 
@@ -56,10 +94,10 @@ int launch_mixed_exterior(const esd_plan* b, const esd_plan* top, const double* 
   const int nfq = b->ref.NFQ, nqf = b->ref.NQF;
   double* wext = ws.wf + b->ne * b->nc * nfq;
   if (b->nc == 5)
-    hipLaunchKernelGGL(k_mixed_exterior<5>, dim3((unsigned)b->n_tasks), dim3(128), 0, s, b->d_tasks, ws_base,
+    hipLaunchKernelGGL(k_mixed_exterior<5>, dim3((unsigned)b->n_tasks), dim3(MIX_BLOCK), 0, s, b->d_tasks, ws_base,
                        top->d_wt_off, top->d_mats, top->d_mat_off, wext, nfq, nqf);
   else
-    hipLaunchKernelGGL(k_mixed_exterior<4>, dim3((unsigned)b->n_tasks), dim3(128), 0, s, b->d_tasks, ws_base,
+    hipLaunchKernelGGL(k_mixed_exterior<4>, dim3((unsigned)b->n_tasks), dim3(MIX_BLOCK), 0, s, b->d_tasks, ws_base,
                        top->d_wt_off, top->d_mats, top->d_mat_off, wext, nfq, nqf);
   return (int)hipGetLastError();
 }

@@ -63,7 +63,17 @@ def test_equal_degree_batch_equals_the_single_plan():
             assert err <= 1e-13 * scale, f"bucket {b}"
 
 
-def _oracle_compare(plan, meshes, degrees, warp, state, ecflux, dissipation, what, sample=None):
+def _oracle_compare(plan, meshes, degrees, warp, state, ecflux, dissipation, what, sample=None,
+                    rounding_floor=False):
+    """Batched residual against the oracle's mixed-degree residual, per
+    conserved variable: max |r_gpu - r_oracle| / ||r_oracle||_inf <= 1e-12.
+    With rounding_floor the bar is max(1e-12, 4 (d_o + d_l)), d_o and d_l the
+    oracle's and the library's own change (same measure) when every input
+    coefficient is scaled by 1 + 2^-52 z, z ~ N(0, 1): at high degree the
+    residual cancels to the point where one ulp of input noise moves either
+    evaluation by about 5e-13 of its size, and two correct FP64 evaluations
+    differ by their two rounding floors together; the factor 4 covers the
+    rounding of the intermediate steps, which input noise does not model."""
     from oracle import mixed as MX
     u = None
     worst = 0.0
@@ -86,6 +96,10 @@ def _oracle_compare(plan, meshes, degrees, warp, state, ecflux, dissipation, wha
     out = plan.residual(u.cuda().contiguous())
     plan.sync_status()
     out = out.cpu()
+    if rounding_floor:
+        z = torch.as_tensor(np.random.default_rng(19).standard_normal(tuple(u.shape)), dtype=u.dtype)
+        out_noisy = plan.residual((u * (1 + 2.0 ** -52 * z)).cuda().contiguous()).cpu()
+        plan.sync_status()
     base = 0
     for k, (m, deg) in enumerate(zip(meshes, degrees)):
         el = np.arange(m.n_elements) if sample is None else sample
@@ -100,9 +114,26 @@ def _oracle_compare(plan, meshes, degrees, warp, state, ecflux, dissipation, wha
             err = np.maximum(err, (got - ref[i]).abs().amax(1).numpy())
         rel = err / scale
         log(f"batched parity {what} mesh {k}: max err / ||r_e||_inf per var {['%.1e' % x for x in rel]}")
-        worst = max(worst, float(rel.max()))
+        tol = np.full(nc, 1e-12)
+        if rounding_floor:
+            z = np.random.default_rng(17)
+            up = {p: v * (1 + 2.0 ** -52 * torch.as_tensor(z.standard_normal(tuple(v.shape)), dtype=v.dtype))
+                  for p, v in utss[k].items()}
+            ref2 = MX.residual(mps[k], up, el)
+            d_ora, d_gpu = np.zeros(nc), np.zeros(nc)
+            for i, e in enumerate(el):
+                g = base + int(e)
+                b, s = int(plan.elem_bucket[g]), int(plan.elem_slot[g])
+                d_ora = np.maximum(d_ora, (ref2[i] - ref[i]).abs().amax(1).numpy())
+                d_gpu = np.maximum(d_gpu, (plan.bucket_view(out_noisy, b)[s] - plan.bucket_view(out, b)[s])
+                                   .abs().amax(1).numpy())
+            d_ora, d_gpu = d_ora / scale, d_gpu / scale
+            log(f"  own change under one-ulp input noise per var: oracle {['%.1e' % x for x in d_ora]}, "
+                f"library {['%.1e' % x for x in d_gpu]}")
+            tol = np.maximum(tol, 4 * (d_ora + d_gpu))
+        worst = max(worst, float((rel / tol).max()))
         base += m.n_elements
-    assert worst <= 1e-12, worst
+    assert worst <= 1.0, worst
 
 
 @pytest.mark.parametrize("dim,M,lo,hi,ecflux,diss", [(2, 3, 1, 5, 0, 1), (3, 3, 1, 4, 0, 1), (3, 3, 2, 4, 1, 0)])
@@ -114,6 +145,23 @@ def test_mixed_degree_parity_with_oracle(dim, M, lo, hi, ecflux, diss):
     plan = batched(dim, [mesh], [deg], warp, ecflux, diss)
     log(f"case dim={dim} M={M} degrees {lo}..{hi}: buckets {[(b['degree'], b['n_elements']) for b in plan.buckets]}")
     _oracle_compare(plan, [mesh], [deg], warp, wl.RandomSmooth(dim, L, 6), ecflux, diss, f"dim{dim}_p{lo}-{hi}")
+
+
+def test_mixed_degree_parity_high_degrees_sampled():
+    """Degrees 5..10 on 162 curved tetrahedra (facets of 36 to 121 nodes: the
+    mixed-interface contraction split over lane slices at p = 5, one lane per
+    node above), 12 sampled elements against the
+    oracle, to the oracle's own rounding floor at these degrees (measured: up to
+    8e-13 of ||r_e||_inf under one-ulp input noise)."""
+    L = 2 * math.pi
+    warp = wl.make_warp_sinprod(L, 0.05)
+    mesh = wl.split_box_mesh(3, 3, L)
+    deg = wl.mixed_degrees(mesh.n_elements, 14, 5, 10)
+    plan = batched(3, [mesh], [deg], warp, 0, 1)
+    el = np.random.default_rng(3).choice(mesh.n_elements, 12, replace=False)
+    log(f"case degrees 5..10: buckets {[(b['degree'], b['n_elements']) for b in plan.buckets]}, sampled {deg[el].tolist()}")
+    _oracle_compare(plan, [mesh], [deg], warp, wl.RandomSmooth(3, L, 6), 0, 1, "dim3_p5-10", sample=el,
+                    rounding_floor=True)
 
 
 def test_two_meshes_in_one_batch():
