@@ -27,8 +27,10 @@ constexpr int MIX_MAX_NP = 286;   // PKD modes of a degree-10 tetrahedron
 // S = 128 / nqf >= 3 slices, slice s summing the modes k = s, s + S, ..., and
 // the slices' partial sums are added in LDS.  Same batch, per launch: buckets
 // of p = 2..5 80 -> 50-72 us; p = 6, 7 (one lane per node) 78 -> 88 us, the
-// same with two slices, so not the split (the partial-sum array adds 5 KB of
-// LDS per workgroup); p = 8..10 unchanged; 0.83 -> 0.76 ms per residual.
+// same with two slices; p = 8..10 unchanged; 0.83 -> 0.76 ms per residual.
+// Both forms in one kernel cost 90 VGPRs and 16.6 KB of LDS (67 and 11.4 KB
+// with one form), 5 waves per SIMD instead of 7, which the one-lane-per-node
+// buckets pay for; a kernel per form would keep them at 7.
 constexpr int MIX_BLOCK = 128;
 
 template <int NC>
