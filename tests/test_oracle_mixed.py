@@ -9,7 +9,10 @@ conforming-interface assumption for elements of different degree).
     is exactly representable on every element, so the residual vanishes to
     rounding;
   * elements whose neighbours all share their degree give the equal-degree
-    residual."""
+    residual;
+  * the carried reference points, mapped by the neighbour's vertices, are the
+    facet nodes' physical positions (modulo the period) and lie on the
+    neighbour's reference boundary."""
 import math
 
 import numpy as np
@@ -68,3 +71,41 @@ def test_elements_with_equal_degree_neighbours_match_the_conforming_residual():
     got = torch.stack(MX.residual(mp, uts, far))
     ref = R.residual(mp.probs[2], uts[2], far)
     assert torch.equal(got, ref)
+
+
+def _barycentric(dim, xi):
+    """Barycentric coordinates on the reference simplex with vertices
+    (-1, ..., -1) and -1 + 2 e_k: lambda_k = (1 + xi_k)/2 for k >= 1 and
+    lambda_0 = 1 - sum_k lambda_k."""
+    xi = np.asarray(xi, dtype=np.float64)
+    lam_k = 0.5 * (1.0 + xi)
+    lam_0 = 1.0 - lam_k.sum(-1, keepdims=True)
+    return np.concatenate([lam_0, lam_k], axis=-1)
+
+
+def test_carried_reference_points_land_on_the_facet_nodes():
+    """The neighbour reference point of every facet node, mapped by the
+    neighbour's own vertices (barycentric combination), is the node's physical
+    position from the geometry module, up to a whole number of periods, and it
+    lies on the boundary of the neighbour's reference simplex (one barycentric
+    coordinate zero, none negative).  Affine meshes of mixed degree, both
+    dimensions, every facet (equal and unequal neighbour degrees)."""
+    for dim, M, lo, hi in ((2, 3, 1, 5), (3, 3, 1, 4)):
+        mesh, L = _mesh(dim, M)
+        deg = wl.mixed_degrees(mesh.n_elements, 30 + dim, lo, hi)
+        mp = MX.setup(mesh, deg, wl.warp_none, 1.4, 0, 1)
+        n_unequal = 0
+        for e in range(mesh.n_elements):
+            pr = mp.probs[int(deg[e])]
+            for z in range(dim + 1):
+                nu, pn, xin = MX._neighbour_points(mp, e, z)
+                n_unequal += int(pn != deg[e])
+                lam = _barycentric(dim, xin.numpy())
+                assert lam.min() >= -1e-13
+                assert np.abs(lam.min(axis=1)).max() <= 1e-13
+                vx_nu = mp.probs[pn].geo.vx[nu]                         # [d+1, d]
+                x = lam @ vx_nu
+                xf = pr.geo.x_f[z][e].numpy()
+                k = np.round((x - xf) / L)
+                assert np.abs(x - xf - k * L).max() <= 1e-12 * L
+        assert n_unequal > 0
