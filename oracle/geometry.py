@@ -30,6 +30,7 @@ from functools import lru_cache
 import numpy as np
 import torch
 
+from .noise import rn
 from .poly1d import DT
 from .refelem import RefElement, pkd, pkd_grad
 
@@ -151,7 +152,7 @@ def build_geometry(ref: RefElement, elem_ids: np.ndarray, elem_x: np.ndarray, wa
     lam = _barycentric(dim, Xm)                         # [Ng, d+1]
     x_aff = np.einsum("gk,ekd->egd", lam.numpy(), vx)   # [Ne, Ng, d]
     x_map = warp(x_aff.reshape(-1, dim)).reshape(ne, -1, dim)
-    dlt = torch.tensor(x_map - x_aff, dtype=DT)         # [Ne, Ng, d]
+    dlt = rn(torch.tensor(x_map - x_aff, dtype=DT))     # [Ne, Ng, d]
     origin = vx[:, 0, :]
     org = torch.tensor(origin, dtype=DT)
     Aff = torch.tensor(0.5 * (vx[:, 1:, :] - vx[:, :1, :]).transpose(0, 2, 1), dtype=DT)   # [Ne, c, m] = dX_c/dxi_m
@@ -162,14 +163,14 @@ def build_geometry(ref: RefElement, elem_ids: np.ndarray, elem_x: np.ndarray, wa
     def grad_x(X):
         L, dL = lagrange_matrices(dim, p, X)
         xv = X_aff(X) + torch.einsum("ki,eid->ekd", L, dlt)
-        gd = torch.stack([torch.einsum("ki,eic->ekc", dL[m], dlt) for m in range(dim)], -1)  # [Ne,k,c,m]
+        gd = rn(torch.stack([torch.einsum("ki,eic->ekc", rn(dL[m]), dlt) for m in range(dim)], -1))  # [Ne,k,c,m]
         return xv, gd                                   # gradient of the displacement only
 
     # interpolated Jacobian (eq. jacobian_approx)
     _, gd_map = grad_x(Xm)
-    Jmap = torch.linalg.det(Aff[:, None] + gd_map)
+    Jmap = rn(torch.linalg.det(rn(Aff[:, None] + gd_map)))
     Lvol, _ = lagrange_matrices(dim, p, ref.xi)
-    J = torch.einsum("ki,ei->ek", Lvol, Jmap)
+    J = rn(torch.einsum("ki,ei->ek", rn(Lvol), Jmap))
 
     def cross(a, b):
         return torch.stack([a[..., 1] * b[..., 2] - a[..., 2] * b[..., 1],
@@ -178,7 +179,7 @@ def build_geometry(ref: RefElement, elem_ids: np.ndarray, elem_x: np.ndarray, wa
 
     def metrics(X):
         xv, gd = grad_x(X)
-        gx = Aff[:, None] + gd
+        gx = rn(Aff[:, None] + gd)
         if dim == 2:
             G = torch.empty(gx.shape, dtype=DT)
             G[..., 0, 0] = gx[..., 1, 1]
@@ -192,18 +193,18 @@ def build_geometry(ref: RefElement, elem_ids: np.ndarray, elem_x: np.ndarray, wa
         Xc = equispaced(3, q + 1)
         Lc, dLc_ = lagrange_matrices(3, p, Xc)
         Xa = X_aff(Xc)                                                    # [Ne, Nc, 3]
-        dc = torch.einsum("ki,eid->ekd", Lc, dlt)                         # delta at curl nodes
-        gdc = torch.stack([torch.einsum("ki,eic->ekc", dLc_[m], dlt) for m in range(3)], -1)  # [Ne,Nc,c,m]
+        dc = rn(torch.einsum("ki,eid->ekd", rn(Lc), dlt))                 # delta at curl nodes
+        gdc = rn(torch.stack([torch.einsum("ki,eic->ekc", rn(dLc_[m]), dlt) for m in range(3)], -1))  # [Ne,Nc,c,m]
         a = [Aff[:, None, c, :] for c in range(3)]                        # grad X_c (constant rows)
 
         def rvec(c1, c2):     # x_c1 grad x_c2 minus its affine-affine part
-            return Xa[..., c1:c1 + 1] * gdc[..., c2, :] + dc[..., c1:c1 + 1] * a[c2] + dc[..., c1:c1 + 1] * gdc[..., c2, :]
+            return rn(Xa[..., c1:c1 + 1] * gdc[..., c2, :] + dc[..., c1:c1 + 1] * a[c2] + dc[..., c1:c1 + 1] * gdc[..., c2, :])
 
         r1, r2, r3 = rvec(2, 1), rvec(2, 0), rvec(0, 1)
         _, dLc = lagrange_matrices(3, q + 1, X)
 
         def curl(r):
-            dr = [torch.einsum("ki,eic->ekc", dLc[m], r) for m in range(3)]  # dr[m][..., c] = d r_c / d xi_m
+            dr = [rn(torch.einsum("ki,eic->ekc", rn(dLc[m]), r)) for m in range(3)]  # dr[m][..., c] = d r_c / d xi_m
             return torch.stack([dr[1][..., 2] - dr[2][..., 1],
                                 dr[2][..., 0] - dr[0][..., 2],
                                 dr[0][..., 1] - dr[1][..., 0]], -1)
@@ -212,7 +213,7 @@ def build_geometry(ref: RefElement, elem_ids: np.ndarray, elem_x: np.ndarray, wa
         c1 = -(cross(a[2], a[1]).expand(-1, npt, -1) + curl(r1))
         c2 = cross(a[2], a[0]).expand(-1, npt, -1) + curl(r2)
         c3 = cross(a[0], a[1]).expand(-1, npt, -1) + curl(r3)
-        G = torch.stack([c1, c2, c3], -1)    # G[..., l, m]: column m from the m-th curl
+        G = rn(torch.stack([c1, c2, c3], -1))    # G[..., l, m]: column m from the m-th curl
         return xv, G
 
     xv, G = metrics(ref.xi)
@@ -222,12 +223,12 @@ def build_geometry(ref: RefElement, elem_ids: np.ndarray, elem_x: np.ndarray, wa
     Gf, nJ, Jf, nn, xf = [], [], [], [], []
     for z in range(ref.Nf):
         xfz, Gz = metrics(ref.xi_f[z])
-        v = torch.einsum("l,ekl m->ekm".replace(" ", ""), ref.nhat[z], Gz)
-        jf = torch.linalg.norm(v, dim=-1)
+        v = rn(torch.einsum("l,ekl m->ekm".replace(" ", ""), ref.nhat[z], Gz))
+        jf = rn(torch.linalg.norm(v, dim=-1))
         Gf.append(Gz)
         nJ.append(v)
         Jf.append(jf)
-        nn.append(v / jf[..., None])
+        nn.append(rn(v / jf[..., None]))
         xf.append(xfz + org[:, None, :])
     return Geometry(dim, p, q, vids, vx, x_vol, J, G, Gf, nJ, Jf, nn, xf, J_exact)
 

@@ -100,8 +100,8 @@ def residual(mp: MixedProblem, uts: dict, elems, force_eval: bool = False) -> li
                 prn = mp.probs[pn]
                 wt_nu = R.entropy_projection(prn, uts[pn], torch.as_tensor([nu]))[0]     # [Nc, Np(pn)]
                 phi = pkd(mp.dim, pn, xin)                                           # [Nqf, Np(pn)]
-                wp = phi @ wt_nu.T                                                   # [Nqf, Nc]
-                rows.append(ph.cons_from_entropy(wp, mp.gamma))
+                wp = R._rn(R.esum("jk,ck->jc", phi, wt_nu))                          # [Nqf, Nc]
+                rows.append(R._rn(ph.cons_from_entropy(wp, mp.gamma)))
             return torch.stack(rows)
 
         res = R.residual(pr, uts[p], sel, exterior)

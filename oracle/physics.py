@@ -22,14 +22,16 @@ import contextlib
 
 import torch
 
+from .noise import rn
+
 LOG_SERIES_THRESHOLD = 1.0e-4
 
 
 def prim(u: torch.Tensor, gamma: float):
     d = u.shape[-1] - 2
     rho = u[..., 0]
-    v = u[..., 1:1 + d] / rho[..., None]
-    p = (gamma - 1.0) * (u[..., d + 1] - 0.5 * rho * (v * v).sum(-1))
+    v = rn(u[..., 1:1 + d] / rho[..., None])
+    p = rn((gamma - 1.0) * rn(u[..., d + 1] - rn(0.5 * rho * (v * v).sum(-1))))
     return rho, v, p
 
 
@@ -55,12 +57,12 @@ def entropy_vars(u: torch.Tensor, gamma: float) -> torch.Tensor:
     """W(U) = dS/dU."""
     d = u.shape[-1] - 2
     rho, v, p = prim(u, gamma)
-    s = torch.log(p) - gamma * torch.log(rho)
-    w1 = (gamma - s) / (gamma - 1.0) - 0.5 * rho * (v * v).sum(-1) / p
+    s = rn(rn(torch.log(p)) - rn(gamma * rn(torch.log(rho))))
+    w1 = rn(rn((gamma - s) / (gamma - 1.0)) - rn(0.5 * rho * (v * v).sum(-1) / p))
     out = [w1]
     for i in range(d):
-        out.append(rho * v[..., i] / p)
-    out.append(-rho / p)
+        out.append(rn(rho * v[..., i] / p))
+    out.append(rn(-rho / p))
     return torch.stack(out, -1)
 
 
@@ -68,12 +70,12 @@ def cons_from_entropy(w: torch.Tensor, gamma: float) -> torch.Tensor:
     """U(W), the inverse of entropy_vars."""
     d = w.shape[-1] - 2
     b = -w[..., d + 1]                       # rho / p
-    v = w[..., 1:1 + d] / b[..., None]
-    s = gamma - (gamma - 1.0) * (w[..., 0] + 0.5 * b * (v * v).sum(-1))
-    rho = torch.exp(-(s + torch.log(b)) / (gamma - 1.0))
-    p = rho / b
-    E = p / (gamma - 1.0) + 0.5 * rho * (v * v).sum(-1)
-    return torch.cat([rho[..., None], rho[..., None] * v, E[..., None]], -1)
+    v = rn(w[..., 1:1 + d] / b[..., None])
+    s = rn(gamma - rn((gamma - 1.0) * rn(w[..., 0] + rn(0.5 * b * (v * v).sum(-1)))))
+    rho = rn(torch.exp(rn(-rn(s + rn(torch.log(b))) / (gamma - 1.0))))
+    p = rn(rho / b)
+    E = rn(rn(p / (gamma - 1.0)) + rn(0.5 * rho * (v * v).sum(-1)))
+    return torch.cat([rho[..., None], rn(rho[..., None] * v), E[..., None]], -1)
 
 
 def flux_potential(u: torch.Tensor, gamma: float) -> torch.Tensor:
@@ -84,7 +86,7 @@ def flux_potential(u: torch.Tensor, gamma: float) -> torch.Tensor:
 
 
 def _series(f2):
-    return 1.0 + f2 / 3.0 + f2 * f2 / 5.0 + f2 * f2 * f2 / 7.0
+    return rn(1.0 + f2 / 3.0 + f2 * f2 / 5.0 + f2 * f2 * f2 / 7.0)
 
 
 def log_mean(am: torch.Tensor, ap: torch.Tensor) -> torch.Tensor:
@@ -94,11 +96,11 @@ def log_mean(am: torch.Tensor, ap: torch.Tensor) -> torch.Tensor:
     small = f2 < LOG_SERIES_THRESHOLD
     # the log branch is evaluated on safe arguments where the series is used,
     # so that autograd never sees 0/0
-    dl = torch.log(ap) - torch.log(am)
+    dl = rn(rn(torch.log(ap)) - rn(torch.log(am)))
     dl_safe = torch.where(small, torch.ones_like(dl), dl)
-    num_safe = torch.where(small, torch.ones_like(dl), ap - am)
-    big = num_safe / dl_safe
-    ser = (am + ap) / (2.0 * _series(f2))
+    num_safe = torch.where(small, torch.ones_like(dl), rn(ap - am))
+    big = rn(num_safe / dl_safe)
+    ser = rn(rn(am + ap) / (2.0 * _series(rn(f2))))
     return torch.where(small, ser, big)
 
 
@@ -107,11 +109,11 @@ def inv_log_mean(am: torch.Tensor, ap: torch.Tensor) -> torch.Tensor:
     f = (ap - am) / (ap + am)
     f2 = f * f
     small = f2 < LOG_SERIES_THRESHOLD
-    dl = torch.log(ap) - torch.log(am)
+    dl = rn(rn(torch.log(ap)) - rn(torch.log(am)))
     dl_safe = torch.where(small, torch.ones_like(dl), dl)
-    num_safe = torch.where(small, torch.ones_like(dl), ap - am)
-    big = dl_safe / num_safe
-    ser = 2.0 * _series(f2) / (am + ap)
+    num_safe = torch.where(small, torch.ones_like(dl), rn(ap - am))
+    big = rn(dl_safe / num_safe)
+    ser = rn(2.0 * _series(rn(f2)) / rn(am + ap))
     return torch.where(small, ser, big)
 
 
@@ -121,17 +123,17 @@ def ranocha_flux(um: torch.Tensor, up: torch.Tensor, n: torch.Tensor, gamma: flo
     rm, vm, pm = prim(um, gamma)
     rp, vp, pp = prim(up, gamma)
     rho_ln = log_mean(rm, rp)
-    inv_rp_ln = inv_log_mean(rm / pm, rp / pp)       # 1 / {rho/p}_ln
-    vavg = 0.5 * (vm + vp)
-    pavg = 0.5 * (pm + pp)
-    vn = (vavg * n).sum(-1)
-    f_rho = rho_ln * vn
+    inv_rp_ln = inv_log_mean(rn(rm / pm), rn(rp / pp))       # 1 / {rho/p}_ln
+    vavg = rn(0.5 * (vm + vp))
+    pavg = rn(0.5 * (pm + pp))
+    vn = rn((vavg * n).sum(-1))
+    f_rho = rn(rho_ln * vn)
     out = [f_rho]
     for i in range(d):
-        out.append(f_rho * vavg[..., i] + pavg * n[..., i])
-    vmvp = (vm * vp).sum(-1)
-    fE = f_rho * (0.5 * vmvp + inv_rp_ln / (gamma - 1.0)) \
-        + 0.5 * (pm * (vp * n).sum(-1) + pp * (vm * n).sum(-1))
+        out.append(rn(rn(f_rho * vavg[..., i]) + rn(pavg * n[..., i])))
+    vmvp = rn((vm * vp).sum(-1))
+    fE = rn(rn(f_rho * rn(rn(0.5 * vmvp) + rn(inv_rp_ln / (gamma - 1.0))))
+            + rn(0.5 * rn(rn(pm * (vp * n).sum(-1)) + rn(pp * (vm * n).sum(-1)))))
     out.append(fE)
     return torch.stack(out, -1)
 
@@ -142,19 +144,19 @@ def chandrashekar_flux(um: torch.Tensor, up: torch.Tensor, n: torch.Tensor, gamm
     d = um.shape[-1] - 2
     rm, vm, pm = prim(um, gamma)
     rp, vp, pp = prim(up, gamma)
-    bm = rm / (2.0 * pm)
-    bp = rp / (2.0 * pp)
+    bm = rn(rm / (2.0 * pm))
+    bp = rn(rp / (2.0 * pp))
     rho_ln = log_mean(rm, rp)
     inv_b_ln = inv_log_mean(bm, bp)
-    vavg = 0.5 * (vm + vp)
-    phat = 0.5 * (rm + rp) / (bm + bp)              # {rho} / (2 {beta})
-    vn = (vavg * n).sum(-1)
-    f_rho = rho_ln * vn
+    vavg = rn(0.5 * (vm + vp))
+    phat = rn(rn(0.5 * (rm + rp)) / rn(bm + bp))              # {rho} / (2 {beta})
+    vn = rn((vavg * n).sum(-1))
+    f_rho = rn(rho_ln * vn)
     out = [f_rho]
     for i in range(d):
-        out.append(f_rho * vavg[..., i] + phat * n[..., i])
-    vmvp = (vm * vp).sum(-1)
-    fE = f_rho * (0.5 * vmvp + 0.5 * inv_b_ln / (gamma - 1.0)) + phat * vn
+        out.append(rn(rn(f_rho * vavg[..., i]) + rn(phat * n[..., i])))
+    vmvp = rn((vm * vp).sum(-1))
+    fE = rn(rn(f_rho * rn(rn(0.5 * vmvp) + rn(0.5 * inv_b_ln / (gamma - 1.0)))) + rn(phat * vn))
     out.append(fE)
     return torch.stack(out, -1)
 
@@ -208,6 +210,6 @@ def interface_flux(um, up, n, gamma, ecflux: int, dissipation: int):
     """f*(U-, U+, n) of eq. (num_flux) with unit normal n."""
     f = EC_FLUXES[ecflux](um, up, n, gamma)
     if dissipation:
-        lam = davis_speed(um, up, n, gamma)
-        f = f - 0.5 * lam[..., None] * (up - um)
+        lam = rn(davis_speed(um, up, n, gamma))
+        f = rn(f - rn(0.5 * lam[..., None] * rn(up - um)))
     return f

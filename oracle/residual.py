@@ -24,6 +24,7 @@ import numpy as np
 import torch
 
 from . import physics as ph
+from .noise import esum, rsum as _rsum, rn as _rn, rn_skew as _rn_skew, rounding_noise  # noqa: F401
 from .geometry import Connectivity, Geometry, build_geometry, connectivity
 from .poly1d import DT
 from .refelem import RefElement, ref_element
@@ -84,12 +85,12 @@ def project(prob: Problem, u_nodal: torch.Tensor, elems=None) -> torch.Tensor:
 def entropy_projection(prob: Problem, ut: torch.Tensor, elems) -> torch.Tensor:
     """w~ of eq. (entropy_expansion) for the given elements -> [nE, Nc, Np]."""
     V, w = prob.ref.V, prob.ref.w
-    u = torch.einsum("ki,eci->ekc", V, ut[elems])
-    W = ph.entropy_vars(u, prob.gamma)
+    u = _rn(esum("ki,eci->ekc", _rn(V), _rn(ut[elems])))
+    W = _rn(ph.entropy_vars(u, prob.gamma))
     J = prob.geo.J[elems]
-    b = torch.einsum("ki,ek,ekc->eci", V, w[None, :] * J, W)
-    A = wadj_inverse(prob, elems)
-    return torch.einsum("eij,ecj->eci", A, b)
+    b = _rn(esum("ki,ekc->eci", _rn(V), _rn(w[None, :, None] * J[..., None]) * W))
+    A = _rn(wadj_inverse(prob, elems))
+    return _rn(esum("eij,ecj->eci", A, b))
 
 
 def _pair_fluxes(prob: Problem, ua: torch.Tensor, ub: torch.Tensor) -> torch.Tensor:
@@ -102,7 +103,7 @@ def _pair_fluxes(prob: Problem, ua: torch.Tensor, ub: torch.Tensor) -> torch.Ten
     for m in range(d):
         n = torch.zeros(A.shape[:-1] + (d,), dtype=DT)
         n[..., m] = 1.0
-        out.append(flux(A, B, n, prob.gamma))
+        out.append(_rn(flux(A, B, n, prob.gamma)))
     return torch.stack(out, -1)
 
 
@@ -113,17 +114,17 @@ def _facet_states(prob: Problem, wt_all: torch.Tensor, idx_of: dict, elems, exte
     ref, con = prob.ref, prob.con
     own, ext = [], []
     for z in range(ref.Nf):
-        wv = torch.einsum("ki,eci->ekc", ref.V, wt_all[[idx_of[int(e)] for e in elems]])
-        wz = torch.einsum("jk,ekc->ejc", ref.R[z], wv)
-        own.append(ph.cons_from_entropy(wz, prob.gamma))
+        wv = _rn(esum("ki,eci->ekc", _rn(ref.V), wt_all[[idx_of[int(e)] for e in elems]]))
+        wz = _rn(esum("jk,ekc->ejc", _rn(ref.R[z]), wv))
+        own.append(_rn(ph.cons_from_entropy(wz, prob.gamma)))
         nb = con.nbr_elem[elems, z]
         nz = con.nbr_face[elems, z]
         wt_nb = wt_all[[idx_of[int(e)] for e in nb]]
-        wv_nb = torch.einsum("ki,eci->ekc", ref.V, wt_nb)
-        wp = torch.stack([ref.R[int(nz[i])] @ wv_nb[i] for i in range(len(elems))])  # [nE, Nqf, Nc]
+        wv_nb = _rn(esum("ki,eci->ekc", _rn(ref.V), wt_nb))
+        wp = torch.stack([esum("jk,kc->jc", _rn(ref.R[int(nz[i])]), wv_nb[i]) for i in range(len(elems))])  # [nE, Nqf, Nc]
         perm = torch.as_tensor(con.node_map[elems, z])
-        wp = torch.gather(wp, 1, perm[:, :, None].expand(-1, -1, wp.shape[-1]))
-        ext_z = ph.cons_from_entropy(wp, prob.gamma)
+        wp = _rn(torch.gather(wp, 1, perm[:, :, None].expand(-1, -1, wp.shape[-1])))
+        ext_z = _rn(ph.cons_from_entropy(wp, prob.gamma))
         ext.append(ext_z if exterior is None else exterior(elems, z, ext_z))
     return own, ext
 
@@ -145,16 +146,16 @@ def residual_nodal(prob: Problem, ut: torch.Tensor, elems=None, exterior=None):
     wt_need = entropy_projection(prob, ut, torch.as_tensor(need))
     idx_of = {int(e): i for i, e in enumerate(need)}
     wt = wt_need[[idx_of[int(e)] for e in elems]]
-    w = torch.einsum("ki,eci->ekc", ref.V, wt)
-    ubar = ph.cons_from_entropy(w, g)
-    G = geo.G[elems]                                   # [nE, Nq, l, m]
+    w = _rn(esum("ki,eci->ekc", _rn(ref.V), wt))
+    ubar = _rn(ph.cons_from_entropy(w, g))
+    G = _rn(geo.G[elems])                              # [nE, Nq, l, m]
     # volume term: - sum_l (2 S^l o sum_m {G_lm} o F^m) 1
     F = _pair_fluxes(prob, ubar, ubar)                 # [nE, Nq, Nq, Nc, m]
     r = torch.zeros_like(ubar)
     for l in range(d):
         Gavg = 0.5 * (G[:, :, None, l, :] + G[:, None, :, l, :])     # [nE, i, j, m]
-        H = torch.einsum("eijm,eijcm->eijc", Gavg, F)
-        r = r - torch.einsum("ij,eijc->eic", 2.0 * ref.S[l], H)
+        H = _rn(esum("eijm,eijcm->eijc", Gavg, F))
+        r = _rn(r - esum("ij,eijc->eic", 2.0 * _rn_skew(ref.S[l]), H))
     del F
     own, ext = _facet_states(prob, wt_need, idx_of, elems, exterior)
     for z in range(ref.Nf):
@@ -163,16 +164,16 @@ def residual_nodal(prob: Problem, ut: torch.Tensor, elems=None, exterior=None):
         Fz = _pair_fluxes(prob, ubar, uf)              # [nE, Nq, Nqf, Nc, m]
         nh = ref.nhat[z]
         GnV = torch.einsum("l,eilm->eim", nh, G)                  # G(xi_i)^T nhat
-        GnF = geo.nJ[z][elems]                                    # G(xi_j^z)^T nhat
+        GnF = _rn(geo.nJ[z][elems])                               # G(xi_j^z)^T nhat
         avg = 0.5 * (GnV[:, :, None, :] + GnF[:, None, :, :])     # [nE, i, j, m]
-        RtB = ref.R[z].T @ torch.diag(ref.w_f[z])                 # [Nq, Nqf]
-        C = RtB[None, :, :, None] * torch.einsum("eijm,eijcm->eijc", avg, Fz)
-        C1 = C.sum(2)
-        Ct1 = C.sum(1)
-        fstar = ph.interface_flux(uf, ext[z], geo.n[z][elems], g, prob.ecflux, prob.dissipation)
-        s = (ref.w_f[z][None, :, None] * geo.Jf[z][elems][..., None]) * fstar - Ct1
-        r = r - C1 - torch.einsum("ji,ejc->eic", ref.R[z], s)
-    return r, w
+        RtB = _rn(ref.R[z].T @ torch.diag(ref.w_f[z]))            # [Nq, Nqf]
+        C = _rn(RtB[None, :, :, None] * esum("eijm,eijcm->eijc", avg, Fz))
+        C1 = _rsum(C, 2)
+        Ct1 = _rsum(C, 1)
+        fstar = _rn(ph.interface_flux(uf, ext[z], _rn(geo.n[z][elems]), g, prob.ecflux, prob.dissipation))
+        s = _rn(_rn(ref.w_f[z][None, :, None] * geo.Jf[z][elems][..., None]) * fstar - Ct1)
+        r = _rn(_rn(r - C1) - esum("ji,ejc->eic", _rn(ref.R[z]), s))
+    return _rn(r), w
 
 
 def residual(prob: Problem, ut: torch.Tensor, elems=None, exterior=None) -> torch.Tensor:
@@ -181,9 +182,9 @@ def residual(prob: Problem, ut: torch.Tensor, elems=None, exterior=None) -> torc
         elems = np.arange(prob.ne)
     elems = np.asarray(elems, dtype=np.int64).reshape(-1)
     r, _ = residual_nodal(prob, ut, elems, exterior)
-    A = wadj_inverse(prob, torch.as_tensor(elems))
-    b = torch.einsum("ki,ekc->eci", prob.ref.V, r)
-    return torch.einsum("eij,ecj->eci", A, b)
+    A = _rn(wadj_inverse(prob, torch.as_tensor(elems)))
+    b = _rn(esum("ki,ekc->eci", _rn(prob.ref.V), r))
+    return _rn(esum("eij,ecj->eci", A, b))
 
 
 def residual_chunked(prob: Problem, ut: torch.Tensor, elems=None, chunk: int = 64) -> torch.Tensor:
@@ -296,40 +297,3 @@ def entropy_rate(prob: Problem, ut: torch.Tensor, dudt: torch.Tensor) -> torch.T
     Wu = ph.entropy_vars(u, prob.gamma)
     du = torch.einsum("ki,eci->ekc", V, dudt)
     return torch.einsum("k,ek,ekc,ekc->", w, prob.geo.J, Wu, du)
-
-
-def residual_magnitude(prob: Problem, ut: torch.Tensor, elems=None) -> torch.Tensor:
-    """The residual of eq. (entropy_stable) + eq. (dudt_modal) evaluated with the
-    absolute value of every term (|S|, |{G}|, |F|, |R^T B|, |R|, |Mt^{-1}|, |V|):
-    the scale of the summands, against which rounding differences between two
-    correct evaluations are measured when the residual itself cancels (e.g. a
-    large uniform pressure background).  -> [nE, Nc, Np]"""
-    ref, geo = prob.ref, prob.geo
-    d, g = ref.dim, prob.gamma
-    if elems is None:
-        elems = np.arange(prob.ne)
-    elems, need = _neighbourhood(prob, elems)
-    wt_need = entropy_projection(prob, ut, torch.as_tensor(need))
-    idx_of = {int(e): i for i, e in enumerate(need)}
-    wt = wt_need[[idx_of[int(e)] for e in elems]]
-    ubar = ph.cons_from_entropy(torch.einsum("ki,eci->ekc", ref.V, wt), g)
-    G = geo.G[elems]
-    F = _pair_fluxes(prob, ubar, ubar).abs()
-    r = torch.zeros_like(ubar)
-    for l in range(d):
-        Gavg = 0.5 * (G[:, :, None, l, :] + G[:, None, :, l, :]).abs()
-        r = r + torch.einsum("ij,eijc->eic", 2.0 * ref.S[l].abs(), torch.einsum("eijm,eijcm->eijc", Gavg, F))
-    del F
-    own, ext = _facet_states(prob, wt_need, idx_of, elems)
-    for z in range(ref.Nf):
-        Fz = _pair_fluxes(prob, ubar, own[z]).abs()
-        GnV = torch.einsum("l,eilm->eim", ref.nhat[z], G)
-        avg = 0.5 * (GnV[:, :, None, :] + geo.nJ[z][elems][:, None, :, :]).abs()
-        RtB = (ref.R[z].T @ torch.diag(ref.w_f[z])).abs()
-        C = RtB[None, :, :, None] * torch.einsum("eijm,eijcm->eijc", avg, Fz)
-        fstar = ph.interface_flux(own[z], ext[z], geo.n[z][elems], g, prob.ecflux, prob.dissipation).abs()
-        s = (ref.w_f[z][None, :, None] * geo.Jf[z][elems][..., None]) * fstar + C.sum(1)
-        r = r + C.sum(2) + torch.einsum("ji,ejc->eic", ref.R[z].abs(), s)
-    A = wadj_inverse(prob, torch.as_tensor(elems)).abs()
-    b = torch.einsum("ki,ekc->eci", ref.V.abs(), r)
-    return torch.einsum("eij,ecj->eci", A, b)

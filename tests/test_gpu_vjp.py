@@ -249,14 +249,15 @@ def _kinetic_energy_fn(plan, degree):
 def test_rk4_adjoint_kinetic_energy_central_differences():
     """d KE(u(T)) / d u(0) after 20 RK4 steps on 10,368 curved tetrahedra at
     p = 6 (Taylor-Green vortex, entropy-conservative): the discrete adjoint
-    against central differences along 32 random directions, h = 1e-6."""
+    against central differences along 32 random directions, h = 1e-6, each
+    direction at 1e-6 relative; dt = 5e-4."""
     import paper_2312_07874_amd as esd
     wk = wl.tgv_tet(M=12, degree=6)
     plan = gpu_plan(wk)
     x = plan.node_coords().cpu().numpy()
     u0 = plan.project(torch.tensor(wk.state(x), device="cuda").contiguous())
     ke = _kinetic_energy_fn(plan, 6)
-    dt, n = 1e-4, 20
+    dt, n = 5e-4, 20
     x0 = u0.clone().requires_grad_(True)
     J = ke(esd.rk4(x0, plan, dt, n))
     (grad,) = torch.autograd.grad(J, x0)
@@ -274,9 +275,8 @@ def test_rk4_adjoint_kinetic_energy_central_differences():
             log(f"direction {k}: fd {fds[-1]:.10e} adjoint {ads[-1]:.10e}")
     plan.sync_status()
     fd, ad = np.array(fds), np.array(ads)
-    # the central difference at h = 1e-6 carries the forward's rounding noise
-    # divided by 2h (about 1e-6 absolute here): compare over all directions
+    per = np.abs(fd - ad) / np.abs(ad)
     rel = float(np.linalg.norm(fd - ad) / np.linalg.norm(ad))
-    worst = float(np.abs(fd - ad).max() / np.abs(ad).max())
-    log(f"32 directions: ||fd - adjoint|| / ||adjoint|| = {rel:.2e}, max |fd - adjoint| / max |adjoint| = {worst:.2e}")
-    assert rel <= 1e-5 and worst <= 1e-5
+    log(f"32 directions: per-direction |fd - adjoint| / |adjoint| max {per.max():.2e} median {np.median(per):.2e}; "
+        f"||fd - adjoint|| / ||adjoint|| = {rel:.2e}")
+    assert per.max() <= 1e-6, per
