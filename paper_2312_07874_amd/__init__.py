@@ -161,7 +161,7 @@ class Plan:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
+        if h and _lib is not None:      # the module may already be torn down at exit
             _lib.esd_plan_destroy(h)
             self._h = None
 

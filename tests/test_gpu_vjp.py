@@ -250,7 +250,10 @@ def test_rk4_adjoint_kinetic_energy_central_differences():
     """d KE(u(T)) / d u(0) after 20 RK4 steps on 10,368 curved tetrahedra at
     p = 6 (Taylor-Green vortex, entropy-conservative): the discrete adjoint
     against central differences along 32 random directions, h = 1e-6, each
-    direction at 1e-6 relative; dt = 5e-4."""
+    direction at 1e-6 relative to its own directional derivative, or to the
+    root mean square over the directions where that is larger (a direction
+    whose derivative nearly vanishes is judged against the typical size, as
+    the difference quotient's rounding does not shrink with it); dt = 5e-4."""
     import paper_2312_07874_amd as esd
     wk = wl.tgv_tet(M=12, degree=6)
     plan = gpu_plan(wk)
@@ -271,11 +274,10 @@ def test_rk4_adjoint_kinetic_energy_central_differences():
         um = plan.rk4((u0 - h * d).contiguous(), dt, n)
         fds.append(float((ke(up) - ke(um)) / (2 * h)))
         ads.append(float((grad * d).sum()))
-        if k % 8 == 0:
-            log(f"direction {k}: fd {fds[-1]:.10e} adjoint {ads[-1]:.10e}")
+        log(f"direction {k}: fd {fds[-1]:.12e} adjoint {ads[-1]:.12e}")
     plan.sync_status()
     fd, ad = np.array(fds), np.array(ads)
-    per = np.abs(fd - ad) / np.abs(ad)
+    per = np.abs(fd - ad) / np.maximum(np.abs(ad), np.sqrt(np.mean(ad ** 2)))
     rel = float(np.linalg.norm(fd - ad) / np.linalg.norm(ad))
     log(f"32 directions: per-direction |fd - adjoint| / |adjoint| max {per.max():.2e} median {np.median(per):.2e}; "
         f"||fd - adjoint|| / ||adjoint|| = {rel:.2e}")
