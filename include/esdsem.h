@@ -183,6 +183,20 @@ esd_status esd_project(const esd_plan* plan, const double* u_nodal_dev, double* 
 esd_status esd_residual(const esd_plan* plan, const double* u_dev, double* dudt_dev,
                         void* ws_dev, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * residual as esd_residual, with its workspace taken from a library-owned
+ * device array of 64 MiB per GPU (allocated when the library is loaded on that
+ * GPU and held until the process ends) instead of a caller buffer.  The call
+ * allocates nothing.  u_dev and dudt_dev as for esd_residual.  Errors:
+ * ESD_EINVAL if info.workspace_bytes exceeds 64 MiB (use esd_residual), if
+ * kernel timing is enabled on the plan, or for NULL/overlapping buffers;
+ * ESD_EUNSUPPORTED, ESD_EHIP as esd_residual.  All calls on one GPU share the
+ * array: two calls that overlap in time on the same GPU (different streams, or
+ * host threads) race and give wrong results.  Every workspace byte the call
+ * reads is written earlier in the same call, so nothing needs clearing. */
+esd_status esd_residual_noalloc(const esd_plan* plan, const double* u_dev, double* dudt_dev, void* stream);
+
 /* nsteps steps of classical four-stage Runge-Kutta with step dt, in place on
  * u_dev.  ws_dev holds info.rk4_workspace_bytes (two residual workspaces and
  * three state-sized buffers).  Every stage is the residual (K1 entropy

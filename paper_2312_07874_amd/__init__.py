@@ -82,6 +82,7 @@ EXPORTS = {
     "esd_node_coords": (_c, [_vp, _vp, _vp]),
     "esd_project": (_c, [_vp, _vp, _vp, _vp]),
     "esd_residual": (_c, [_vp, _vp, _vp, _vp, _vp]),
+    "esd_residual_noalloc": (_c, [_vp, _vp, _vp, _vp]),
     "esd_rk4": (_c, [_vp, _vp, ctypes.c_double, ctypes.c_int32, _vp, _vp, _vp]),
     "esd_residual_vjp": (_c, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "esd_rk4_vjp": (_c, [_vp, _vp, ctypes.c_double, ctypes.c_int32, _vp, _vp, _vp]),
@@ -217,6 +218,16 @@ class Plan:
         if out is None:
             out = torch.empty_like(u)
         _check(_lib.esd_residual(self._h, _ptr(u), _ptr(out), _ptr(self.workspace()), _stream()), "esd_residual")
+        return out
+
+    def residual_noalloc(self, u, out):
+        """esd_residual_noalloc: the residual into the caller's out, with the
+        library's fixed device scratch as workspace (no allocation anywhere)."""
+        import torch
+        assert u.is_cuda and u.dtype == torch.float64 and u.is_contiguous()
+        assert out.is_cuda and out.dtype == torch.float64 and out.is_contiguous()
+        assert tuple(u.shape) == self.state_shape and tuple(out.shape) == self.state_shape
+        _check(_lib.esd_residual_noalloc(self._h, _ptr(u), _ptr(out), _stream()), "esd_residual_noalloc")
         return out
 
     def rk4(self, u, dt: float, nsteps: int, ckpt=None):

@@ -50,6 +50,7 @@ def build(verbose: bool = False) -> str:
         [HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "adjoint.hip"), "-o", os.path.join(BUILD, "adjoint.o")],
         [HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "diagnostics.hip"), "-o", os.path.join(BUILD, "diagnostics.o")],
         [HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "batch.hip"), "-o", os.path.join(BUILD, "batch.o")],
+        [HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "scratch.hip"), "-o", os.path.join(BUILD, "scratch.o")],
     ]
     with ThreadPoolExecutor(max_workers=len(jobs)) as ex:
         list(ex.map(lambda c: _run(c, verbose), jobs))
@@ -57,7 +58,7 @@ def build(verbose: bool = False) -> str:
     _run([HIPCC, "-shared", f"--offload-arch={ARCH}", "-o", tmp,
           os.path.join(BUILD, "host_setup.o"), os.path.join(BUILD, "api.o"), os.path.join(BUILD, "kernels.o"),
           os.path.join(BUILD, "adjoint.o"), os.path.join(BUILD, "diagnostics.o"),
-          os.path.join(BUILD, "batch.o"), "-pthread"], verbose)
+          os.path.join(BUILD, "batch.o"), os.path.join(BUILD, "scratch.o"), "-pthread"], verbose)
     os.replace(tmp, LIB)
     return LIB
 

@@ -11,6 +11,8 @@
 #include <string>
 #include <vector>
 
+#include "scratch.hpp"
+
 #include "esdsem.h"
 #include "plan.hpp"
 
@@ -693,6 +695,24 @@ esd_status esd_residual(const esd_plan* P, const double* u_dev, double* dudt_dev
   if ((const void*)u_dev == (const void*)dudt_dev) return fail(ESD_EINVAL, "u and dudt overlap");
   if (((uintptr_t)ws_dev) % 256 != 0) return fail(ESD_EINVAL, "workspace not 256-byte aligned");
   const int rc = residual_any(P, u_dev, dudt_dev, ws_dev, (hipStream_t)stream);
+  if (rc < 0) return fail(ESD_EUNSUPPORTED, "degree not built");
+  if (rc != 0) return fail(ESD_EHIP, std::string("launch failed: ") + hipGetErrorString((hipError_t)rc));
+  return ESD_OK;
+}
+
+esd_status esd_residual_noalloc(const esd_plan* P, const double* u_dev, double* dudt_dev, void* stream) {
+  esd_status st = check_device(P);
+  if (st != ESD_OK) return st;
+  if (!u_dev || !dudt_dev) return fail(ESD_EINVAL, "NULL buffer");
+  if ((const void*)u_dev == (const void*)dudt_dev) return fail(ESD_EINVAL, "u and dudt overlap");
+  if (P->timing) return fail(ESD_EINVAL, "kernel timing is enabled on this plan (it records events)");
+  if (P->ws_bytes > esd::SCRATCH_BYTES)
+    return fail(ESD_EINVAL, "residual workspace of " + std::to_string(P->ws_bytes) + " bytes exceeds the " +
+                                std::to_string(esd::SCRATCH_BYTES) + "-byte library scratch");
+  void* ws = nullptr;
+  const int e = esd::scratch_address(&ws, nullptr);
+  if (e != 0) return fail(ESD_EHIP, std::string("scratch address: ") + hipGetErrorString((hipError_t)e));
+  const int rc = residual_any(P, u_dev, dudt_dev, ws, (hipStream_t)stream);
   if (rc < 0) return fail(ESD_EUNSUPPORTED, "degree not built");
   if (rc != 0) return fail(ESD_EHIP, std::string("launch failed: ") + hipGetErrorString((hipError_t)rc));
   return ESD_OK;
