@@ -89,32 +89,45 @@ def _series(f2):
     return rn(1.0 + f2 / 3.0 + f2 * f2 / 5.0 + f2 * f2 * f2 / 7.0)
 
 
-def log_mean(am: torch.Tensor, ap: torch.Tensor) -> torch.Tensor:
-    """{a}_ln = (a+ - a-)/(ln a+ - ln a-); series branch for nearly equal args."""
+def _f2(am, ap):
     f = (ap - am) / (ap + am)
-    f2 = f * f
-    small = f2 < LOG_SERIES_THRESHOLD
-    # the log branch is evaluated on safe arguments where the series is used,
-    # so that autograd never sees 0/0
-    dl = rn(rn(torch.log(ap)) - rn(torch.log(am)))
-    dl_safe = torch.where(small, torch.ones_like(dl), dl)
-    num_safe = torch.where(small, torch.ones_like(dl), rn(ap - am))
-    big = rn(num_safe / dl_safe)
-    ser = rn(rn(am + ap) / (2.0 * _series(rn(f2))))
-    return torch.where(small, ser, big)
+    return f * f
+
+
+def log_mean_series(am, ap):
+    """(a- + a+) / (2 (1 + f^2/3 + f^4/5 + f^6/7)): the log mean for f^2 < 1e-4."""
+    return rn(rn(am + ap) / (2.0 * _series(rn(_f2(am, ap)))))
+
+
+def log_mean_log(am, ap):
+    """(a+ - a-) / (ln a+ - ln a-)."""
+    return rn(rn(ap - am) / rn(rn(torch.log(ap)) - rn(torch.log(am))))
+
+
+def inv_log_mean_series(am, ap):
+    return rn(2.0 * _series(rn(_f2(am, ap))) / rn(am + ap))
+
+
+def inv_log_mean_log(am, ap):
+    return rn(rn(rn(torch.log(ap)) - rn(torch.log(am))) / rn(ap - am))
+
+
+def log_mean(am: torch.Tensor, ap: torch.Tensor) -> torch.Tensor:
+    """{a}_ln = (a+ - a-)/(ln a+ - ln a-); series branch for nearly equal args.
+    The log branch is evaluated on safe arguments where the series is used, so
+    that autograd never sees 0/0."""
+    small = _f2(am, ap) < LOG_SERIES_THRESHOLD
+    one = torch.ones_like(am)
+    big = log_mean_log(torch.where(small, one, am), torch.where(small, 2.0 * one, ap))
+    return torch.where(small, log_mean_series(am, ap), big)
 
 
 def inv_log_mean(am: torch.Tensor, ap: torch.Tensor) -> torch.Tensor:
     """1/{a}_ln."""
-    f = (ap - am) / (ap + am)
-    f2 = f * f
-    small = f2 < LOG_SERIES_THRESHOLD
-    dl = rn(rn(torch.log(ap)) - rn(torch.log(am)))
-    dl_safe = torch.where(small, torch.ones_like(dl), dl)
-    num_safe = torch.where(small, torch.ones_like(dl), rn(ap - am))
-    big = rn(dl_safe / num_safe)
-    ser = rn(2.0 * _series(rn(f2)) / rn(am + ap))
-    return torch.where(small, ser, big)
+    small = _f2(am, ap) < LOG_SERIES_THRESHOLD
+    one = torch.ones_like(am)
+    big = inv_log_mean_log(torch.where(small, one, am), torch.where(small, 2.0 * one, ap))
+    return torch.where(small, inv_log_mean_series(am, ap), big)
 
 
 def ranocha_flux(um: torch.Tensor, up: torch.Tensor, n: torch.Tensor, gamma: float) -> torch.Tensor:
@@ -196,7 +209,7 @@ def _max(a, b):
 
 
 def davis_speed(um, up, n, gamma):
-    """lambda of eq. (wave_speed); ties take the interior (-) branch."""
+    """lambda of eq. (wave_speed); its derivative at near-ties as in _max."""
     rm, vm, pm = prim(um, gamma)
     rp, vp, pp = prim(up, gamma)
     a = (vm * n).sum(-1).abs()

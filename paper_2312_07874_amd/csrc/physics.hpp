@@ -331,7 +331,7 @@ ESD_HD void tie_weights(double a, double b, double& wa, double& wb) {
 }
 
 // J_f f*(U-, U+, n) with nJ = J_f n:  f#(U-, U+, nJ) - (J_f lambda)/2 (U+ - U-),
-// J_f lambda = max(|v-.nJ|, |v+.nJ|) + J_f max(c-, c+) (ties take the interior branch)
+// J_f lambda = max(|v-.nJ|, |v+.nJ|) + J_f max(c-, c+)
 template <int DIM, int FLUX>
 ESD_HD void interface_flux(const Node<DIM>& Um, const Node<DIM>& Up, const double* nJ, double Jf, double gamma,
                            double gm1_inv, int dissipation, double* F) {
