@@ -1,18 +1,27 @@
 #!/usr/bin/env python3
 """Benchmark of the entropy-stable modal DSEM residual on one MI355X.
 
-A step is one classical RK4 step on the workload (4 residual evaluations, each
+A step is one classical RK4 step of the workload (4 residual evaluations, each
 the whole path: entropy projection, flux differencing, facet correction,
-interface flux, weight-adjusted inverse; the stage combinations are fused into
-the right-hand-side kernel's output), with the state resident in HBM.  Prints
-one JSON line:
+interface flux, weight-adjusted inverse; the stage combinations are formed by
+the right-hand-side kernel), with the state resident in HBM, replayed from the
+plan's captured HIP graph.  The headline workload is the largest single-GPU
+configuration: four periodic meshes of curved tetrahedra (6 M^3 elements,
+M = 8, 10, 12, 14; 35,904 elements) with per-element degrees uniform on
+2..10 in one batched plan.  Prints one JSON line:
 
   value     FP64 residual evaluations x DOF per second (DOF = elements x (d+2) x modes)
-  roofline  for the dominant kernel (the right-hand-side kernel K2, with its
-            fused stage combination): algorithmic flops or bytes per launch,
-            whichever bound is binding, / its average duration, from HIP events
-            recorded around every launch on its stream during the timed steps
-  cpu_baseline  the dense FP64 oracle on a bounded sample of the same workload
+  roofline  the right-hand-side kernel K2 (all degree buckets of the residual):
+            algorithmic FP64 flops per launch (perfmodel: the oracle's formulas,
+            transcendentals and divisions weighted by their gfx950 instruction
+            cost) / its average duration from HIP events recorded around every
+            launch on its stream; "residual" gives the same for K1 + K2 (+ the
+            mixed-degree interface kernel)
+  cpu_baseline  the dense FP64 oracle on a bounded element sample, all
+            physical host cores; cpu_baseline_protocol adds the 1-core run and
+            the median of 5 on a cheap workload
+  extra     Taylor-Green tetrahedra at p = 4..10, the vortex triangles at p = 4
+            and 8, and the 20-step gradient workload
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
@@ -22,6 +31,8 @@ import argparse
 import json
 import math
 import os
+import statistics
+import subprocess
 import sys
 import time
 
@@ -33,138 +44,62 @@ sys.path.insert(0, ROOT)
 import workloads as wl  # noqa: E402
 
 METRIC = "FP64 residual evals × DOF/s and flux-pairs/s vs FP64 roofline; VJP/forward cost"
+HEADLINE = "batched_tets_M8-10-12-14_p2-10"
 
-WORKLOADS = {
-    "vortex_tri_M64_p4": lambda: wl.vortex_tri(M=64, degree=4),
-    "vortex_tri_M64_p8": lambda: wl.vortex_tri(M=64, degree=8),
-    "tgv_tet_M16_p4": lambda: wl.tgv_tet(M=16, degree=4),
-    "tgv_tet_M16_p6": lambda: wl.tgv_tet(M=16, degree=6),
-}
+# Taylor-Green tetrahedra at p = 4..10 (at p = 9, 10 a smaller mesh keeps the
+# plan's geometry and workspaces near 1 GB), the vortex triangles at p = 4, 8
+WORKLOADS = {n: (lambda n=n: wl.named(n)) for n in
+             [f"tgv_tet_M16_p{p}" for p in range(4, 9)] + ["tgv_tet_M12_p9", "tgv_tet_M12_p10",
+                                                           "vortex_tri_M64_p4", "vortex_tri_M64_p8"]}
+DEFAULT_EXTRA = ",".join(WORKLOADS)
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
-KERNEL_SOURCES = ("device.hpp", "physics.hpp", "kernels.hip", "plan.hpp")
-
-
-def kernel_source_hash() -> str:
-    """sha256 over the sources the right-hand-side kernel is built from."""
-    import hashlib
-
-    h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2312_07874_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()
-
-
 def measured_traffic(name: str):
-    """HBM bytes per K2 launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs
-    recorded in profiles/traffic.json, if they were taken on these kernel
-    sources (else None)."""
-    try:
-        with open(TRAFFIC_FILE) as fh:
-            t = json.load(fh)
-    except (OSError, ValueError):
-        return None
-    if t.get("kernel_source_sha256") != kernel_source_hash():
-        return None
-    w = t.get("workloads", {}).get(name)
-    return None if w is None else w["read_bytes_per_launch"] + w["write_bytes_per_launch"]
+    from paper_2312_07874_amd import profiling
+    return profiling.measured_traffic(name)
 
 
-def run_gpu(name: str, steps: int, warmup: int, autotune: bool = True):
-    import torch
-
-    import paper_2312_07874_amd as esd
+# ---------------------------------------------------------------- roofline
+def _roof(flops: float, bytes_: float, seconds: float, kernel: str, traffic=None):
     from paper_2312_07874_amd import perfmodel as pm
-
-    wk = WORKLOADS[name]()
-    t0 = time.perf_counter()
-    plan = esd.Plan.from_workload(wk)
-    log(f"[bench] {name}: plan {plan.info.n_elements} elements, p={wk.degree}, "
-        f"{plan.info.n_dof} DOF, setup {time.perf_counter() - t0:.1f}s")
-    x = plan.node_coords().cpu().numpy()
-    u = plan.project(torch.tensor(wk.state(x), device="cuda").contiguous())
-    plan.sync_status()
-    if autotune:
-        plan.autotune(u)
-    blocks = plan.tuning()
-    blocks_k1 = plan.tuning_k1()
-    dt = 1e-4
-    if warmup:
-        plan.rk4(u, dt, warmup)
-    torch.cuda.synchronize()
-    plan.sync_status()
-    plan.set_timing(True)
-    plan.get_timing()
-    torch.cuda.synchronize()
-    # the timed steps: one call (one projection of u, then per stage one kernel
-    # that forms the stage combination and projects the next stage input)
-    t0 = time.perf_counter()
-    plan.rk4(u, dt, steps)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    plan.set_timing(False)
-    k1_ms, k2_ms, nlaunch = plan.get_timing()
-    plan.sync_status()
-    fused = plan.tuning_fused()
-    info = plan.info
-    n_res = 4 * steps
-    d, p = wk.dim, wk.degree
-    k2_avg_s = k2_ms / nlaunch * 1e-3
-    res_k1_ms, res_k2_ms = time_residual_kernels(plan, u)
-    # the dominant kernel of a stage: K2 forming the stage combination, and,
-    # with fused stages, projecting the next stage input
-    fl = pm.k2_flops(d, p, wk.ecflux, wk.dissipation) * info.n_elements
-    if fused:
-        fl += pm.k1_flops(d, p) * info.n_elements
-    by = (pm.k2_next_bytes(d, p) if fused else pm.k2_rk_bytes(d, p)) * info.n_elements
-    t_fl = fl / (pm.PEAK_FP64_TFLOPS * 1e12)
-    t_by = by / (pm.PEAK_HBM_GBS * 1e9)
+    t_fl = flops / (pm.PEAK_FP64_TFLOPS * 1e12)
+    t_by = bytes_ / (pm.PEAK_HBM_GBS * 1e9)
     if t_fl >= t_by:
-        roof = {"bound": "alu", "achieved": fl / k2_avg_s / 1e12, "peak": pm.PEAK_FP64_TFLOPS, "unit": "TFLOP/s"}
+        r = {"bound": "alu", "achieved": flops / seconds / 1e12, "peak": pm.PEAK_FP64_TFLOPS, "unit": "TFLOP/s"}
     else:
-        roof = {"bound": "hbm", "achieved": by / k2_avg_s / 1e9, "peak": pm.PEAK_HBM_GBS, "unit": "GB/s"}
-    roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = measured_traffic(name)
-    roof["kernel"] = ("k_rhs<..., true> (RK4 stage: right-hand side, stage combination, next projection)" if fused
-                      else "k_rhs<..., false> (RK4 stage: right-hand side and stage combination; K1 separate)")
-    roof["algorithmic_flops_per_launch"] = fl
-    roof["algorithmic_bytes_per_launch"] = by
-    roof["avg_launch_ms"] = k2_avg_s * 1e3
-    vjp = time_vjp(plan, u)
-    graph_ms = time_graph_steps(plan, u, dt, steps)
-    return {
-        "workload": name,
-        "elements": info.n_elements,
-        "degree": p,
-        "dof": info.n_dof,
-        "value": n_res * info.n_dof / elapsed,
-        "ms_per_step": elapsed / steps * 1e3,
-        "rk4_stages_fused": fused,
-        "ms_per_stage_kernel": k2_avg_s * 1e3,
-        "ms_per_stage_k1": k1_ms / nlaunch,
-        "ms_per_residual_k1_k2": res_k1_ms + res_k2_ms,
-        "k1_avg_ms": res_k1_ms,
-        "k2_avg_ms": res_k2_ms,
-        "flux_pairs_per_s": n_res * info.flux_pairs_paper / elapsed,
-        "flux_pairs_distinct_per_s": n_res * info.flux_pairs_distinct / elapsed,
-        "roofline": roof,
-        "k1_flop_rate_tflops": pm.k1_flops(d, p) * info.n_elements / res_k1_ms / 1e9,
-        "vjp": vjp,
-        "k2_block_autotuned": blocks[0],
-        "k1_block_autotuned": blocks_k1[0],
-        "ms_per_step_graph": graph_ms,
-    }
+        r = {"bound": "hbm", "achieved": bytes_ / seconds / 1e9, "peak": pm.PEAK_HBM_GBS, "unit": "GB/s"}
+    r["frac"] = r["achieved"] / r["peak"]
+    r["traffic"] = traffic
+    r["kernel"] = kernel
+    r["algorithmic_flops_per_launch"] = flops
+    r["algorithmic_bytes_per_launch"] = bytes_
+    r["avg_launch_ms"] = seconds * 1e3
+    return r
 
 
+def _work(buckets, ecflux, dissipation, dim):
+    """Algorithmic flops (K1, K2) and minimum / layout bytes per residual over
+    the buckets [(degree, elements)]."""
+    from paper_2312_07874_amd import perfmodel as pm
+    k1 = k2 = mb = lb = 0
+    for p, n in buckets:
+        f = pm.residual_flops(dim, p, ecflux, dissipation)
+        k1 += n * f["k1"]
+        k2 += n * f["k2"]
+        mb += n * pm.min_bytes(dim, p)
+        lb += n * pm.layout_bytes(dim, p)
+    return k1, k2, mb, lb
+
+
+# ---------------------------------------------------------------- timing helpers
 def time_residual_kernels(plan, u, reps: int = 5):
-    """K1 and K2 of the plain residual (esd_residual), from HIP events around
-    each launch: (K1 ms, K2 ms) averages."""
+    """K1 (with the mixed-degree interface kernel of batched plans) and K2 of
+    the plain residual (esd_residual), from HIP events around each launch on
+    its stream: (K1 ms, K2 ms) averages per residual."""
     import torch
 
     out = torch.empty_like(u)
@@ -176,27 +111,29 @@ def time_residual_kernels(plan, u, reps: int = 5):
         plan.residual(u, out)
     k1, k2, n = plan.get_timing()
     plan.set_timing(False)
+    plan.sync_status()
     return k1 / n, k2 / n
 
 
-def time_graph_steps(plan, u, dt, steps):
-    """The same RK4 steps replayed from the captured graph (no per-kernel events)."""
+def time_rk4_steps(plan, u, dt, steps, warmup):
+    """RK4 steps replayed from the plan's captured graph: ms per step."""
     import torch
 
-    plan.rk4(u, dt, 1)            # capture
+    plan.rk4(u, dt, max(1, warmup))   # captures the graph
     torch.cuda.synchronize()
+    plan.sync_status()
     t0 = time.perf_counter()
     plan.rk4(u, dt, steps)
     torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) / steps * 1e3
+    elapsed = time.perf_counter() - t0
     plan.sync_status()
-    return ms
+    return elapsed
 
 
 def time_vjp(plan, u, reps: int = 5):
-    """Cost of one residual VJP (forward projection + the two adjoint kernels)
-    against one residual evaluation, both timed with events on the stream the
-    library launches on (torch's current stream)."""
+    """One residual VJP (forward projection + the two adjoint kernels) against
+    one residual evaluation, both timed with events on the stream the library
+    launches on (torch's current stream)."""
     import torch
 
     g = torch.Generator(device="cuda").manual_seed(0)
@@ -220,7 +157,70 @@ def time_vjp(plan, u, reps: int = 5):
     return {"residual_ms": f, "vjp_ms": b, "vjp_over_forward": b / f}
 
 
-def run_batched(steps: int, warmup: int):
+# ---------------------------------------------------------------- workloads
+def _measure(plan, u, name, buckets, dim, ecflux, dissipation, steps, warmup, vjp):
+    info = plan.info
+    dt = 1e-4
+    elapsed = time_rk4_steps(plan, u, dt, steps, warmup)
+    n_res = 4 * steps
+    k1_ms, k2_ms = time_residual_kernels(plan, u)
+    k1f, k2f, mb, lb = _work(buckets, ecflux, dissipation, dim)
+    roof = _roof(k2f, mb, k2_ms * 1e-3, "k_rhs (right-hand side; every degree bucket of one residual)",
+                 measured_traffic(name))
+    roof_res = _roof(k1f + k2f, mb, (k1_ms + k2_ms) * 1e-3,
+                     "whole residual: k_entropy_projection (+ k_mixed_exterior) + k_rhs")
+    out = {
+        "workload": name,
+        "elements": int(info.n_elements),
+        "dof": int(info.n_dof),
+        "value": n_res * info.n_dof / elapsed,
+        "ms_per_step": elapsed / steps * 1e3,
+        "steps": steps,
+        "ms_per_residual_k1_k2": k1_ms + k2_ms,
+        "k1_avg_ms": k1_ms,
+        "k2_avg_ms": k2_ms,
+        "flux_pairs_per_s": n_res * info.flux_pairs_paper / elapsed,
+        "flux_pairs_distinct_per_s": n_res * info.flux_pairs_distinct / elapsed,
+        "roofline": roof,
+        "roofline_residual": roof_res,
+        "algorithmic_flops_per_residual": k1f + k2f,
+        "min_bytes_per_residual": mb,
+        "layout_bytes_over_min_bytes": lb / mb,
+        "rk4_stages_fused": plan.tuning_fused(),
+    }
+    if vjp:
+        out["vjp"] = time_vjp(plan, u)
+        out["vjp_over_forward"] = out["vjp"]["vjp_over_forward"]
+    return out
+
+
+def run_single(name: str, steps: int, warmup: int, autotune: bool = True):
+    import torch
+
+    import paper_2312_07874_amd as esd
+
+    wk = WORKLOADS[name]()
+    t0 = time.perf_counter()
+    plan = esd.Plan.from_workload(wk)
+    log(f"[bench] {name}: plan {plan.info.n_elements} elements, p={wk.degree}, "
+        f"{plan.info.n_dof} DOF, setup {time.perf_counter() - t0:.1f}s")
+    x = plan.node_coords().cpu().numpy()
+    u = plan.project(torch.tensor(wk.state(x), device="cuda").contiguous())
+    plan.sync_status()
+    if autotune:
+        plan.autotune(u)
+        log(f"[bench] {name}: autotuned at {time.perf_counter() - t0:.1f}s")
+    vjp = wk.dim == 2 or wk.degree <= 8
+    r = _measure(plan, u, name, [(wk.degree, plan.info.n_elements)], wk.dim, wk.ecflux, wk.dissipation, steps,
+                 warmup, vjp)
+    log(f"[bench] {name}: measured at {time.perf_counter() - t0:.1f}s")
+    r["degree"] = wk.degree
+    r["k2_block_autotuned"] = plan.tuning()[0]
+    r["k1_block_autotuned"] = plan.tuning_k1()[0]
+    return r
+
+
+def run_batched(steps: int, warmup: int, autotune: bool = True):
     """Four periodic tetrahedral meshes (6 M^3 elements, M = 8, 10, 12, 14) with
     per-element degrees uniform on 2..10 in one batched plan."""
     import torch
@@ -236,46 +236,20 @@ def run_batched(steps: int, warmup: int):
     x = plan.node_coords().cpu().numpy()
     u = plan.project(torch.tensor(bt.state(x), device="cuda").reshape(plan.nodal_shape).contiguous())
     plan.sync_status()
-    blocks = plan.autotune(u)
-    dt = 1e-4
-    if warmup:
-        plan.rk4(u, dt, warmup)
-    torch.cuda.synchronize()
-    plan.set_timing(True)
-    plan.get_timing()
-    t0 = time.perf_counter()
-    plan.rk4(u, dt, steps)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    plan.set_timing(False)
-    stage_k1_ms, stage_ms, nstage = plan.get_timing()
-    plan.sync_status()
-    res_k1_ms, res_k2_ms = time_residual_kernels(plan, u)
-    graph_ms = time_graph_steps(plan, u, dt, steps)
-    n_res = 4 * steps
-    return {
-        "workload": bt.name,
-        "elements": int(plan.info.n_elements),
-        "dof": int(plan.info.n_dof),
-        "buckets": [[b["degree"], int(b["n_elements"])] for b in plan.buckets],
-        "value": n_res * plan.info.n_dof / elapsed,
-        "ms_per_step": elapsed / steps * 1e3,
-        "rk4_stages_fused": plan.tuning_fused(),
-        "ms_per_stage_all_buckets": (stage_k1_ms + stage_ms) / nstage,
-        "ms_per_residual_k1_k2": res_k1_ms + res_k2_ms,
-        "k1_and_interfaces_avg_ms": res_k1_ms,
-        "k2_all_buckets_avg_ms": res_k2_ms,
-        "flux_pairs_per_s": n_res * plan.info.flux_pairs_paper / elapsed,
-        "k2_blocks_autotuned": blocks,
-        "ms_per_step_graph": graph_ms,
-    }
+    blocks = plan.autotune(u) if autotune else plan.tuning()
+    buckets = [(int(b["degree"]), int(b["n_elements"])) for b in plan.buckets]
+    r = _measure(plan, u, bt.name, buckets, 3, bt.ecflux, bt.dissipation, steps, warmup, False)
+    r["buckets"] = [list(b) for b in buckets]
+    r["k2_blocks_autotuned"] = list(blocks)
+    return r, plan, u
 
 
 def run_adjoint(nsteps: int = 20):
     """The gradient workload: tgv tet M12 p6 (10,368 curved tetrahedra), nsteps
-    RK4 steps forward with the stage inputs checkpointed, then the discrete
-    adjoint of those steps for a seeded random cotangent of the final state;
-    times against the same steps without checkpoints, and the checkpoint memory."""
+    RK4 steps (dt = 5e-4) forward with the stage inputs checkpointed, then the
+    discrete adjoint of those steps for a seeded random cotangent of the final
+    state; times against the same steps without checkpoints, and the
+    checkpoint memory."""
     import torch
 
     import paper_2312_07874_amd as esd
@@ -285,7 +259,7 @@ def run_adjoint(nsteps: int = 20):
     x = plan.node_coords().cpu().numpy()
     u0 = plan.project(torch.tensor(wk.state(x), device="cuda").contiguous())
     plan.autotune(u0)
-    dt = 1e-3
+    dt = 5e-4
     ckpt = torch.empty((4 * nsteps,) + tuple(u0.shape), dtype=torch.float64, device="cuda")
     g = torch.Generator(device="cuda").manual_seed(1)
     ubar0 = torch.randn(tuple(u0.shape), generator=g, dtype=torch.float64, device="cuda")
@@ -313,7 +287,7 @@ def run_adjoint(nsteps: int = 20):
     fwd_ck = ev[2].elapsed_time(ev[3])
     adj = ev[4].elapsed_time(ev[5])
     return {
-        "workload": f"{wk.name} gradient over {nsteps} RK4 steps",
+        "workload": f"{wk.name} gradient over {nsteps} RK4 steps (dt 5e-4)",
         "elements": plan.info.n_elements,
         "dof": plan.info.n_dof,
         "forward_ms": fwd,
@@ -322,69 +296,187 @@ def run_adjoint(nsteps: int = 20):
         "gradient_over_forward": (fwd_ck + adj) / fwd,
         "adjoint_over_forward": adj / fwd,
         "checkpoint_bytes": ckpt.numel() * 8,
+        "peak_memory_bytes": torch.cuda.max_memory_allocated(),
         "rk4_stages_fused": plan.tuning_fused(),
     }
 
 
-def cpu_baseline(name: str, budget_s: float):
-    """The oracle (dense FP64, PyTorch CPU) timed on a bounded element sample."""
+def run_dense_vs_lines():
+    """The all-pairs (dense-operator) residual against the line-based one on
+    the same nodes (esd_residual_dense vs esd_residual), K1 and K2 timed with
+    HIP events, at p = 2, 5, 10 on triangles (2 x 24^2 curved) and tetrahedra
+    (6 x 5^3 curved), next to the two-point flux counts: the line-based
+    kernel's distinct pairs, the all-pairs count of the dense loops, and the
+    paper's reduction factors (tensor-product vs multidimensional operators on
+    their own node sets, Sec. 5.3), which it counts on symmetric quadrature
+    rules this build does not have."""
+    import torch
+
+    import paper_2312_07874_amd as esd
+
+    paper = {(2, 2): 1.56, (2, 5): 2.78, (2, 10): 4.57, (3, 2): 1.88, (3, 5): 3.44, (3, 10): 10.99}
+    out = []
+    for (dim, p), fac in paper.items():
+        wk = wl.random_tri(M=24, degree=p, seed=5) if dim == 2 else wl.random_tet(M=5, degree=p, seed=5)
+        plan = esd.Plan.from_workload(wk)
+        x = plan.node_coords().cpu().numpy()
+        u = plan.project(torch.tensor(wk.state(x), device="cuda").contiguous())
+        o = torch.empty_like(u)
+        res = {}
+        for kind, fn in (("lines", plan.residual), ("dense", plan.residual_dense)):
+            fn(u, o)
+            torch.cuda.synchronize()
+            plan.set_timing(True)
+            plan.get_timing()
+            for _ in range(3):
+                fn(u, o)
+            k1, k2, n = plan.get_timing()
+            plan.set_timing(False)
+            res[kind] = (k1 / n, k2 / n)
+        plan.sync_status()
+        Q, nq = p + 1, (p + 1) ** dim
+        nfq = (dim + 1) * (Q if dim == 2 else Q * Q)
+        lines = plan.info.flux_pairs_distinct // plan.info.n_elements
+        out.append({"dim": dim, "degree": p, "elements": int(plan.info.n_elements),
+                    "k2_ms_lines": res["lines"][1], "k2_ms_dense": res["dense"][1],
+                    "residual_ms_lines": sum(res["lines"]), "residual_ms_dense": sum(res["dense"]),
+                    "time_ratio_k2": res["dense"][1] / res["lines"][1],
+                    "time_ratio_residual": sum(res["dense"]) / sum(res["lines"]),
+                    "flux_evaluations_per_element_lines": int(lines),
+                    "flux_evaluations_per_element_dense": nq * nq + nq * nfq,
+                    "paper_reduction_factor": fac})
+        log(f"[bench] dense vs lines dim {dim} p {p}: K2 {res['dense'][1]:.3f} / {res['lines'][1]:.3f} ms")
+    return out
+
+
+# ---------------------------------------------------------------- CPU baseline (the oracle)
+def host_cpu():
+    """(physical cores, model name) from lscpu."""
+    try:
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, check=True).stdout
+    except (OSError, subprocess.CalledProcessError):
+        return os.cpu_count() or 1, "unknown"
+    kv = {}
+    for line in txt.splitlines():
+        if ":" in line:
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    try:
+        cores = int(kv.get("Core(s) per socket", "0")) * int(kv.get("Socket(s)", "1"))
+    except ValueError:
+        cores = 0
+    return (cores or os.cpu_count() or 1), kv.get("Model name", "unknown")
+
+
+def cpu_baseline_batched(buckets, per_degree=6, reps=3):
+    """The oracle's residual timed on per_degree elements of every degree of the
+    headline batch (on a 162-tetrahedron mesh of the same warped kind, all
+    physical host cores, median of reps after one warm-up), scaled by the
+    bucket sizes to one residual of the batch."""
     import torch
 
     from oracle import residual as R
 
+    cores, model = host_cpu()
+    torch.set_num_threads(cores)
+    bt = wl.batched_tets()
+    per = {}
+    for p, _ in buckets:
+        wk = wl.Workload(f"sample_p{p}", 3, 3, bt.L, p, bt.warp, bt.state, bt.ecflux, bt.dissipation)
+        prob = R.setup(wk.mesh(), p, wk.warp, wk.gamma, wk.ecflux, wk.dissipation)
+        ut = R.project(prob, torch.tensor(wk.state(prob.geo.x_vol.numpy())))
+        el = list(range(7, 7 + 25 * per_degree, 25))
+        R.residual(prob, ut, el)               # warm-up
+        ts = []
+        for _ in range(reps):
+            t = time.perf_counter()
+            R.residual(prob, ut, el)
+            ts.append(time.perf_counter() - t)
+        per[p] = statistics.median(ts) / len(el)
+        log(f"[bench] oracle, {len(el)} tetrahedra at p = {p}: {per[p] * len(el):.2f}s")
+    t_res = sum(n * per[p] for p, n in buckets)
+    ndof = sum(n * 5 * (p + 1) * (p + 2) * (p + 3) // 6 for p, n in buckets)
+    spent = sum(per.values()) * per_degree * (reps + 1)
+    return {"value": ndof / t_res, "unit": "DOF*residual-evals/s", "cores": cores, "kind": "oracle",
+            "cpu_model": model,
+            "sample": (f"dense oracle residual of {per_degree} curved tetrahedra of each degree 2..10 (each with its "
+                       f"neighbours' entropy projection; median of {reps} after one warm-up; {spent:.1f}s of CPU "
+                       f"work), per-element times scaled by the bucket sizes to one residual of the "
+                       f"35,904-element batch")}
+
+
+def cpu_baseline_protocol(name="vortex_tri_M64_p4", nel=64, reps=5):
+    """1-core and all-core median of 5 (after one warm-up) of the oracle's
+    residual on a fixed element sample."""
+    import torch
+
+    from oracle import residual as R
+
+    cores, model = host_cpu()
     wk = WORKLOADS[name]()
-    t0 = time.perf_counter()
     prob = R.setup(wk.mesh(), wk.degree, wk.warp, wk.gamma, wk.ecflux, wk.dissipation)
     ut = R.project(prob, torch.tensor(wk.state(prob.geo.x_vol.numpy())))
-    log(f"[bench] oracle setup {time.perf_counter() - t0:.1f}s")
-    rng = np.random.default_rng(0)
-    order = rng.permutation(prob.ne)
-    chunk = 8
-    done, spent = 0, 0.0
-    while spent < budget_s and done < prob.ne:
-        el = order[done:done + chunk]
-        t = time.perf_counter()
+    el = np.random.default_rng(0).permutation(prob.ne)[:nel]
+    ndof = nel * prob.nc * prob.ref.Np
+    res = {}
+    for threads in (1, cores):
+        torch.set_num_threads(threads)
         R.residual(prob, ut, el)
-        spent += time.perf_counter() - t
-        done += len(el)
-    ndof = done * prob.nc * prob.ref.Np
-    return {"value": ndof / spent, "unit": "DOF*residual-evals/s", "cores": torch.get_num_threads(),
-            "kind": "oracle",
-            "sample": f"dense oracle residual of {done} of {prob.ne} elements of {name} "
-                      f"(each with its neighbours' entropy projection), {spent:.1f}s"}
+        ts = []
+        for _ in range(reps):
+            t = time.perf_counter()
+            R.residual(prob, ut, el)
+            ts.append(time.perf_counter() - t)
+        res[threads] = statistics.median(ts)
+    torch.set_num_threads(cores)
+    return {"workload": name, "unit": "DOF*residual-evals/s", "cpu_model": model,
+            "value_1_core": ndof / res[1], "value_all_cores": ndof / res[cores], "cores": cores,
+            "sample": f"{nel} elements, median of {reps} after one warm-up"}
 
 
+# ---------------------------------------------------------------- main
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="vortex_tri_M64_p4", choices=sorted(WORKLOADS))
-    ap.add_argument("--extra", default="vortex_tri_M64_p8,tgv_tet_M16_p4,tgv_tet_M16_p6",
+    ap.add_argument("--workload", default=HEADLINE, choices=[HEADLINE] + sorted(WORKLOADS))
+    ap.add_argument("--extra", default=DEFAULT_EXTRA,
                     help="comma-separated additional workloads reported under 'extra' ('' for none)")
-    ap.add_argument("--extra-steps", type=int, default=3)
-    ap.add_argument("--no-batched", action="store_true", help="skip the batched mixed-degree workload")
+    ap.add_argument("--extra-steps", type=int, default=4)
     ap.add_argument("--no-adjoint", action="store_true", help="skip the 20-step gradient workload")
+    ap.add_argument("--no-dense", action="store_true", help="skip the all-pairs vs line-based comparison")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default block sizes")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="finish with a plain 1 GiB device-to-device copy (counter calibration for profiles)")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (see the sharding "
-              "design notes); run with --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (the sharding design is "
+              "in the design notes); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
-    main_res = run_gpu(args.workload, args.steps, args.warmup, not args.no_autotune)
+    if args.workload == HEADLINE:
+        main_res, _, _ = run_batched(args.steps, args.warmup, not args.no_autotune)
+        config = {"workload": HEADLINE, "elements": main_res["elements"], "degrees": "2..10 (per element)",
+                  "buckets": main_res["buckets"], "dof": main_res["dof"],
+                  "step": "one classical RK4 step (4 residual evaluations + stage combinations), graph-replayed"}
+    else:
+        main_res = run_single(args.workload, args.steps, args.warmup, not args.no_autotune)
+        config = {"workload": args.workload, "elements": main_res["elements"], "degree": main_res["degree"],
+                  "dof": main_res["dof"],
+                  "step": "one classical RK4 step (4 residual evaluations + stage combinations), graph-replayed"}
     extra = []
     for name in [s for s in args.extra.split(",") if s]:
         if name != args.workload:
-            extra.append(run_gpu(name, args.extra_steps, 1, not args.no_autotune))
-    if not args.no_batched:
-        extra.append(run_batched(args.extra_steps, 1))
+            extra.append(run_single(name, args.extra_steps, 1, not args.no_autotune))
     if not args.no_adjoint:
         extra.append(run_adjoint())
-    cpu = None if args.no_cpu_baseline else cpu_baseline(args.workload, args.cpu_seconds)
+    dense = None if args.no_dense else run_dense_vs_lines()
+    cpu = proto = None
+    if not args.no_cpu_baseline:
+        if args.workload == HEADLINE:
+            cpu = cpu_baseline_batched([tuple(b) for b in main_res["buckets"]])
+        proto = cpu_baseline_protocol()
     out = {
         "metric": METRIC,
         "value": main_res["value"],
@@ -398,24 +490,24 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": args.workload, "elements": main_res["elements"], "degree": main_res["degree"],
-                   "dof": main_res["dof"],
-                   "step": "one classical RK4 step (4 residual evaluations + stage combinations)"},
+        "config": config,
         "flux_pairs_per_s": main_res["flux_pairs_per_s"],
         "flux_pairs_distinct_per_s": main_res["flux_pairs_distinct_per_s"],
-        "rk4_stages_fused": main_res["rk4_stages_fused"],
-        "ms_per_stage_kernel": main_res["ms_per_stage_kernel"],
         "ms_per_residual_k1_k2": main_res["ms_per_residual_k1_k2"],
-        "ms_per_step_graph": main_res["ms_per_step_graph"],
         "k1_avg_ms": main_res["k1_avg_ms"],
-        "k2_block_autotuned": main_res["k2_block_autotuned"],
-        "k1_block_autotuned": main_res["k1_block_autotuned"],
+        "k2_avg_ms": main_res["k2_avg_ms"],
         "roofline": main_res["roofline"],
-        "vjp_over_forward": main_res["vjp"]["vjp_over_forward"],
-        "vjp": main_res["vjp"],
+        "roofline_residual": main_res["roofline_residual"],
+        "layout_bytes_over_min_bytes": main_res["layout_bytes_over_min_bytes"],
+        "rk4_stages_fused": main_res["rk4_stages_fused"],
         "cpu_baseline": cpu,
+        "cpu_baseline_protocol": proto,
         "extra": extra,
+        "dense_vs_lines": dense,
     }
+    for k in ("vjp_over_forward", "vjp", "k2_blocks_autotuned", "k2_block_autotuned", "k1_block_autotuned"):
+        if k in main_res:
+            out[k] = main_res[k]
     print(json.dumps(out), flush=True)
     if args.calibrate_copy:
         import torch

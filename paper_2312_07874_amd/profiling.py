@@ -1,30 +1,34 @@
-"""Summaries of rocprofv3 output for the right-hand-side kernel K2.
+"""The profiled command and summaries of its rocprofv3 output.
 
-Two commands, both reading the CSV files rocprofv3 writes with
-``--output-format csv``:
+  python -m paper_2312_07874_amd.profiling run WORKLOAD [REPS] [--no-autotune]
+      The command to profile: builds the plan of WORKLOAD (a name understood by
+      workloads.named), projects its state, autotunes its block sizes (as the
+      benchmark does; --no-autotune keeps the defaults, for counter runs),
+      evaluates REPS residuals
+      (esd_residual: per residual K1 of every degree bucket, the mixed-degree
+      interface kernel of batched plans, K2 of every bucket), synchronises,
+      and ends with a plain 1 GiB device-to-device copy whose counters
+      calibrate the traffic counters.
 
   python -m paper_2312_07874_amd.profiling traffic WORKLOAD FETCH_CSV WRITE_CSV
-      HBM bytes of K2 from a ``--pmc FETCH_SIZE`` and a ``--pmc WRITE_SIZE`` run
-      of ``bench.py --workload WORKLOAD --steps 1 --warmup 0 --no-autotune
-      --extra "" --no-batched --no-adjoint --calibrate-copy``.  The first four K2 dispatches
-      of such a run are the four stage kernels of the timed RK4 step (right-hand
-      side and stage combination, with fused stages also the next projection);
-      their counters
-      are averaged and scaled by what the same counters read on the closing
-      1 GiB device-to-device copy.  The result goes into profiles/traffic.json
-      with a hash of the kernel sources (bench.py reports it only while they
-      are unchanged).
+      HBM bytes of K2 per residual from a ``--pmc FETCH_SIZE`` and a
+      ``--pmc WRITE_SIZE`` run of the command above: the K2 dispatches (every
+      bucket) summed per residual, averaged over the last 5 residuals (after
+      the autotuner's trial launches), scaled by
+      what the same counter reads for the copy.  The result goes into
+      profiles/traffic.json with a hash of the kernel sources (bench.py reports
+      it only while they are unchanged).
 
   python -m paper_2312_07874_amd.profiling counters CSV [CSV ...]
-      Any ``--pmc`` counters of a ``--steps 1 --warmup 0 --no-autotune`` bench
-      run: per counter, the mean over the four stage kernels of the timed RK4
-      step and over the entropy-projection launches, as a markdown table.
+      Any ``--pmc`` counters of the command above: per counter, the mean per
+      residual of K2 (every bucket summed) and of K1 over the last 5 residuals,
+      as a markdown table.
 
-  python -m paper_2312_07874_amd.profiling stats TRACE_CSV [KERNEL_PREFIX]
-      Per-block-size launch count and average duration of a kernel from a
-      ``--kernel-trace`` run (default prefix ``esd::k_rhs<``), as a markdown table.
+  python -m paper_2312_07874_amd.profiling stats TRACE_CSV
+      Launch count and average duration per kernel (and block size) from a
+      ``--kernel-trace`` run, as a markdown table.
 
-No GPU is needed: this only reads files.
+Only ``run`` needs a GPU; the others read files.
 """
 from __future__ import annotations
 
@@ -36,8 +40,35 @@ import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+KERNEL_SOURCES = ("device.hpp", "physics.hpp", "kernels.hip", "plan.hpp")
 K2_PREFIX = "esd::k_rhs<"
+K1_PREFIX = "esd::k_entropy_projection<"
 COPY_BYTES = 1 << 30
+
+
+def kernel_source_hash() -> str:
+    """sha256 over the sources the right-hand-side kernel is built from."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2312_07874_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(name: str):
+    """HBM bytes of K2 per residual recorded in profiles/traffic.json, if they
+    were taken on the current kernel sources (else None)."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    w = t.get("workloads", {}).get(name)
+    return None if w is None else w["read_bytes_per_residual"] + w["write_bytes_per_residual"]
 
 
 def _rows(path):
@@ -62,110 +93,162 @@ def _short(name):
     return name.split("(")[0]
 
 
-def _is_k2(name):
-    return _short(name).startswith(K2_PREFIX)
+def _per_residual(rows, prefix):
+    """Sums over each run of consecutive dispatches of kernels with the prefix
+    (one run per residual: K1 of every bucket, then the interface kernels,
+    then K2 of every bucket)."""
+    sums, cur, inside = [], 0.0, False
+    for _, n, v in rows:
+        if _short(n).startswith(prefix):
+            cur += v
+            inside = True
+        elif inside:
+            sums.append(cur)
+            cur, inside = 0.0, False
+    if inside:
+        sums.append(cur)
+    return sums
 
 
-def _k2_and_copy(path, counter):
+def _k2_and_copy(path, counter, last=5):
+    """K2 sums of the last residuals (the run command's, after the autotuner's
+    trial launches) and the copy's counter."""
     rows = _counter(path, counter)
-    k2 = [(d, n, v) for d, n, v in rows if _is_k2(n)]
-    copies = [v for d, n, v in rows if "copyBuffer" in n]
-    if len(k2) < 4 or not copies:
-        raise SystemExit(f"{path}: need 4 K2 dispatches and the calibration copy, found {len(k2)} and {len(copies)}")
-    return k2[:4], max(copies)
+    k2 = _per_residual([r for r in rows if "copyBuffer" not in r[1]], K2_PREFIX)[-last:]
+    copies = [v for _, n, v in rows if "copyBuffer" in n]
+    if not k2 or not copies:
+        raise SystemExit(f"{path}: need K2 dispatches and the calibration copy")
+    return k2, max(copies)
 
 
 def traffic(workload, fetch_csv, write_csv):
-    import bench                              # kernel_source_hash, the workloads
+    import workloads as wl
+
     from . import perfmodel as pm
 
     k2f, copy_f = _k2_and_copy(fetch_csv, "FETCH_SIZE")
     k2w, copy_w = _k2_and_copy(write_csv, "WRITE_SIZE")
     fetch_scale = COPY_BYTES / (copy_f * 1024.0)
     write_scale = COPY_BYTES / (copy_w * 1024.0)
-    fk = [v for _, _, v in k2f]
-    wk = [v for _, _, v in k2w]
-    wl = bench.WORKLOADS[workload]()
-    ne = int(wl.mesh().elem_vertex_ids.shape[0])
+    w = wl.named(workload)
+    if hasattr(w, "meshes"):
+        import numpy as np
+        buckets = {}
+        for d in w.degrees:
+            for p, n in zip(*np.unique(d, return_counts=True)):
+                buckets[int(p)] = buckets.get(int(p), 0) + int(n)
+        dim, items = w.dim, sorted(buckets.items())
+    else:
+        dim, items = w.dim, [(w.degree, w.mesh().n_elements)]
     rec = {
-        "kernel": _short(k2f[0][1]),
-        "launches": "the 4 stages of one RK4 step",
-        "fetch_kib_per_stage": fk,
-        "write_kib_per_stage": wk,
+        "kernel": "esd::k_rhs (every bucket of one residual)",
+        "residuals": len(k2f),
+        "fetch_kib_per_residual": k2f,
+        "write_kib_per_residual": k2w,
         "fetch_scale": fetch_scale,
         "write_scale": write_scale,
-        "read_bytes_per_launch": statistics.fmean(fk) * 1024.0 * fetch_scale,
-        "write_bytes_per_launch": statistics.fmean(wk) * 1024.0 * write_scale,
-        "algorithmic_bytes_per_launch": (pm.k2_next_bytes(wl.dim, wl.degree) if _short(k2f[0][1]).endswith("true>")
-                                         else pm.k2_rk_bytes(wl.dim, wl.degree)) * ne,
+        "read_bytes_per_residual": statistics.fmean(k2f) * 1024.0 * fetch_scale,
+        "write_bytes_per_residual": statistics.fmean(k2w) * 1024.0 * write_scale,
+        "min_bytes_per_residual": sum(n * pm.min_bytes(dim, p) for p, n in items),
+        "layout_bytes_k2_per_residual": sum(n * pm.k2_bytes(dim, p) for p, n in items),
     }
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         t = {}
-    h = bench.kernel_source_hash()
+    h = kernel_source_hash()
     if t.get("kernel_source_sha256") != h:
-        t = {"kernel_source_sha256": h, "kernel_sources": list(bench.KERNEL_SOURCES), "workloads": {}}
+        t = {"kernel_source_sha256": h, "kernel_sources": list(KERNEL_SOURCES), "workloads": {}}
     t["workloads"][workload] = rec
     with open(TRAFFIC_FILE, "w") as fh:
         json.dump(t, fh, indent=1)
-    meas = rec["read_bytes_per_launch"] + rec["write_bytes_per_launch"]
-    print(f"| {workload} | `{rec['kernel']}` | {statistics.fmean(fk):.1f} | {statistics.fmean(wk):.1f} | "
-          f"{fetch_scale:.3f} / {write_scale:.3f} | {rec['read_bytes_per_launch'] / 1e6:.2f} MB | "
-          f"{rec['write_bytes_per_launch'] / 1e6:.2f} MB | {rec['algorithmic_bytes_per_launch'] / 1e6:.2f} MB | "
-          f"{meas / rec['algorithmic_bytes_per_launch']:.2f} |")
+    meas = rec["read_bytes_per_residual"] + rec["write_bytes_per_residual"]
+    print(f"| {workload} | {statistics.fmean(k2f):.1f} | {statistics.fmean(k2w):.1f} | "
+          f"{fetch_scale:.3f} / {write_scale:.3f} | {rec['read_bytes_per_residual'] / 1e6:.2f} MB | "
+          f"{rec['write_bytes_per_residual'] / 1e6:.2f} MB | {rec['layout_bytes_k2_per_residual'] / 1e6:.2f} MB | "
+          f"{rec['min_bytes_per_residual'] / 1e6:.2f} MB | {meas / rec['layout_bytes_k2_per_residual']:.2f} |")
 
 
 def counters(paths):
     k2, k1 = {}, {}
-    names = {}
     for path in paths:
-        seen = {}
-        for r in sorted(_rows(path), key=lambda r: int(r["Dispatch_Id"])):
-            name = _short(r["Kernel_Name"])
-            c = r["Counter_Name"]
-            v = float(r["Counter_Value"])
-            if name.startswith(K2_PREFIX):
-                n = seen.setdefault((c, "k2"), 0)
-                if n < 4:
-                    k2.setdefault(c, []).append(v)
-                    names["k2"] = name
-                seen[(c, "k2")] = n + 1
-            elif name.startswith("esd::k_entropy_projection<") and name.endswith("false>"):
-                k1.setdefault(c, []).append(v)
-                names["k1"] = name
-    print(f"| counter | `{names.get('k2', 'K2')}` (4 stages) | `{names.get('k1', 'K1')}` |")
+        rows = list(_rows(path))
+        for c in sorted({r["Counter_Name"] for r in rows}):
+            sel = sorted(((int(r["Dispatch_Id"]), r["Kernel_Name"], float(r["Counter_Value"]))
+                          for r in rows if r["Counter_Name"] == c and "copyBuffer" not in r["Kernel_Name"]))
+            k2[c] = _per_residual(sel, K2_PREFIX)[-5:]
+            k1[c] = _per_residual(sel, K1_PREFIX)[-5:]
+    print("| counter | K2 per residual (every bucket) | K1 per residual |")
     print("|---|---|---|")
     for c in k2:
-        a = statistics.fmean(k2[c])
-        b = statistics.fmean(k1[c]) if c in k1 else float("nan")
+        a = statistics.fmean(k2[c]) if k2[c] else float("nan")
+        b = statistics.fmean(k1[c]) if k1.get(c) else float("nan")
         print(f"| {c} | {a:.4g} | {b:.4g} |")
 
 
-def stats(trace_csv, prefix=K2_PREFIX):
+def stats(trace_csv):
     by = {}
     for r in _rows(trace_csv):
         name = _short(r.get("Kernel_Name", ""))
-        if not name.startswith(prefix):
+        if not name.startswith("esd::"):
             continue
         bs = int(r.get("Workgroup_Size_X") or r.get("Workgroup_Size") or 0)
         dur = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
         by.setdefault((name, bs), []).append(dur)
-    print("| kernel | block | launches | average us |")
-    print("|---|---|---|---|")
+    print("| kernel | block | launches | average us | total us |")
+    print("|---|---|---|---|---|")
     for (name, bs), d in sorted(by.items()):
-        print(f"| `{name}` | {bs} | {len(d)} | {statistics.fmean(d) / 1e3:.2f} |")
+        print(f"| `{name}` | {bs} | {len(d)} | {statistics.fmean(d) / 1e3:.2f} | {sum(d) / 1e3:.1f} |")
+
+
+def run(workload, reps=5, autotune=True):
+    sys.path.insert(0, ROOT)
+    import torch
+
+    import workloads as wl
+
+    import paper_2312_07874_amd as esd
+
+    w = wl.named(workload)
+    if hasattr(w, "meshes"):
+        plan = esd.BatchedPlan(w.dim, [(m.elem_vertex_ids, m.elem_vertex_coords, d) for m, d in zip(w.meshes, w.degrees)],
+                               w.warp, w.gamma, w.ecflux, w.dissipation)
+        x = plan.node_coords().cpu().numpy()
+        u = plan.project(torch.tensor(w.state(x), device="cuda").reshape(plan.nodal_shape).contiguous())
+    else:
+        plan = esd.Plan.from_workload(w)
+        x = plan.node_coords().cpu().numpy()
+        u = plan.project(torch.tensor(w.state(x), device="cuda").contiguous())
+    print(f"[profiling] {workload}: plan built, state projected", flush=True)
+    if autotune:
+        plan.autotune(u)
+        print(f"[profiling] {workload}: autotuned", flush=True)
+    out = torch.empty_like(u)
+    torch.cuda.synchronize()
+    for i in range(reps):
+        plan.residual(u, out)
+        torch.cuda.synchronize()
+        print(f"[profiling] {workload}: residual {i + 1} of {reps}", flush=True)
+    plan.sync_status()
+    a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(f"[profiling] {workload}: calibration copy 1 GiB; blocks {plan.tuning()}", flush=True)
 
 
 def main(argv):
-    if len(argv) >= 4 and argv[0] == "traffic":
+    if len(argv) >= 2 and argv[0] == "run":
+        pos = [a for a in argv[1:] if not a.startswith("--")]
+        run(pos[0], int(pos[1]) if len(pos) > 1 else 5, "--no-autotune" not in argv)
+    elif len(argv) >= 4 and argv[0] == "traffic":
         sys.path.insert(0, ROOT)
         traffic(argv[1], argv[2], argv[3])
     elif len(argv) >= 2 and argv[0] == "counters":
         counters(argv[1:])
     elif len(argv) >= 2 and argv[0] == "stats":
-        stats(argv[1], *(argv[2:3]))
+        stats(argv[1])
     else:
         raise SystemExit(__doc__)
 

@@ -17,12 +17,14 @@ def test_distinct_pair_counts_match_the_closed_forms(dim, p):
     correction pairs: (q+1)^2 (q+3) per triangle, (q+1)^3 (2.5 q + 4) per
     tetrahedron (lines of q+1 nodes: q(q+1)/2 pairs each; triangles 2 (q+1)
     lines and 3 (q+1)^2 facet pairs; tetrahedra 3 (q+1)^2 lines and
-    3 (q+1)^3 + (q+1)^4 facet pairs)."""
+    3 (q+1)^3 + (q+1)^4 facet pairs); a pair on an eta_1 line belongs to every
+    S^l, one on the last line family to one."""
     q = p
-    v2, v1, fc, nif = pm.pair_counts(dim, p)
-    got = v2 + v1 + fc
+    vol, fc, nif = pm.pair_counts(dim, p)
+    got = sum(n for n, _ in vol) + fc
     want = (q + 1) ** 2 * (q + 3) if dim == 2 else int(round((q + 1) ** 3 * (2.5 * q + 4)))
     assert got == want
+    assert [t for _, t in vol] == list(range(dim, 0, -1))
     assert nif == (3 * (q + 1) if dim == 2 else 4 * (q + 1) ** 2)
 
 
@@ -31,9 +33,38 @@ def test_distinct_pair_counts_match_the_closed_forms(dim, p):
 def test_stage_byte_models_are_ordered(dim, p):
     """The plain residual's K2 < the RK4 stage kernel that forms the stage
     combination < that one plus a separate K1; fusing the next projection into
-    the stage kernel saves the stage input's write and read."""
+    the stage kernel saves the stage input's write and read; the library's
+    layout moves at least the single-pass minimum."""
     plain, rk, fused, k1 = pm.k2_bytes(dim, p), pm.k2_rk_bytes(dim, p), pm.k2_next_bytes(dim, p), pm.k1_bytes(dim, p)
     assert plain < rk < fused < rk + k1
+    assert pm.layout_bytes(dim, p) >= pm.min_bytes(dim, p)
+
+
+def test_minimum_bytes_match_the_stated_figures():
+    """8 [N_c (2 N_p + 2 N_f N_qf) + (d^2 + 1) N_q + d N_f N_qf]: tetrahedra
+    23.2 KB at p = 4, 54.5 KB at p = 6, 179.7 KB at p = 10; triangles 3.2 KB at
+    p = 4, 8.3 KB at p = 8."""
+    assert pm.min_bytes(3, 4) == 8 * (5 * (2 * 35 + 2 * 100) + 10 * 125 + 3 * 100)
+    assert abs(pm.min_bytes(3, 6) / 1e3 - 54.5) < 0.1 and abs(pm.min_bytes(3, 10) / 1e3 - 179.7) < 0.1
+    assert abs(pm.min_bytes(2, 4) / 1e3 - 3.16) < 0.01 and abs(pm.min_bytes(2, 8) / 1e3 - 8.28) < 0.01
+
+
+def test_flop_model_components():
+    """The weighted counts: a division, square root, logarithm and exponential
+    cost more than one flop; the residual's flops grow with the degree; the
+    volume pairs of a tetrahedron at p = 6 are the distinct pairs times the
+    flux and its direction and accumulation."""
+    w = pm.weights()
+    assert all(w[k] > 1 for k in ("div", "sqrt", "log", "exp"))
+    prev = 0
+    for p in range(2, 11):
+        f = pm.residual_flops(3, p, 0, 1)
+        assert f["total"] == f["k1"] + f["k2"] and f["total"] > prev
+        prev = f["total"]
+    f = pm.residual_flops(3, 6, 0, 0)
+    Q = 7
+    n = Q * Q * Q * (Q - 1) // 2
+    assert f["volume_pairs"] == sum(n * (f["flux_per_pair"] + 9 * t - 3 + 10) for t in (3, 2, 1))
 
 
 def _write_csv(path, header, rows):
@@ -49,20 +80,19 @@ _PMC = ["Correlation_Id", "Dispatch_Id", "Agent_Id", "Queue_Id", "Process_Id", "
 
 
 def _pmc_rows(counter, values):
-    """K1 first, four stage kernels, a plain residual's K2 and the 1 GiB copy
-    last (counter values in KiB, as rocprofv3 reports them)."""
-    names = (["void esd::k_entropy_projection<2, 4, false>(double const*)"]
-             + ["void esd::k_rhs<2, 4, 0, true>(double const*, double*)"] * 4
-             + ["void esd::k_rhs<2, 4, 0, false>(double const*, double*)", "__amd_rocclr_copyBuffer"])
+    """Two residuals (K1, K2) of a single-degree plan and the 1 GiB copy last
+    (counter values in KiB, as rocprofv3 reports them)."""
+    names = (["void esd::k_entropy_projection<2, 4, false>(double const*)",
+              "void esd::k_rhs<2, 4, 0, false>(double const*, double*)"] * 2 + ["__amd_rocclr_copyBuffer"])
     rows = []
     for d, (n, v) in enumerate(zip(names, values), start=1):
         rows.append([d, d, "Agent 1", 1, 1, 1, 1, 1, n, 256, 0, 0, 100, 0, 32, counter, v, 0, 1])
     return rows
 
 
-def test_traffic_reader_takes_the_stage_kernels_and_the_copy_scale(tmp_path, monkeypatch):
-    fetch = [9.0, 100.0, 120.0, 120.0, 100.0, 7.0, 1 << 19]       # copy: FETCH reads half of 1 GiB
-    write = [5.0, 40.0, 40.0, 40.0, 20.0, 3.0, 1 << 20]            # copy: WRITE reads all of it
+def test_traffic_reader_sums_k2_per_residual_and_takes_the_copy_scale(tmp_path, monkeypatch):
+    fetch = [9.0, 100.0, 7.0, 120.0, 1 << 19]       # copy: FETCH reads half of 1 GiB
+    write = [5.0, 40.0, 3.0, 30.0, 1 << 20]         # copy: WRITE reads all of it
     fcsv, wcsv = tmp_path / "f.csv", tmp_path / "w.csv"
     _write_csv(fcsv, _PMC, _pmc_rows("FETCH_SIZE", fetch))
     _write_csv(wcsv, _PMC, _pmc_rows("WRITE_SIZE", write))
@@ -70,40 +100,23 @@ def test_traffic_reader_takes_the_stage_kernels_and_the_copy_scale(tmp_path, mon
     monkeypatch.setattr(prof, "TRAFFIC_FILE", str(out))
     prof.traffic("vortex_tri_M64_p4", str(fcsv), str(wcsv))
     rec = json.load(open(out))["workloads"]["vortex_tri_M64_p4"]
-    assert rec["kernel"] == "esd::k_rhs<2, 4, 0, true>"
-    assert rec["fetch_kib_per_stage"] == [100.0, 120.0, 120.0, 100.0]
+    assert rec["fetch_kib_per_residual"] == [100.0, 120.0]
     assert rec["fetch_scale"] == pytest.approx(2.0) and rec["write_scale"] == pytest.approx(1.0)
-    assert rec["read_bytes_per_launch"] == pytest.approx(110.0 * 1024 * 2.0)
-    assert rec["write_bytes_per_launch"] == pytest.approx(35.0 * 1024)
-    # the fused stage kernel is priced with its own byte model, 8192 triangles
-    assert rec["algorithmic_bytes_per_launch"] == pm.k2_next_bytes(2, 4) * 8192
+    assert rec["read_bytes_per_residual"] == pytest.approx(110.0 * 1024 * 2.0)
+    assert rec["write_bytes_per_residual"] == pytest.approx(35.0 * 1024)
+    assert rec["min_bytes_per_residual"] == pm.min_bytes(2, 4) * 8192
+    monkeypatch.setattr(prof, "kernel_source_hash", lambda: json.load(open(out))["kernel_source_sha256"])
+    assert prof.measured_traffic("vortex_tri_M64_p4") == pytest.approx(110.0 * 1024 * 2.0 + 35.0 * 1024)
 
 
-def test_traffic_reader_rejects_a_run_without_the_calibration_copy(tmp_path, monkeypatch):
-    rows = [r for r in _pmc_rows("FETCH_SIZE", [1.0] * 7) if "copyBuffer" not in r[8]]
-    fcsv = tmp_path / "f.csv"
-    _write_csv(fcsv, _PMC, rows)
-    monkeypatch.setattr(prof, "TRAFFIC_FILE", str(tmp_path / "t.json"))
-    with pytest.raises(SystemExit):
-        prof.traffic("vortex_tri_M64_p4", str(fcsv), str(fcsv))
-
-
-def test_stats_groups_launches_by_block(tmp_path, capsys):
-    hdr = ["Kind", "Agent_Id", "Queue_Id", "Stream_Id", "Thread_Id", "Dispatch_Id", "Kernel_Id", "Kernel_Name",
-           "Correlation_Id", "Start_Timestamp", "End_Timestamp", "LDS_Block_Size", "Scratch_Size", "VGPR_Count",
-           "Accum_VGPR_Count", "SGPR_Count", "Workgroup_Size_X", "Workgroup_Size_Y", "Workgroup_Size_Z",
-           "Grid_Size_X", "Grid_Size_Y", "Grid_Size_Z"]
-    k2 = "void esd::k_rhs<3, 6, 0, false>(double const*)"
-    rows = []
-    for i, (bs, dur) in enumerate([(256, 2000), (256, 4000), (512, 9000), (256, 3000)]):
-        rows.append(["KERNEL_DISPATCH", "Agent 1", 1, 0, 1, i, 1, k2, i, 1000 * i, 1000 * i + dur,
-                     0, 0, 100, 0, 32, bs, 1, 1, bs, 1, 1])
-    rows.append(["KERNEL_DISPATCH", "Agent 1", 1, 0, 1, 9, 2, "__amd_rocclr_copyBuffer", 9, 0, 5, 0, 0, 8, 0, 32,
-                 512, 1, 1, 512, 1, 1])
-    t = tmp_path / "trace.csv"
-    _write_csv(t, hdr, rows)
-    prof.stats(str(t))
-    out = capsys.readouterr().out
-    assert "| `esd::k_rhs<3, 6, 0, false>` | 256 | 3 | 3.00 |" in out
-    assert "| `esd::k_rhs<3, 6, 0, false>` | 512 | 1 | 9.00 |" in out
-    assert "copyBuffer" not in out
+def test_batched_k2_dispatches_are_summed_per_residual():
+    rows = [(1, "void esd::k_entropy_projection<3, 2, false>(x)", 1.0),
+            (2, "void esd::k_entropy_projection<3, 3, false>(x)", 2.0),
+            (3, "void esd::k_mixed_exterior<3, 2>(x)", 0.5),
+            (4, "void esd::k_rhs<3, 2, 0, false>(x)", 10.0),
+            (5, "void esd::k_rhs<3, 3, 0, false>(x)", 20.0),
+            (6, "void esd::k_entropy_projection<3, 2, false>(x)", 1.0),
+            (7, "void esd::k_rhs<3, 2, 0, false>(x)", 11.0),
+            (8, "void esd::k_rhs<3, 3, 0, false>(x)", 21.0)]
+    assert prof._per_residual(rows, prof.K2_PREFIX) == [30.0, 32.0]
+    assert prof._per_residual(rows, prof.K1_PREFIX) == [3.0, 1.0]

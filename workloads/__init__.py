@@ -298,3 +298,19 @@ def tgv_tet_mach(M=4, degree=4, Ma=0.1, dissipation=1) -> Workload:
     L = 2.0 * math.pi
     return Workload(f"tgv_tet_M{M}_p{degree}_Ma{Ma}", 3, M, L, degree, make_warp_sinprod(L, 0.05),
                     lambda x, gamma=GAMMA: taylor_green(x, Ma, gamma), 0, dissipation)
+
+
+def named(name: str):
+    """The benchmark workload of a given name: vortex_tri_M{M}_p{p},
+    tgv_tet_M{M}_p{p}, batched_tets_M{M1-M2-...}_p{lo}-{hi}."""
+    import re
+    m = re.fullmatch(r"vortex_tri_M(\d+)_p(\d+)", name)
+    if m:
+        return vortex_tri(M=int(m.group(1)), degree=int(m.group(2)))
+    m = re.fullmatch(r"tgv_tet_M(\d+)_p(\d+)", name)
+    if m:
+        return tgv_tet(M=int(m.group(1)), degree=int(m.group(2)))
+    m = re.fullmatch(r"batched_tets_M([\d-]+)_p(\d+)-(\d+)", name)
+    if m:
+        return batched_tets(Ms=tuple(int(x) for x in m.group(1).split("-")), lo=int(m.group(2)), hi=int(m.group(3)))
+    raise KeyError(name)
