@@ -183,6 +183,18 @@ esd_status esd_project(const esd_plan* plan, const double* u_nodal_dev, double* 
 esd_status esd_residual(const esd_plan* plan, const double* u_dev, double* dudt_dev,
                         void* ws_dev, void* stream);
 
+/* The same residual as esd_residual evaluated as a dense (multidimensional)
+ * SBP operator would: every volume node against every volume node (N_q^2
+ * two-point fluxes per element, eq. flux_differencing with dense S^l) and
+ * against every facet node (N_q N_f N_qf, eq. facet_correction with dense
+ * R^T B), the coefficients being those of the tensor-product operators (zero
+ * off their collapsed-coordinate lines).  Measures the O(p^{2d}) formulation
+ * against the O(p^{d+1}) line-based one of esd_residual on the same nodes
+ * (Sec. 5.1, 5.3).  Single-degree plans only (ESD_EUNSUPPORTED otherwise);
+ * arguments and errors as esd_residual. */
+esd_status esd_residual_dense(const esd_plan* plan, const double* u_dev, double* dudt_dev, void* ws_dev,
+                              void* stream);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid allocation): the same
  * residual as esd_residual, with its workspace taken from a library-owned
@@ -239,8 +251,10 @@ esd_status esd_plan_get_tuning(const esd_plan* plan, int32_t* k2_block, int32_t 
  * facet_correction, num_flux and dudt_modal exactly, including the interface
  * coupling to the neighbours):
  *   grad_dev = (d du~/dt / d u~)^T vbar_dev,  all [element][variable][mode].
- * The derivative of the wave speed takes the branch the forward takes (ties go
- * to the interior side; |x| has derivative 0 at 0).  grad_dev must not overlap
+ * The wave speed of eq. (wave_speed) is a max, not differentiable where its
+ * arguments agree: where they agree to 1e-10 relative (a tie up to rounding)
+ * the derivative is the mean of the two one-sided derivatives, elsewhere that
+ * of the larger argument (|x| has derivative 0 at 0).  grad_dev must not overlap
  * u_dev or vbar_dev; ws_dev holds info.vjp_workspace_bytes (256-byte aligned).
  * Errors: ESD_EINVAL, ESD_EUNSUPPORTED (degree not built, or facet nodes not
  * paired both ways), ESD_EHIP; inadmissible states set the sticky flag. */

@@ -83,6 +83,7 @@ EXPORTS = {
     "esd_project": (_c, [_vp, _vp, _vp, _vp]),
     "esd_residual": (_c, [_vp, _vp, _vp, _vp, _vp]),
     "esd_residual_noalloc": (_c, [_vp, _vp, _vp, _vp]),
+    "esd_residual_dense": (_c, [_vp, _vp, _vp, _vp, _vp]),
     "esd_rk4": (_c, [_vp, _vp, ctypes.c_double, ctypes.c_int32, _vp, _vp, _vp]),
     "esd_residual_vjp": (_c, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "esd_rk4_vjp": (_c, [_vp, _vp, ctypes.c_double, ctypes.c_int32, _vp, _vp, _vp]),
@@ -218,6 +219,17 @@ class Plan:
         if out is None:
             out = torch.empty_like(u)
         _check(_lib.esd_residual(self._h, _ptr(u), _ptr(out), _ptr(self.workspace()), _stream()), "esd_residual")
+        return out
+
+    def residual_dense(self, u, out=None):
+        """esd_residual_dense: the residual with all-pairs volume and facet loops."""
+        import torch
+        assert u.is_cuda and u.dtype == torch.float64 and u.is_contiguous()
+        assert tuple(u.shape) == self.state_shape
+        if out is None:
+            out = torch.empty_like(u)
+        _check(_lib.esd_residual_dense(self._h, _ptr(u), _ptr(out), _ptr(self.workspace()), _stream()),
+               "esd_residual_dense")
         return out
 
     def residual_noalloc(self, u, out):

@@ -700,6 +700,19 @@ esd_status esd_residual(const esd_plan* P, const double* u_dev, double* dudt_dev
   return ESD_OK;
 }
 
+esd_status esd_residual_dense(const esd_plan* P, const double* u_dev, double* dudt_dev, void* ws_dev, void* stream) {
+  esd_status st = check_device(P);
+  if (st != ESD_OK) return st;
+  if (P->batched) return fail(ESD_EUNSUPPORTED, "the all-pairs residual takes single-degree plans");
+  if (!u_dev || !dudt_dev || !ws_dev) return fail(ESD_EINVAL, "NULL buffer");
+  if ((const void*)u_dev == (const void*)dudt_dev) return fail(ESD_EINVAL, "u and dudt overlap");
+  if (((uintptr_t)ws_dev) % 256 != 0) return fail(ESD_EINVAL, "workspace not 256-byte aligned");
+  const int rc = esd::launch_residual_dense(P, u_dev, dudt_dev, split_ws(P, ws_dev), (hipStream_t)stream);
+  if (rc < 0) return fail(ESD_EUNSUPPORTED, "degree not built");
+  if (rc != 0) return fail(ESD_EHIP, std::string("launch failed: ") + hipGetErrorString((hipError_t)rc));
+  return ESD_OK;
+}
+
 esd_status esd_residual_noalloc(const esd_plan* P, const double* u_dev, double* dudt_dev, void* stream) {
   esd_status st = check_device(P);
   if (st != ESD_OK) return st;

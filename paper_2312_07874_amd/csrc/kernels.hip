@@ -116,12 +116,14 @@ k_entropy_projection(const double* __restrict__ u, double* __restrict__ wt, doub
   constexpr int NC = Sh::NC, NQ = Sh::NQ, NP = Sh::NP, NGV = Sh::NGV;
   __shared__ double sM[EPB * NC * NP];
   __shared__ double sA[EPB * NC * NQ];
-  __shared__ double sS[EPB * Sh::SCR];
-  constexpr int KB = 8 * EPB * (NC * NP + NC * NQ + Sh::SCR);
-  // the composed V V^T table only where it keeps the workgroups per CU
-  constexpr unsigned TM = tab_keeps_wgs<DIM, P, TAB_PSI | TAB_FACET, TAB_PSI | TAB_FACET | TAB_PSIM>(KB, wave_cap<DIM, P>())
-                              ? (TAB_PSI | TAB_FACET | TAB_PSIM)
-                              : tab_mask<DIM, P, TAB_PSI | TAB_FACET>(KB);
+  __shared__ double sS[EPB * Sh::XSCR];
+  constexpr int KB = 8 * EPB * (NC * NP + NC * NQ + Sh::XSCR);
+  // the composed V V^T table only where it keeps the workgroups per CU; where
+  // the two PKD tables do not fit (tetrahedra at p = 10), psi2 alone
+  constexpr unsigned TM0 = tab_keeps_wgs<DIM, P, TAB_PSI | TAB_FACET, TAB_PSI | TAB_FACET | TAB_PSIM>(KB, wave_cap<DIM, P>())
+                               ? (TAB_PSI | TAB_FACET | TAB_PSIM)
+                               : tab_mask<DIM, P, TAB_PSI | TAB_FACET>(KB);
+  constexpr unsigned TM = TM0 != 0 ? TM0 : (DIM == 3 ? tab_mask<DIM, P, TAB_PSI2>(KB) : 0u);
   constexpr bool VVT = (TM & TAB_PSIM) != 0;
   __shared__ double sTab[TM ? TabLds<DIM, P, TM>::SIZE : 1];
   const DevTables T = stage_tables<DIM, P, TM>(T0, sTab);
@@ -214,7 +216,7 @@ __device__ __forceinline__ void facet_task(const Node<DIM>& Vi, const double* gn
                                            const double* __restrict__ gf, int j, double coef, const Scheme& S,
                                            double* racc) {
   constexpr int NC = DIM + 2, NFQ = Shape<DIM, P>::NFQ;
-  const Node<DIM> Fj = load_node<DIM>(sF, NFQ, j);
+  const Node<DIM> Fj = load_facet_node<DIM>(sF, NFQ, j);
   double n[DIM];
 #pragma unroll
   for (int i = 0; i < DIM; ++i) n[i] = 0.5 * (gn_i[i] + gf[i * NFQ + j]);
@@ -228,9 +230,96 @@ __device__ __forceinline__ void facet_task(const Node<DIM>& Vi, const double* gn
   }
 }
 
+// ------------------------------------------------------------------ K2, all-pairs variant
+// The multidimensional-style evaluation of the same two terms, as an operator
+// without line structure performs them: every volume node i evaluates the
+// two-point flux with every volume node j (N_q^2 evaluations per element,
+// eq. flux_differencing with dense S^l) and with every facet node of every
+// facet (N_q N_f N_qf evaluations, eq. facet_correction with dense R^T B),
+// the coefficient being zero where the tensor-product operators have no entry
+// (the flux is still evaluated: a dense operator knows no zeros).  r_i is
+// owned by node i's task (each ordered pair evaluated, as the dense sum runs);
+// C^T 1 accumulates through LDS atomics.  Used to measure the cost of the
+// dense formulation on the same nodes against the line-based one.
+template <int DIM, int P, int FLUX>
+__device__ __forceinline__ void dense_volume_task(const double* sN, const double* __restrict__ g, double* racc, int i,
+                                                  const DevTables& T, const Scheme& S) {
+  using Sh = Shape<DIM, P>;
+  constexpr int Q = Sh::Q, NQ = Sh::NQ, NC = Sh::NC;
+  const Node<DIM> Ni = load_node<DIM>(sN, NQ, i);
+  const int i1 = i % Q, i2 = (i / Q) % Q, i3 = DIM == 3 ? i / (Q * Q) : 0;
+  for (int j = 0; j < NQ; ++j) {
+    const int j1 = j % Q, j2 = (j / Q) % Q, j3 = DIM == 3 ? j / (Q * Q) : 0;
+    double n[DIM];
+#pragma unroll
+    for (int m = 0; m < DIM; ++m) n[m] = 0.0;
+    // the line family the pair shares, if any (i == j shares all: coefficient 0)
+    int a = 0, b = 0, t0 = -1, t1 = -1, hc0 = 0, hc1 = 0;
+    if (DIM == 2) {
+      if (j2 == i2) { a = i1; b = j1; t0 = 0; t1 = 1; hc0 = 0; hc1 = 2; }
+      else if (j1 == i1) { a = i2; b = j2; t0 = 2; hc0 = 4; }
+    } else {
+      if (j2 == i2 && j3 == i3) { a = i1; b = j1; t0 = 0; t1 = 1; hc0 = 0; hc1 = 3; }
+      else if (j1 == i1 && j3 == i3) { a = i2; b = j2; t0 = 2; t1 = 3; hc0 = 6; hc1 = 9; }
+      else if (j1 == i1 && j2 == i2) { a = i3; b = j3; t0 = 4; hc0 = 12; }
+    }
+    if (t0 >= 0 && i != j) {
+      const double c0 = T.A[t0 * Q * Q + a * Q + b];
+#pragma unroll
+      for (int m = 0; m < DIM; ++m) n[m] = c0 * (g[(hc0 + m) * NQ + i] + g[(hc0 + m) * NQ + j]);
+      if (t1 >= 0) {
+        const double c1 = T.A[t1 * Q * Q + a * Q + b];
+#pragma unroll
+        for (int m = 0; m < DIM; ++m) n[m] += c1 * (g[(hc1 + m) * NQ + i] + g[(hc1 + m) * NQ + j]);
+      }
+    }
+    const Node<DIM> Nj = load_node<DIM>(sN, NQ, j);
+    double F[NC];
+    ec_flux<DIM, FLUX>(Ni, Nj, n, S.gm1_inv, F);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) racc[c] -= F[c];
+  }
+}
+
+// node i against every facet node: gn[z] is G(xi_i)^T nhat of facet z
+template <int DIM, int P, int FLUX>
+__device__ __forceinline__ void dense_facet_task(const Node<DIM>& Vi, const double (*gn)[DIM], const double* sF,
+                                                 double* sT, const double* __restrict__ gf, int i, const DevTables& T,
+                                                 const Scheme& S, double* racc) {
+  using Sh = Shape<DIM, P>;
+  constexpr int Q = Sh::Q, NQF = Sh::NQF, NFQ = Sh::NFQ, NC = Sh::NC;
+  const int i1 = i % Q, i2 = (i / Q) % Q, i3 = DIM == 3 ? i / (Q * Q) : 0;
+  for (int j = 0; j < NFQ; ++j) {
+    const int z = j / NQF, jj = j % NQF;
+    double coef = 0.0;
+    if (DIM == 2) {
+      if (z == 1 && jj == i2) coef = T.lgp1[i1] * T.wf[j];
+      else if (z == 2 && jj == i2) coef = T.lgm1[i1] * T.wf[j];
+      else if (z == 0 && jj == i1) coef = T.lgm1[i2] * T.wf[j];
+    } else {
+      if (z == 1 && jj == i2 + Q * i3) coef = T.lgp1[i1] * T.wf[j];
+      else if (z == 2 && jj == i2 + Q * i3) coef = T.lgm1[i1] * T.wf[j];
+      else if (z == 0 && jj == i1 + Q * i3) coef = T.lgm1[i2] * T.wf[j];
+      else if (z == 3 && jj % Q == i1) coef = T.gjm1[i3] * T.I42[(jj / Q) * Q + i2] * T.wf[j];
+    }
+    const Node<DIM> Fj = load_facet_node<DIM>(sF, NFQ, j);
+    double n[DIM];
+#pragma unroll
+    for (int m = 0; m < DIM; ++m) n[m] = 0.5 * (gn[z][m] + gf[m * NFQ + j]);
+    double F[NC];
+    ec_flux<DIM, FLUX>(Vi, Fj, n, S.gm1_inv, F);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const double C = coef * F[c];
+      racc[c] -= C;
+      atomicAdd(&sT[c * NFQ + j], -C);
+    }
+  }
+}
+
 // ------------------------------------------------------------------ K2: right-hand side
-template <int DIM, int P, int FLUX, bool NEXT>
-__global__ void __launch_bounds__((Launch<DIM, P>::BSMAX))
+template <int DIM, int P, int FLUX, bool NEXT, bool DENSE = false>
+__global__ void __launch_bounds__((Launch<DIM, P>::BSMAX), (Launch<DIM, P>::K2_MINW))
 k_rhs(const double* __restrict__ wt, const double* __restrict__ wfb, double* __restrict__ dudt,
       const double* __restrict__ gvol, const double* __restrict__ gfac, const int32_t* __restrict__ conn,
       DevTables T0, Scheme S, int64_t ne, int* flag, double* frec, RkEpilogue epi) {
@@ -241,9 +330,11 @@ k_rhs(const double* __restrict__ wt, const double* __restrict__ wfb, double* __r
   // own facet node records live in LDS when everything fits, else in this
   // element's slice of the workspace (frec, [e][8][NFQ]; read through the caches)
   constexpr bool FLDS = Sh::K2_FACET_LDS;
+  // facet record slots per node (7 used; triangles keep 8 for the modal staging at high degree)
+  constexpr int FRA = DIM == 3 ? FREC : 8;
   __shared__ double sN[EPB * Sh::SCR];      // node data [el][8][NQ]; transform scratch
   __shared__ double sR[EPB * NC * NQ];      // w at nodes, then r
-  __shared__ double sF[FLDS ? EPB * 8 * NFQ : 1];   // own facet node records (LDS case)
+  __shared__ double sF[FLDS ? EPB * FRA * NFQ : 1];   // own facet node records (LDS case)
   __shared__ double sT[EPB * NC * NFQ];     // C^T 1, then s = B J_f f* - C^T 1
   // operator tables in LDS: tetrahedra keep them in the tail of sF beyond the
   // modal staging, free during both transform phases (copied again once the
@@ -254,8 +345,8 @@ k_rhs(const double* __restrict__ wt, const double* __restrict__ wfb, double* __r
   // records, read their tables from T0.
   constexpr unsigned W0 = NEXT ? (TAB_PSI | TAB_FACET) : TAB_PSI;
   constexpr unsigned W1 = W0 | TAB_PSIM;   // with the composed stage of V V^T
-  constexpr int ROOM = (DIM == 3 && FLDS) ? 8 * NFQ - NC * NP : -1;   // doubles free in sF's tail
-  constexpr int KB = 8 * (EPB * (Sh::SCR + NC * NQ + NC * NFQ) + (FLDS ? EPB * 8 * NFQ : 1));
+  constexpr int ROOM = (DIM == 3 && FLDS) ? FRA * NFQ - NC * NP : -1;   // doubles free in sF's tail
+  constexpr int KB = 8 * (EPB * (Sh::SCR + NC * NQ + NC * NFQ) + (FLDS ? EPB * FRA * NFQ : 1));
   constexpr unsigned TM =
       DIM == 2 ? (tab_keeps_wgs<DIM, P, W0, W1>(KB, wave_cap<DIM, P>()) ? W1 : tab_mask<DIM, P, W0>(KB))
                : (TabLds<DIM, P, W1>::SIZE <= ROOM   ? W1
@@ -267,14 +358,14 @@ k_rhs(const double* __restrict__ wt, const double* __restrict__ wfb, double* __r
   __shared__ double sTab[DIM == 2 && TM ? TabLds<DIM, P, TM>::SIZE : 1];
   double* const tab_buf = TAB_SF ? sF + NC * NP : sTab;
   const DevTables T = stage_tables<DIM, P, TM>(T0, tab_buf);
-  static_assert(FLDS ? 8 * NFQ >= NC * NP : NFQ >= NP, "modal staging must fit the facet buffers");
+  static_assert(FLDS ? FRA * NFQ >= NC * NP : NFQ >= NP, "modal staging must fit the facet buffers");
   // modal w~ before the facet data exist, du~/dt after they are dead
   double* sM = FLDS ? sF : sT;
   double* lift_scratch = FLDS ? sF : sN;
   const int64_t e0 = (int64_t)blockIdx.x * EPB;
   const int nel = (int)((ne - e0) < EPB ? (ne - e0) : EPB);
   const int nec = nel * NC;
-  double* fr = FLDS ? sF : frec + e0 * 8 * NFQ;
+  double* fr = FLDS ? sF : frec + e0 * FRA * NFQ;
   const int tid = threadIdx.x, nth = blockDim.x;
   double* T1 = sN;
   double* T2 = sN + EPB * Sh::T1;
@@ -314,7 +405,7 @@ k_rhs(const double* __restrict__ wt, const double* __restrict__ wfb, double* __r
     Node<DIM> Um, Up;
     bad |= !from_entropy<DIM>(w, S.gamma, S.gm1_inv, Um);
     bad |= !from_entropy<DIM>(wn, S.gamma, S.gm1_inv, Up);
-    store_node<DIM>(fr + el * 8 * NFQ, NFQ, j, Um);
+    store_facet_node<DIM>(fr + el * FRA * NFQ, NFQ, j, Um);
     double F[NC];
     interface_flux<DIM, FLUX>(Um, Up, nJ, Jf, S.gamma, S.gm1_inv, S.dissipation, F);
     const double wj = T0.wf[j];
@@ -331,7 +422,17 @@ k_rhs(const double* __restrict__ wt, const double* __restrict__ wfb, double* __r
   //      registers, r_b through LDS atomics.
   for (int o = tid; o < nec * NQ; o += nth) sR[o] = 0.0;
   __syncthreads();
-  {
+  if constexpr (DENSE) {
+    for (int task = tid; task < nel * NQ; task += nth) {
+      const int el = task / NQ, i = task % NQ;
+      double racc[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) racc[c] = 0.0;
+      dense_volume_task<DIM, P, FLUX>(sN + el * Sh::SCR, gvol + (e0 + el) * NGV * NQ, racc, i, T0, S);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) sR[(el * NC + c) * NQ + i] += racc[c];
+    }
+  } else {
     constexpr int TPE = DIM * NQ;           // volume tasks per element
     for (int task = tid; task < nel * TPE; task += nth) {
       const int el = task / TPE, lt = task % TPE;
@@ -368,7 +469,7 @@ k_rhs(const double* __restrict__ wt, const double* __restrict__ wfb, double* __r
   for (int task = tid; task < nel * NQ; task += nth) {
     const int el = task / NQ, t = task % NQ;
     const double* sNe = sN + el * Sh::SCR;
-    const double* sFe = fr + el * 8 * NFQ;
+    const double* sFe = fr + el * FRA * NFQ;
     double* sTe = sT + el * NC * NFQ;
     const double* g = gvol + (e0 + el) * NGV * NQ;
     const double* gf = gfac + (e0 + el) * (DIM + 1) * NFQ;
@@ -390,9 +491,14 @@ k_rhs(const double* __restrict__ wt, const double* __restrict__ wfb, double* __r
         gB[m] = -g1;                                     // facet 3: nhat = (-1, 0)
         gC[m] = -2.0 * g[(4 + m) * NQ + i] / w1;         // facet 1: nhat = (0, -1)
       }
-      facet_task<DIM, P, FLUX>(Vi, gA, sFe, sTe, gf, 1 * NQF + b2, T0.lgp1[b1] * T0.wf[1 * NQF + b2], S, racc);
-      facet_task<DIM, P, FLUX>(Vi, gB, sFe, sTe, gf, 2 * NQF + b2, T0.lgm1[b1] * T0.wf[2 * NQF + b2], S, racc);
-      facet_task<DIM, P, FLUX>(Vi, gC, sFe, sTe, gf, 0 * NQF + b1, T0.lgm1[b2] * T0.wf[0 * NQF + b1], S, racc);
+      if constexpr (DENSE) {
+        const double gn[3][2] = {{gC[0], gC[1]}, {gA[0], gA[1]}, {gB[0], gB[1]}};
+        dense_facet_task<DIM, P, FLUX>(Vi, gn, sFe, sTe, gf, i, T0, S, racc);
+      } else {
+        facet_task<DIM, P, FLUX>(Vi, gA, sFe, sTe, gf, 1 * NQF + b2, T0.lgp1[b1] * T0.wf[1 * NQF + b2], S, racc);
+        facet_task<DIM, P, FLUX>(Vi, gB, sFe, sTe, gf, 2 * NQF + b2, T0.lgm1[b1] * T0.wf[2 * NQF + b2], S, racc);
+        facet_task<DIM, P, FLUX>(Vi, gC, sFe, sTe, gf, 0 * NQF + b1, T0.lgm1[b2] * T0.wf[0 * NQF + b1], S, racc);
+      }
     } else {
       const int b3 = t % Q, b2 = (t / Q) % Q, b1 = t / (Q * Q);
       i = b1 + Q * (b2 + Q * b3);
@@ -410,18 +516,24 @@ k_rhs(const double* __restrict__ wt, const double* __restrict__ wfb, double* __r
         gC[m] = -4.0 * g[(6 + m) * NQ + i] * inv13;      // facet 1: nhat = (0,-1,0)
         gD[m] = -8.0 * g[(12 + m) * NQ + i] * inv12;     // facet 4: nhat = (0,0,-1)
       }
-      const int j23 = b2 + Q * b3;
-      facet_task<DIM, P, FLUX>(Vi, gA, sFe, sTe, gf, 1 * NQF + j23, T0.lgp1[b1] * T0.wf[1 * NQF + j23], S, racc);
-      facet_task<DIM, P, FLUX>(Vi, gB, sFe, sTe, gf, 2 * NQF + j23, T0.lgm1[b1] * T0.wf[2 * NQF + j23], S, racc);
-      const int j13 = b1 + Q * b3;
-      facet_task<DIM, P, FLUX>(Vi, gC, sFe, sTe, gf, 0 * NQF + j13, T0.lgm1[b2] * T0.wf[0 * NQF + j13], S, racc);
-      const double cz = T0.gjm1[b3];
+      if constexpr (DENSE) {
+        const double gn[4][3] = {{gC[0], gC[1], gC[2]}, {gA[0], gA[1], gA[2]}, {gB[0], gB[1], gB[2]},
+                                 {gD[0], gD[1], gD[2]}};
+        dense_facet_task<DIM, P, FLUX>(Vi, gn, sFe, sTe, gf, i, T0, S, racc);
+      } else {
+        const int j23 = b2 + Q * b3;
+        facet_task<DIM, P, FLUX>(Vi, gA, sFe, sTe, gf, 1 * NQF + j23, T0.lgp1[b1] * T0.wf[1 * NQF + j23], S, racc);
+        facet_task<DIM, P, FLUX>(Vi, gB, sFe, sTe, gf, 2 * NQF + j23, T0.lgm1[b1] * T0.wf[2 * NQF + j23], S, racc);
+        const int j13 = b1 + Q * b3;
+        facet_task<DIM, P, FLUX>(Vi, gC, sFe, sTe, gf, 0 * NQF + j13, T0.lgm1[b2] * T0.wf[0 * NQF + j13], S, racc);
+        const double cz = T0.gjm1[b3];
 #pragma unroll
-      for (int m = 0; m < Q; ++m) {
-        int a2 = m + b2 + b3;                 // rotated so that neighbouring lanes hit different facet nodes
-        a2 = a2 % Q;
-        const int j = 3 * NQF + b1 + Q * a2;
-        facet_task<DIM, P, FLUX>(Vi, gD, sFe, sTe, gf, j, cz * T0.I42[a2 * Q + b2] * T0.wf[j], S, racc);
+        for (int m = 0; m < Q; ++m) {
+          int a2 = m + b2 + b3;                 // rotated so that neighbouring lanes hit different facet nodes
+          a2 = a2 % Q;
+          const int j = 3 * NQF + b1 + Q * a2;
+          facet_task<DIM, P, FLUX>(Vi, gD, sFe, sTe, gf, j, cz * T0.I42[a2 * Q + b2] * T0.wf[j], S, racc);
+        }
       }
     }
     double* r = sR + el * NC * NQ;
@@ -563,6 +675,39 @@ static int run_residual(const esd_plan* pl, const double* u, double* dudt, Works
   launch_k2<DIM, P>(pl, dudt, ws, s, epi, nb, bs);
   if (pl->timing) timing_event(pl, s);
   return (int)hipGetLastError();
+}
+
+// the all-pairs variant of the residual: K1, then K2 with dense volume and facet loops
+template <int DIM, int P>
+static int run_residual_dense(const esd_plan* pl, const double* u, double* dudt, Workspace ws, hipStream_t s) {
+  using L = Launch<DIM, P>;
+  const int64_t nb = (pl->ne + L::EPB - 1) / L::EPB;
+  if (pl->timing) timing_event(pl, s);
+  const int bs1 = pl->k1_block > 0 ? pl->k1_block : L::BS;
+  hipLaunchKernelGGL((k_entropy_projection<DIM, P, false>), dim3(nb), dim3(bs1), 0, s, u, ws.wt, ws.wf,
+                     pl->d_gvol, pl->tab, pl->scheme, pl->ne, pl->d_flag);
+  if (pl->timing) timing_event(pl, s);
+  const int bs = pl->k2_block > 0 ? pl->k2_block : L::BS;
+  const RkEpilogue epi;
+#define K2D_ARGS \
+  dim3(nb), dim3(bs), 0, s, ws.wt, ws.wf, dudt, pl->d_gvol, pl->d_gfac, pl->d_conn, pl->tab, pl->scheme, pl->ne, \
+      pl->d_flag, ws.frec, epi
+  if (pl->scheme.ecflux == FLUX_RANOCHA)
+    hipLaunchKernelGGL((k_rhs<DIM, P, FLUX_RANOCHA, false, true>), K2D_ARGS);
+  else
+    hipLaunchKernelGGL((k_rhs<DIM, P, FLUX_CHANDRASHEKAR, false, true>), K2D_ARGS);
+#undef K2D_ARGS
+  if (pl->timing) timing_event(pl, s);
+  return (int)hipGetLastError();
+}
+
+int launch_residual_dense(const esd_plan* pl, const double* u, double* dudt, Workspace ws, hipStream_t s) {
+#define X(D, PP) \
+  if (pl->dim == D && pl->p == PP) return run_residual_dense<D, PP>(pl, u, dudt, ws, s);
+  ESD_TRI_DEGREES(X)
+  ESD_TET_DEGREES(X)
+#undef X
+  return -1;
 }
 
 template <int DIM, int P>

@@ -146,6 +146,8 @@ namespace esd {
 int launch_residual(const esd_plan* P, const double* u, double* dudt, Workspace ws, hipStream_t s,
                     const RkEpilogue& epi = RkEpilogue());
 int launch_project(const esd_plan* P, const double* u_nodal, double* u, hipStream_t s);
+// the residual with all-pairs (dense-operator) volume and facet loops
+int launch_residual_dense(const esd_plan* P, const double* u, double* dudt, Workspace ws, hipStream_t s);
 int launch_axpy(double* y, const double* x, double a, const double* z, int64_t n, hipStream_t s);
 int launch_entropy_projection(const esd_plan* P, const double* u, Workspace ws, hipStream_t s);
 // adjoint.hip
