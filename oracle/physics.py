@@ -219,10 +219,92 @@ def davis_speed(um, up, n, gamma):
     return _max(a, b) + _max(cm, cp)
 
 
+def entropy_jacobian(rho, v, p, gamma):
+    """A0 = dU/dW, the (symmetric positive definite) Jacobian of the
+    conservative variables with respect to the entropy variables of
+    eq. (euler_entropy), at the primitive state (rho, v, p):
+        [[rho,   rho v^T,              E],
+         [rho v, rho v v^T + p I,      rho H v],
+         [E,     rho H v^T,            rho H^2 - a^2 p/(gamma-1)]]
+    with a^2 = gamma p/rho, H = a^2/(gamma-1) + |v|^2/2, E = p/(gamma-1) + rho |v|^2/2."""
+    d = v.shape[-1]
+    v2 = (v * v).sum(-1)
+    a2 = gamma * p / rho
+    H = a2 / (gamma - 1.0) + 0.5 * v2
+    E = p / (gamma - 1.0) + 0.5 * rho * v2
+    n = d + 2
+    A = torch.zeros(rho.shape + (n, n), dtype=rho.dtype)
+    A[..., 0, 0] = rho
+    A[..., 0, 1:1 + d] = rho[..., None] * v
+    A[..., 1:1 + d, 0] = rho[..., None] * v
+    A[..., 0, d + 1] = E
+    A[..., d + 1, 0] = E
+    A[..., 1:1 + d, 1:1 + d] = rho[..., None, None] * v[..., :, None] * v[..., None, :] \
+        + p[..., None, None] * torch.eye(d, dtype=rho.dtype)
+    A[..., 1:1 + d, d + 1] = (rho * H)[..., None] * v
+    A[..., d + 1, 1:1 + d] = (rho * H)[..., None] * v
+    A[..., d + 1, d + 1] = rho * H * H - a2 * p / (gamma - 1.0)
+    return A
+
+
+def abs_flux_jacobian_apply(rho, v, p, n, gamma, dU):
+    """|A_n| dU for the Euler flux Jacobian A_n = d(F . n)/dU (n a unit vector)
+    at the primitive state (rho, v, p): the acoustic waves of speeds
+    v.n -+ a with strengths alpha_-+ = (dp -+ rho a dv_n)/(2 a^2) along
+    r_-+ = (1, v -+ a n, H -+ a v.n), and the rest of dU (entropy and shear
+    waves) at speed v.n; dp and dv are the primitive jumps that dU stands for
+    at the state."""
+    d = v.shape[-1]
+    v2 = (v * v).sum(-1)
+    a = torch.sqrt(gamma * p / rho)
+    H = a * a / (gamma - 1.0) + 0.5 * v2
+    vn = (v * n).sum(-1)
+    drho = dU[..., 0]
+    dm = dU[..., 1:1 + d]
+    dE = dU[..., d + 1]
+    dv = (dm - v * drho[..., None]) / rho[..., None]
+    dp = (gamma - 1.0) * (dE - (v * dm).sum(-1) + 0.5 * v2 * drho)
+    dvn = (dv * n).sum(-1)
+    am = (dp - rho * a * dvn) / (2.0 * a * a)
+    ap = (dp + rho * a * dvn) / (2.0 * a * a)
+
+    def r(sign):
+        return torch.cat([torch.ones_like(rho)[..., None], v + sign * a[..., None] * n,
+                          (H + sign * a * vn)[..., None]], -1)
+
+    rm_, rp_ = r(-1.0), r(1.0)
+    rest = dU - am[..., None] * rm_ - ap[..., None] * rp_
+    return (vn.abs()[..., None] * rest + (vn - a).abs()[..., None] * am[..., None] * rm_
+            + (vn + a).abs()[..., None] * ap[..., None] * rp_)
+
+
+def _mean_state(um, up, gamma):
+    rm, vm, pm = prim(um, gamma)
+    rp, vp, pp = prim(up, gamma)
+    return 0.5 * (rm + rp), 0.5 * (vm + vp), 0.5 * (pm + pp)
+
+
 def interface_flux(um, up, n, gamma, ecflux: int, dissipation: int):
-    """f*(U-, U+, n) of eq. (num_flux) with unit normal n."""
+    """f*(U-, U+, n) of eq. (num_flux) with unit normal n.  dissipation:
+      0  none (entropy-conservative interface flux);
+      1  local Lax-Friedrichs with Davis' wave speed, - lambda/2 (u+ - u-);
+      2  scalar dissipation on the jump of the entropy variables,
+         - lambda/2 A0(u_mean) (w+ - w-), lambda Davis' wave speed;
+      3  matrix dissipation, - 1/2 |A_n(u_mean)| A0(u_mean) (w+ - w-).
+    The last two are the alternatives the paper names after eq. (num_flux);
+    A0 = dU/dW and |A_n| are symmetric positive semidefinite in product, so
+    both are entropy stable.  u_mean: arithmetic means of rho, v, p."""
     f = EC_FLUXES[ecflux](um, up, n, gamma)
-    if dissipation:
+    if dissipation == 1:
         lam = rn(davis_speed(um, up, n, gamma))
         f = rn(f - rn(0.5 * lam[..., None] * rn(up - um)))
+    elif dissipation in (2, 3):
+        dw = entropy_vars(up, gamma) - entropy_vars(um, gamma)
+        rho, v, p = _mean_state(um, up, gamma)
+        dU = (entropy_jacobian(rho, v, p, gamma) @ dw[..., None])[..., 0]
+        if dissipation == 2:
+            lam = davis_speed(um, up, n, gamma)
+            f = f - 0.5 * lam[..., None] * dU
+        else:
+            f = f - 0.5 * abs_flux_jacobian_apply(rho, v, p, n, gamma, dU)
     return f

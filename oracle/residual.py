@@ -297,3 +297,80 @@ def entropy_rate(prob: Problem, ut: torch.Tensor, dudt: torch.Tensor) -> torch.T
     Wu = ph.entropy_vars(u, prob.gamma)
     du = torch.einsum("ki,eci->ekc", V, dudt)
     return torch.einsum("k,ek,ekc,ekc->", w, prob.geo.J, Wu, du)
+
+
+# ---------------------------------------------------------------- alternative forms
+def _nodal_states(prob: Problem, ut: torch.Tensor, elems):
+    """u = V u~ at the volume nodes of elems, u^z = R^z u at their facet nodes
+    and the exterior states (the neighbours' facet values at the matched
+    nodes), without any entropy projection."""
+    ref, con = prob.ref, prob.con
+    elems, need = _neighbourhood(prob, elems)
+    idx_of = {int(e): i for i, e in enumerate(need)}
+    u_need = torch.einsum("ki,eci->ekc", ref.V, ut[torch.as_tensor(need)])
+    u = u_need[[idx_of[int(e)] for e in elems]]
+    own, ext = [], []
+    for z in range(ref.Nf):
+        own.append(torch.einsum("jk,ekc->ejc", ref.R[z], u))
+        nb, nz = con.nbr_elem[elems, z], con.nbr_face[elems, z]
+        wp = torch.stack([ref.R[int(nz[i])] @ u_need[idx_of[int(nb[i])]] for i in range(len(elems))])
+        perm = torch.as_tensor(con.node_map[elems, z])
+        ext.append(torch.gather(wp, 1, perm[:, :, None].expand(-1, -1, wp.shape[-1])))
+    return elems, u, own, ext
+
+
+def _cart_fluxes(u, g):
+    """[..., Nc, d]: the Cartesian Euler fluxes f_m(u)."""
+    d = u.shape[-1] - 2
+    return torch.stack([_cart_flux(u, m, g) for m in range(d)], -1)
+
+
+def residual_conservative(prob: Problem, ut: torch.Tensor, elems=None) -> torch.Tensor:
+    """du~/dt of the standard (conservative) weak form eq. (rhs_cons):
+    r = sum_l Q^lT sum_m G^(l,m) f^m - sum_z R^zT B^z J^z f*^z, with u = V u~
+    at the volume nodes and u^z = R^z u at the facet nodes (no entropy
+    projection), then the weight-adjusted inverse."""
+    ref, geo = prob.ref, prob.geo
+    d, g = ref.dim, prob.gamma
+    if elems is None:
+        elems = np.arange(prob.ne)
+    elems, u, own, ext = _nodal_states(prob, ut, elems)
+    f = _cart_fluxes(u, g)                                      # [nE, Nq, Nc, m]
+    G = geo.G[elems]                                            # [nE, Nq, l, m]
+    r = torch.zeros_like(u)
+    for l in range(d):
+        Gf = torch.einsum("eim,eicm->eic", G[:, :, l, :], f)
+        r = r + torch.einsum("ji,ejc->eic", ref.Q[l], Gf)
+    for z in range(ref.Nf):
+        fstar = ph.interface_flux(own[z], ext[z], geo.n[z][elems], g, prob.ecflux, prob.dissipation)
+        s = (ref.w_f[z][None, :, None] * geo.Jf[z][elems][..., None]) * fstar
+        r = r - torch.einsum("ji,ejc->eic", ref.R[z], s)
+    A = wadj_inverse(prob, torch.as_tensor(elems))
+    return torch.einsum("eij,ecj->eci", A, torch.einsum("ki,ekc->eci", ref.V, r))
+
+
+def residual_skew(prob: Problem, ut: torch.Tensor, elems=None) -> torch.Tensor:
+    """du~/dt of the skew-symmetric weak form eq. (rhs_skew):
+    r = 1/2 sum_l (Q^lT sum_m G^(l,m) f^m - sum_m G^(l,m) Q^l f^m)
+        - sum_z R^zT B^z J^z (f*^z - 1/2 sum_m N^(z,m) R^z f^m),
+    u = V u~ at the volume nodes, u^z = R^z u (no entropy projection)."""
+    ref, geo = prob.ref, prob.geo
+    d, g = ref.dim, prob.gamma
+    if elems is None:
+        elems = np.arange(prob.ne)
+    elems, u, own, ext = _nodal_states(prob, ut, elems)
+    f = _cart_fluxes(u, g)                                      # [nE, Nq, Nc, m]
+    G = geo.G[elems]
+    r = torch.zeros_like(u)
+    for l in range(d):
+        Gf = torch.einsum("eim,eicm->eic", G[:, :, l, :], f)
+        Qf = torch.einsum("ij,ejcm->eicm", ref.Q[l], f)
+        r = r + 0.5 * (torch.einsum("ji,ejc->eic", ref.Q[l], Gf) - torch.einsum("eim,eicm->eic", G[:, :, l, :], Qf))
+    for z in range(ref.Nf):
+        fstar = ph.interface_flux(own[z], ext[z], geo.n[z][elems], g, prob.ecflux, prob.dissipation)
+        Rf = torch.einsum("jk,ekcm->ejcm", ref.R[z], f)
+        Nf = torch.einsum("ejm,ejcm->ejc", geo.n[z][elems], Rf)
+        s = (ref.w_f[z][None, :, None] * geo.Jf[z][elems][..., None]) * (fstar - 0.5 * Nf)
+        r = r - torch.einsum("ji,ejc->eic", ref.R[z], s)
+    A = wadj_inverse(prob, torch.as_tensor(elems))
+    return torch.einsum("eij,ecj->eci", A, torch.einsum("ki,ekc->eci", ref.V, r))
