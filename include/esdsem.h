@@ -63,7 +63,12 @@ typedef enum {
 /* Interface dissipation of eq. (num_flux). */
 typedef enum {
   ESD_DISS_NONE = 0,          /* entropy-conservative interface flux (Sec. 7.2)  */
-  ESD_DISS_LLF_DAVIS = 1      /* local Lax-Friedrichs with eq. (wave_speed)      */
+  ESD_DISS_LLF_DAVIS = 1,     /* local Lax-Friedrichs with eq. (wave_speed)      */
+  /* the entropy-stable alternatives named after eq. (num_flux), both on the
+   * jump of the entropy variables, A0 = dU/dW at the arithmetic-mean state
+   * (rho, v, p); forward only (the VJP entry points return ESD_EUNSUPPORTED): */
+  ESD_DISS_ENTROPY_JUMP = 2,  /* scalar: lambda/2 A0 (w+ - w-), lambda of eq. (wave_speed) */
+  ESD_DISS_MATRIX = 3         /* matrix: 1/2 |A_n| A0 (w+ - w-), |A_n| the absolute Euler flux Jacobian */
 } esd_dissipation;
 
 /* Maps n points x_in [n][dim] (physical, unwarped) to x_out [n][dim].  Called

@@ -30,7 +30,7 @@ STATUS = {0: "ESD_OK", -1: "ESD_EINVAL", -2: "ESD_EJACOBIAN", -3: "ESD_EADMISSIB
           -5: "ESD_ENONCONFORMING", -6: "ESD_EHIP", -7: "ESD_ENOMEM"}
 
 FLUX_RANOCHA, FLUX_CHANDRASHEKAR = 0, 1
-DISS_NONE, DISS_LLF_DAVIS = 0, 1
+DISS_NONE, DISS_LLF_DAVIS, DISS_ENTROPY_JUMP, DISS_MATRIX = 0, 1, 2, 3
 
 WARP_FN = ctypes.CFUNCTYPE(None, ctypes.c_int64, ctypes.POINTER(ctypes.c_double),
                            ctypes.POINTER(ctypes.c_double), ctypes.c_void_p)

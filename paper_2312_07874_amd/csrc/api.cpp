@@ -112,7 +112,7 @@ esd_status create_single(const esd_mesh_desc* mesh, const esd_scheme_desc* schem
   if (mesh->n_elements <= 0 || !mesh->elem_vertex_ids || !mesh->elem_vertex_coords)
     return fail(ESD_EINVAL, "empty mesh");
   if (!(scheme->gamma > 1.0) || scheme->ecflux < 0 || scheme->ecflux > 1 || scheme->dissipation < 0 ||
-      scheme->dissipation > 1)
+      scheme->dissipation > 3)
     return fail(ESD_EINVAL, "bad scheme parameters");
   esd_plan* P = new (std::nothrow) esd_plan();
   if (!P) return fail(ESD_ENOMEM, "host allocation failed");
@@ -254,7 +254,7 @@ esd_status esd_plan_create_batched(const esd_batch_desc* d, const esd_scheme_des
     return fail(ESD_EINVAL, "bad batch description");
   if (d->dim != 2 && d->dim != 3) return fail(ESD_EUNSUPPORTED, "dim must be 2 or 3");
   if (!(scheme->gamma > 1.0) || scheme->ecflux < 0 || scheme->ecflux > 1 || scheme->dissipation < 0 ||
-      scheme->dissipation > 1)
+      scheme->dissipation > 3)
     return fail(ESD_EINVAL, "bad scheme parameters");
   const int dim = d->dim, nv = dim + 1, NF = dim + 1, nc = dim + 2;
   const bool host_only = (flags & 1u) != 0;
@@ -1050,6 +1050,8 @@ esd_status esd_residual_vjp(const esd_plan* P, const double* u_dev, const double
     return fail(ESD_EINVAL, "grad overlaps u or vbar");
   if (((uintptr_t)ws_dev) % 256 != 0) return fail(ESD_EINVAL, "workspace not 256-byte aligned");
   if (P->batched) return fail(ESD_EUNSUPPORTED, "VJP of a batched plan");
+  if (P->scheme.dissipation > 1)
+    return fail(ESD_EUNSUPPORTED, "VJP built for the entropy-conservative and Lax-Friedrichs interface fluxes");
   if (!P->conn_involutive) return fail(ESD_EUNSUPPORTED, "facet permutation is not an involution");
   if (!esd::vjp_degree_supported(P->dim, P->p)) return fail(ESD_EUNSUPPORTED, "VJP not built for this degree");
   const int rc = esd::launch_vjp(P, u_dev, vbar_dev, grad_dev, split_ws(P, ws_dev), (hipStream_t)stream);
@@ -1065,6 +1067,8 @@ esd_status esd_rk4_vjp(const esd_plan* P, const double* stage_ckpt_dev, double d
   if (!stage_ckpt_dev || !ubar_dev || !ws_dev || nsteps < 0 || !std::isfinite(dt))
     return fail(ESD_EINVAL, "bad argument");
   if (((uintptr_t)ws_dev) % 256 != 0) return fail(ESD_EINVAL, "workspace not 256-byte aligned");
+  if (P->scheme.dissipation > 1)
+    return fail(ESD_EUNSUPPORTED, "VJP built for the entropy-conservative and Lax-Friedrichs interface fluxes");
   if (P->batched) return fail(ESD_EUNSUPPORTED, "VJP of a batched plan");
   if (!P->conn_involutive) return fail(ESD_EUNSUPPORTED, "facet permutation is not an involution");
   if (!esd::vjp_degree_supported(P->dim, P->p)) return fail(ESD_EUNSUPPORTED, "VJP not built for this degree");

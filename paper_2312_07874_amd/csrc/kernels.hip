@@ -407,7 +407,7 @@ k_rhs(const double* __restrict__ wt, const double* __restrict__ wfb, double* __r
     bad |= !from_entropy<DIM>(wn, S.gamma, S.gm1_inv, Up);
     store_facet_node<DIM>(fr + el * FRA * NFQ, NFQ, j, Um);
     double F[NC];
-    interface_flux<DIM, FLUX>(Um, Up, nJ, Jf, S.gamma, S.gm1_inv, S.dissipation, F);
+    interface_flux<DIM, FLUX>(Um, Up, nJ, Jf, S.gamma, S.gm1_inv, S.dissipation, F, w, wn);
     const double wj = T0.wf[j];
 #pragma unroll
     for (int c = 0; c < NC; ++c) sT[(el * NC + c) * NFQ + j] = wj * F[c];

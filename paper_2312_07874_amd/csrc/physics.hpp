@@ -330,13 +330,91 @@ ESD_HD void tie_weights(double a, double b, double& wa, double& wb) {
   }
 }
 
-// J_f f*(U-, U+, n) with nJ = J_f n:  f#(U-, U+, nJ) - (J_f lambda)/2 (U+ - U-),
-// J_f lambda = max(|v-.nJ|, |v+.nJ|) + J_f max(c-, c+)
+// dU = A0 dw, A0 = dU/dW at the primitive state (rho, v, p) (symmetric positive definite):
+//   [[rho, rho v^T, E], [rho v, rho v v^T + p I, rho H v], [E, rho H v^T, rho H^2 - a^2 p/(gamma-1)]]
+template <int DIM>
+ESD_HD void entropy_jacobian_apply(double rho, const double* v, double p, double gamma, double gm1_inv,
+                                   const double* dw, double* dU) {
+  double v2 = 0.0, vdw = 0.0;
+  for (int i = 0; i < DIM; ++i) {
+    v2 += v[i] * v[i];
+    vdw += v[i] * dw[1 + i];
+  }
+  const double a2 = gamma * p * frcp(rho);
+  const double H = a2 * gm1_inv + 0.5 * v2, E = p * gm1_inv + 0.5 * rho * v2;
+  const double w0 = dw[0], wl = dw[DIM + 1];
+  dU[0] = rho * w0 + rho * vdw + E * wl;
+  for (int i = 0; i < DIM; ++i) dU[1 + i] = rho * v[i] * (w0 + vdw) + p * dw[1 + i] + rho * H * v[i] * wl;
+  dU[DIM + 1] = E * w0 + rho * H * vdw + (rho * H * H - a2 * p * gm1_inv) * wl;
+}
+
+// |A_n| dU for the Euler flux Jacobian in the unit direction n at (rho, v, p):
+// acoustic waves of speeds v.n -+ a with strengths (dp -+ rho a dv_n)/(2 a^2)
+// along (1, v -+ a n, H -+ a v.n); the rest of dU at speed |v.n|
+template <int DIM>
+ESD_HD void abs_jacobian_apply(double rho, const double* v, double p, const double* n, double gamma,
+                               double gm1_inv, const double* dU, double* out) {
+  double v2 = 0.0, vn = 0.0, vdm = 0.0, dvn = 0.0;
+  const double ir = frcp(rho);
+  for (int i = 0; i < DIM; ++i) {
+    v2 += v[i] * v[i];
+    vn += v[i] * n[i];
+    vdm += v[i] * dU[1 + i];
+  }
+  const double a = sqrt(gamma * p * ir);
+  const double H = a * a * gm1_inv + 0.5 * v2;
+  const double dp = (gamma - 1.0) * (dU[DIM + 1] - vdm + 0.5 * v2 * dU[0]);
+  for (int i = 0; i < DIM; ++i) dvn += (dU[1 + i] - v[i] * dU[0]) * ir * n[i];
+  const double i2a2 = 0.5 * frcp(a * a);
+  const double am = (dp - rho * a * dvn) * i2a2, ap = (dp + rho * a * dvn) * i2a2;
+  const double l0 = fabs(vn), lm = fabs(vn - a), lp = fabs(vn + a);
+  // rest = dU - am r- - ap r+ goes at |v.n|
+  out[0] = l0 * (dU[0] - am - ap) + lm * am + lp * ap;
+  for (int i = 0; i < DIM; ++i) {
+    const double rm = v[i] - a * n[i], rp = v[i] + a * n[i];
+    out[1 + i] = l0 * (dU[1 + i] - am * rm - ap * rp) + lm * am * rm + lp * ap * rp;
+  }
+  const double hm = H - a * vn, hp = H + a * vn;
+  out[DIM + 1] = l0 * (dU[DIM + 1] - am * hm - ap * hp) + lm * am * hm + lp * ap * hp;
+}
+
+// J_f f*(U-, U+, n) with nJ = J_f n:  f#(U-, U+, nJ) minus the dissipation:
+//   1  (J_f lambda)/2 (U+ - U-), J_f lambda = max(|v-.nJ|, |v+.nJ|) + J_f max(c-, c+);
+//   2  (J_f lambda)/2 A0(mean) (w+ - w-)  (scalar dissipation on the entropy-variable jump);
+//   3  J_f/2 |A_n(mean)| A0(mean) (w+ - w-)  (matrix dissipation);
+// mean: arithmetic means of rho, v, p; wm, wp: the entropy variables of U-, U+
+// (needed by 2 and 3)
 template <int DIM, int FLUX>
 ESD_HD void interface_flux(const Node<DIM>& Um, const Node<DIM>& Up, const double* nJ, double Jf, double gamma,
-                           double gm1_inv, int dissipation, double* F) {
+                           double gm1_inv, int dissipation, double* F, const double* wm = nullptr,
+                           const double* wp = nullptr) {
   ec_flux<DIM, FLUX>(Um, Up, nJ, gm1_inv, F);
   if (!dissipation) return;
+  if (dissipation >= 2) {
+    double dw[DIM + 2], dU[DIM + 2], vbar[DIM];
+    for (int c = 0; c < DIM + 2; ++c) dw[c] = wp[c] - wm[c];
+    for (int i = 0; i < DIM; ++i) vbar[i] = 0.5 * (Um.v[i] + Up.v[i]);
+    const double rbar = 0.5 * (Um.rho + Up.rho), pbar = 0.5 * (Um.p + Up.p);
+    entropy_jacobian_apply<DIM>(rbar, vbar, pbar, gamma, gm1_inv, dw, dU);
+    if (dissipation == 2) {
+      double vmn = 0.0, vpn = 0.0;
+      for (int i = 0; i < DIM; ++i) {
+        vmn += Um.v[i] * nJ[i];
+        vpn += Up.v[i] * nJ[i];
+      }
+      const double am = fabs(vmn), ap = fabs(vpn);
+      const double cm = sqrt(gamma * Um.p / Um.rho), cp = sqrt(gamma * Up.p / Up.rho);
+      const double h = 0.5 * ((am >= ap ? am : ap) + Jf * (cm >= cp ? cm : cp));
+      for (int c = 0; c < DIM + 2; ++c) F[c] -= h * dU[c];
+    } else {
+      double n[DIM], D[DIM + 2];
+      const double iJ = frcp(Jf);
+      for (int i = 0; i < DIM; ++i) n[i] = nJ[i] * iJ;
+      abs_jacobian_apply<DIM>(rbar, vbar, pbar, n, gamma, gm1_inv, dU, D);
+      for (int c = 0; c < DIM + 2; ++c) F[c] -= 0.5 * Jf * D[c];
+    }
+    return;
+  }
   double vmn = 0.0, vpn = 0.0, vm2 = 0.0, vp2 = 0.0;
   for (int i = 0; i < DIM; ++i) {
     vmn += Um.v[i] * nJ[i];

@@ -22,7 +22,7 @@ void flux_batch(int64_t m, const double* wa, const double* wb, const double* nrm
     node_from_w<DIM>(wa + k * NC, gamma, A);
     node_from_w<DIM>(wb + k * NC, gamma, B);
     if (iface)
-      interface_flux<DIM, FLUX>(A, B, nrm + k * DIM, Jf[k], gamma, g, diss, F + k * NC);
+      interface_flux<DIM, FLUX>(A, B, nrm + k * DIM, Jf[k], gamma, g, diss, F + k * NC, wa + k * NC, wb + k * NC);
     else
       ec_flux<DIM, FLUX>(A, B, nrm + k * DIM, g, F + k * NC);
   }

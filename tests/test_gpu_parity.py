@@ -31,6 +31,11 @@ SMALL = [
     ("tet_p2_random_ec", wl.random_tet(M=3, degree=2, seed=6, dissipation=0)),
     ("tet_p3_random_lf", wl.random_tet(M=3, degree=3, seed=7)),
     ("tet_p4_tgv_ec", wl.tgv_tet(M=3, degree=4)),
+    # the entropy-variable dissipation variants (scalar on the jump, matrix)
+    ("tri_p4_random_entropy_jump", wl.random_tri(M=3, degree=4, seed=51, dissipation=2)),
+    ("tri_p3_random_matrix", wl.random_tri(M=3, degree=3, seed=52, dissipation=3)),
+    ("tet_p3_random_entropy_jump", wl.random_tet(M=3, degree=3, seed=53, dissipation=2)),
+    ("tet_p4_random_matrix", wl.random_tet(M=3, degree=4, seed=54, dissipation=3)),
 ]
 
 
@@ -94,6 +99,16 @@ def test_rk4_density_wave_parity():
     du = plan.residual(u)
     er = float(R.entropy_rate(prob, u.cpu(), du.cpu()))
     assert abs(er) < 1e-12 * float(du.abs().max()) * prob.ne
+
+
+def test_vjp_of_the_entropy_variable_dissipations_is_rejected():
+    import paper_2312_07874_amd as esd
+    wk = wl.random_tri(M=3, degree=2, seed=55, dissipation=3)
+    plan = gpu_plan(wk)
+    u = torch.zeros(plan.state_shape, dtype=torch.float64, device="cuda")
+    with pytest.raises(esd.EsdError) as e:
+        plan.vjp(u, u.clone())
+    assert e.value.status == -4
 
 
 def test_inadmissible_state_sets_flag():

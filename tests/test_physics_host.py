@@ -131,6 +131,25 @@ def test_interface_flux_and_vjp(lib, dim, flux, diss):
         assert np.all(err <= 1e-10 * np.maximum(mag, 1.0)), float((err / np.maximum(mag, 1.0)).max())
 
 
+@pytest.mark.parametrize("dim,flux,diss", [(d, f, s) for d in (2, 3) for f in (0, 1) for s in (2, 3)])
+def test_interface_flux_entropy_variable_dissipation(lib, dim, flux, diss):
+    """The library's scalar entropy-jump (2) and matrix (3) dissipation against
+    the oracle's (forward only)."""
+    m = 400
+    ua, ub = states(dim, m, 31 + dim + flux)
+    wa, wb = wvars(ua), wvars(ub)
+    n, Jf = normals(dim, m, 19)
+    n = n / np.linalg.norm(n, axis=1, keepdims=True)
+    nJ = np.ascontiguousarray(n * Jf[:, None])
+    F = np.zeros((m, dim + 2))
+    lib.ph_flux(dim, flux, m, P(wa), P(wb), P(nJ), P(Jf), GAMMA, diss, 1, P(F))
+    Fo = torch.tensor(Jf)[:, None] * PH.interface_flux(PH.cons_from_entropy(torch.tensor(wa), GAMMA),
+                                                        PH.cons_from_entropy(torch.tensor(wb), GAMMA),
+                                                        torch.tensor(n), GAMMA, flux, diss)
+    scale = np.abs(Fo.numpy()).max(0)
+    assert np.all(np.abs(F - Fo.numpy()).max(0) <= 1e-13 * scale), (np.abs(F - Fo.numpy()).max(0) / scale)
+
+
 @pytest.mark.parametrize("dim", [2, 3])
 def test_entropy_vars_and_vjp(lib, dim):
     m = 500
