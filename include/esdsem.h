@@ -116,6 +116,24 @@ typedef struct {
  * esd_plan_host_array may be used with it). */
 esd_status esd_plan_create(const esd_mesh_desc* mesh, const esd_scheme_desc* scheme,
                            uint32_t flags, esd_plan** out);
+
+/* Device allocator for the plan's own arrays (operator tables, geometry,
+ * connectivity, status flag), so that a caller such as PyTorch owns that
+ * memory too: alloc(bytes, ctx) returns a 256-byte aligned device pointer on
+ * the current device, or NULL (the call then fails with ESD_ENOMEM);
+ * free(ptr, ctx) releases it (called from esd_plan_destroy, and on failed
+ * creation).  Both are called on the creating thread during creation. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* ctx);
+  void (*free)(void* ptr, void* ctx);
+  void* ctx;
+} esd_allocator;
+
+/* esd_plan_create / esd_plan_create_batched with a device allocator (NULL:
+ * hipMalloc and hipFree, as the plain calls).  ESD_EINVAL if one of the two
+ * functions is missing or a pointer is not 256-byte aligned. */
+esd_status esd_plan_create_ex(const esd_mesh_desc* mesh, const esd_scheme_desc* scheme, uint32_t flags,
+                              const esd_allocator* alloc, esd_plan** out);
 void esd_plan_destroy(esd_plan* plan);
 esd_status esd_plan_query(const esd_plan* plan, esd_plan_info* out);
 
@@ -148,6 +166,8 @@ typedef struct {
  * esd_plan_create. */
 esd_status esd_plan_create_batched(const esd_batch_desc* batch, const esd_scheme_desc* scheme, uint32_t flags,
                                    esd_plan** out);
+esd_status esd_plan_create_batched_ex(const esd_batch_desc* batch, const esd_scheme_desc* scheme, uint32_t flags,
+                                      const esd_allocator* alloc, esd_plan** out);
 
 /* Buckets of a plan (a single-degree plan has one): count, degree[b],
  * n_elements[b], and offsets dof_offset[b] (doubles into the state) and

@@ -64,6 +64,14 @@ class PlanInfo(ctypes.Structure):
                 ("vjp_workspace_bytes", ctypes.c_size_t), ("rk4_vjp_workspace_bytes", ctypes.c_size_t)]
 
 
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class _Allocator(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", ctypes.c_void_p)]
+
+
 _vp = ctypes.c_void_p
 _c = ctypes.c_int
 EXPORTS = {
@@ -77,6 +85,10 @@ EXPORTS = {
     "esd_plan_element_map": (_c, [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64),
                                   ctypes.c_int64]),
     "esd_plan_destroy": (None, [_vp]),
+    "esd_plan_create_ex": (_c, [ctypes.POINTER(_MeshDesc), ctypes.POINTER(_SchemeDesc), ctypes.c_uint32,
+                                ctypes.POINTER(_Allocator), ctypes.POINTER(_vp)]),
+    "esd_plan_create_batched_ex": (_c, [ctypes.POINTER(_BatchDesc), ctypes.POINTER(_SchemeDesc), ctypes.c_uint32,
+                                        ctypes.POINTER(_Allocator), ctypes.POINTER(_vp)]),
     "esd_plan_query": (_c, [_vp, ctypes.POINTER(PlanInfo)]),
     "esd_plan_host_array": (_c, [_vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int64]),
     "esd_node_coords": (_c, [_vp, _vp, _vp]),
@@ -125,12 +137,42 @@ def _stream():
     return torch.cuda.current_stream().cuda_stream
 
 
+class TorchAllocator:
+    """Device memory of a plan's own arrays (tables, geometry, connectivity,
+    status flag) taken from torch's caching allocator (esd_allocator): the
+    blocks are torch tensors held here until the library frees them."""
+
+    def __init__(self):
+        import torch
+        self.blocks = {}
+
+        def _alloc(nbytes, ctx):
+            try:
+                t = torch.empty(max(1, (int(nbytes) + 7) // 8), dtype=torch.float64, device="cuda")
+            except RuntimeError:
+                return None
+            self.blocks[t.data_ptr()] = t
+            return t.data_ptr()
+
+        def _free(ptr, ctx):
+            self.blocks.pop(ptr, None)
+
+        self._fns = (ALLOC_FN(_alloc), FREE_FN(_free))
+        self.struct = _Allocator(self._fns[0], self._fns[1], None)
+
+    @property
+    def bytes(self):
+        return sum(t.numel() * 8 for t in self.blocks.values())
+
+
 class Plan:
-    """A mesh + scheme set up on the device (esd_plan_create)."""
+    """A mesh + scheme set up on the device (esd_plan_create; with
+    allocator=TorchAllocator() its device arrays come from torch)."""
 
     def __init__(self, dim: int, degree: int, elem_vertex_ids, elem_vertex_coords,
                  warp: Optional[Callable[[np.ndarray], np.ndarray]] = None, gamma: float = 1.4,
-                 ecflux: int = FLUX_RANOCHA, dissipation: int = DISS_LLF_DAVIS, host_only: bool = False):
+                 ecflux: int = FLUX_RANOCHA, dissipation: int = DISS_LLF_DAVIS, host_only: bool = False,
+                 allocator: Optional[TorchAllocator] = None):
         self._ids = np.ascontiguousarray(elem_vertex_ids, dtype=np.int64)
         self._xy = np.ascontiguousarray(elem_vertex_coords, dtype=np.float64)
         ne = self._ids.shape[0]
@@ -146,8 +188,13 @@ class Plan:
                          self._xy.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), self._cb, None)
         sch = _SchemeDesc(gamma, ecflux, dissipation)
         h = _vp()
-        _check(_lib.esd_plan_create(ctypes.byref(desc), ctypes.byref(sch), 1 if host_only else 0, ctypes.byref(h)),
-               "esd_plan_create")
+        self.allocator = allocator
+        if allocator is None:
+            _check(_lib.esd_plan_create(ctypes.byref(desc), ctypes.byref(sch), 1 if host_only else 0,
+                                        ctypes.byref(h)), "esd_plan_create")
+        else:
+            _check(_lib.esd_plan_create_ex(ctypes.byref(desc), ctypes.byref(sch), 1 if host_only else 0,
+                                           ctypes.byref(allocator.struct), ctypes.byref(h)), "esd_plan_create_ex")
         self._h = h
         self.info = PlanInfo()
         _check(_lib.esd_plan_query(self._h, ctypes.byref(self.info)), "esd_plan_query")
@@ -345,7 +392,8 @@ class BatchedPlan(Plan):
     nodal arrays are flat [n_nodes, ...] in the same bucket order."""
 
     def __init__(self, dim: int, meshes, warp=None, gamma: float = 1.4, ecflux: int = FLUX_RANOCHA,
-                 dissipation: int = DISS_LLF_DAVIS, host_only: bool = False):
+                 dissipation: int = DISS_LLF_DAVIS, host_only: bool = False,
+                 allocator: Optional[TorchAllocator] = None):
         """meshes: list of (elem_vertex_ids, elem_vertex_coords, elem_degree)."""
         self._ids = [np.ascontiguousarray(m[0], dtype=np.int64) for m in meshes]
         self._xy = [np.ascontiguousarray(m[1], dtype=np.float64) for m in meshes]
@@ -360,8 +408,14 @@ class BatchedPlan(Plan):
         desc = _BatchDesc(dim, nm, self._ne.ctypes.data_as(P64), self._pid, self._pxy, self._pdeg, self._cb, None)
         sch = _SchemeDesc(gamma, ecflux, dissipation)
         h = _vp()
-        _check(_lib.esd_plan_create_batched(ctypes.byref(desc), ctypes.byref(sch), 1 if host_only else 0,
-                                            ctypes.byref(h)), "esd_plan_create_batched")
+        self.allocator = allocator
+        if allocator is None:
+            _check(_lib.esd_plan_create_batched(ctypes.byref(desc), ctypes.byref(sch), 1 if host_only else 0,
+                                                ctypes.byref(h)), "esd_plan_create_batched")
+        else:
+            _check(_lib.esd_plan_create_batched_ex(ctypes.byref(desc), ctypes.byref(sch), 1 if host_only else 0,
+                                                   ctypes.byref(allocator.struct), ctypes.byref(h)),
+                   "esd_plan_create_batched_ex")
         self._h = h
         self.info = PlanInfo()
         _check(_lib.esd_plan_query(self._h, ctypes.byref(self.info)), "esd_plan_query")

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstring>
 #include <exception>
+#include <algorithm>
 #include <array>
 #include <limits>
 #include <map>
@@ -32,24 +33,50 @@ size_t align256(size_t n) { return (n + 255) / 256 * 256; }
     if (e_ != hipSuccess) return fail(ESD_EHIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
+// the allocator of the plan being created (set by the creating entry point
+// for the duration of the call; copied into every plan it creates)
+thread_local const esd_allocator* g_alloc = nullptr;
+
+void adopt_allocator(esd_plan* p) {
+  if (g_alloc && g_alloc->alloc && g_alloc->free) {
+    p->dev_alloc = g_alloc->alloc;
+    p->dev_free = g_alloc->free;
+    p->alloc_ctx = g_alloc->ctx;
+  }
+}
+
+void* dev_alloc(const esd_plan* p, size_t bytes) {
+  if (p->dev_alloc) return p->dev_alloc(bytes, p->alloc_ctx);
+  void* ptr = nullptr;
+  return hipMalloc(&ptr, bytes) == hipSuccess ? ptr : nullptr;
+}
+
+void dev_free(const esd_plan* p, void* ptr) {
+  if (!ptr) return;
+  if (p->dev_free) p->dev_free(ptr, p->alloc_ctx);
+  else (void)hipFree(ptr);
+}
+
 template <typename T>
-esd_status upload(T** dst, const std::vector<T>& src) {
-  if (hipMalloc((void**)dst, src.size() * sizeof(T)) != hipSuccess) return fail(ESD_ENOMEM, "hipMalloc failed");
+esd_status upload(const esd_plan* p, T** dst, const std::vector<T>& src) {
+  *dst = (T*)dev_alloc(p, std::max<size_t>(1, src.size()) * sizeof(T));
+  if (!*dst) return fail(ESD_ENOMEM, "device allocation failed");
+  if (((uintptr_t)*dst) % 256 != 0) return fail(ESD_EINVAL, "the device allocator returned memory not 256-byte aligned");
   HIP_TRY(hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
   return ESD_OK;
 }
 
 void free_device(esd_plan* p) {
-  if (p->d_tables) (void)hipFree(p->d_tables);
-  if (p->d_gvol) (void)hipFree(p->d_gvol);
-  if (p->d_gfac) (void)hipFree(p->d_gfac);
-  if (p->d_conn) (void)hipFree(p->d_conn);
-  if (p->d_xvol) (void)hipFree(p->d_xvol);
-  if (p->d_flag && p->flag_owned) (void)hipFree(p->d_flag);
-  if (p->d_tasks) (void)hipFree(p->d_tasks);
-  if (p->d_mats) (void)hipFree(p->d_mats);
-  if (p->d_mat_off) (void)hipFree(p->d_mat_off);
-  if (p->d_wt_off) (void)hipFree(p->d_wt_off);
+  dev_free(p, p->d_tables);
+  dev_free(p, p->d_gvol);
+  dev_free(p, p->d_gfac);
+  dev_free(p, p->d_conn);
+  dev_free(p, p->d_xvol);
+  if (p->flag_owned) dev_free(p, p->d_flag);
+  dev_free(p, p->d_tasks);
+  dev_free(p, p->d_mats);
+  dev_free(p, p->d_mat_off);
+  dev_free(p, p->d_wt_off);
   p->d_tables = p->d_gvol = p->d_gfac = p->d_xvol = p->d_mats = nullptr;
   p->d_conn = p->d_tasks = nullptr;
   p->d_mat_off = p->d_wt_off = nullptr;
@@ -116,6 +143,7 @@ esd_status create_single(const esd_mesh_desc* mesh, const esd_scheme_desc* schem
     return fail(ESD_EINVAL, "bad scheme parameters");
   esd_plan* P = new (std::nothrow) esd_plan();
   if (!P) return fail(ESD_ENOMEM, "host allocation failed");
+  adopt_allocator(P);
   try {
     P->dim = mesh->dim;
     P->p = mesh->degree;
@@ -173,7 +201,7 @@ esd_status create_single(const esd_mesh_desc* mesh, const esd_scheme_desc* schem
     add(R.wj);
     add(R.xl);
     add(R.psiM);
-    esd_status st = upload(&P->d_tables, tb);
+    esd_status st = upload(P, &P->d_tables, tb);
     if (st != ESD_OK) {
       free_device(P);
       delete P;
@@ -183,7 +211,7 @@ esd_status create_single(const esd_mesh_desc* mesh, const esd_scheme_desc* schem
     P->tab = {b + off[0], b + off[1], b + off[2], b + off[3], b + off[4],  b + off[5],
               b + off[6], b + off[7], b + off[8], b + off[9], b + off[10], b + off[11], b + off[12]};
     // geometry
-    st = upload(&P->d_gvol, pack_gvol(*P));
+    st = upload(P, &P->d_gvol, pack_gvol(*P));
     const int NFQ = R.NFQ, NQF = R.NQF, dim = P->dim, NF = R.NF;
     std::vector<double> gf((size_t)P->ne * (dim + 1) * NFQ);
     std::vector<int32_t> conn((size_t)P->ne * NFQ);
@@ -216,10 +244,10 @@ esd_status create_single(const esd_mesh_desc* mesh, const esd_scheme_desc* schem
           break;
         }
       }
-    if (st == ESD_OK) st = upload(&P->d_gfac, gf);
-    if (st == ESD_OK && connect) st = upload(&P->d_conn, conn);
-    if (st == ESD_OK) st = upload(&P->d_xvol, P->geo.x_vol);
-    if (st == ESD_OK) st = upload(&P->d_flag, std::vector<int>(1, 0));
+    if (st == ESD_OK) st = upload(P, &P->d_gfac, gf);
+    if (st == ESD_OK && connect) st = upload(P, &P->d_conn, conn);
+    if (st == ESD_OK) st = upload(P, &P->d_xvol, P->geo.x_vol);
+    if (st == ESD_OK) st = upload(P, &P->d_flag, std::vector<int>(1, 0));
     if (st != ESD_OK) {
       free_device(P);
       delete P;
@@ -245,6 +273,24 @@ esd_status esd_plan_create(const esd_mesh_desc* mesh, const esd_scheme_desc* sch
   return create_single(mesh, scheme, flags, true, out);
 }
 
+esd_status esd_plan_create_ex(const esd_mesh_desc* mesh, const esd_scheme_desc* scheme, uint32_t flags,
+                              const esd_allocator* alloc, esd_plan** out) {
+  if (alloc && (!alloc->alloc || !alloc->free)) return fail(ESD_EINVAL, "allocator needs both functions");
+  g_alloc = alloc;
+  const esd_status st = esd_plan_create(mesh, scheme, flags, out);
+  g_alloc = nullptr;
+  return st;
+}
+
+esd_status esd_plan_create_batched_ex(const esd_batch_desc* batch, const esd_scheme_desc* scheme, uint32_t flags,
+                                      const esd_allocator* alloc, esd_plan** out) {
+  if (alloc && (!alloc->alloc || !alloc->free)) return fail(ESD_EINVAL, "allocator needs both functions");
+  g_alloc = alloc;
+  const esd_status st = esd_plan_create_batched(batch, scheme, flags, out);
+  g_alloc = nullptr;
+  return st;
+}
+
 esd_status esd_plan_create_batched(const esd_batch_desc* d, const esd_scheme_desc* scheme, uint32_t flags,
                                    esd_plan** out) {
   if (!out) return fail(ESD_EINVAL, "out is NULL");
@@ -260,6 +306,7 @@ esd_status esd_plan_create_batched(const esd_batch_desc* d, const esd_scheme_des
   const bool host_only = (flags & 1u) != 0;
   esd_plan* P = new (std::nothrow) esd_plan();
   if (!P) return fail(ESD_ENOMEM, "host allocation failed");
+  adopt_allocator(P);
   auto bail = [&](esd_status st, const std::string& m) {
     esd_plan_destroy(P);
     return fail(st, m);
@@ -409,8 +456,8 @@ esd_status esd_plan_create_batched(const esd_batch_desc* d, const esd_scheme_des
       }
       sp->n_tasks = (int64_t)tasks.size() / 8;
       if (!host_only) {
-        esd_status st = upload(&sp->d_conn, conn);
-        if (st == ESD_OK && !tasks.empty()) st = upload(&sp->d_tasks, tasks);
+        esd_status st = upload(sp, &sp->d_conn, conn);
+        if (st == ESD_OK && !tasks.empty()) st = upload(sp, &sp->d_tasks, tasks);
         if (st != ESD_OK) return bail(st, "upload failed");
       }
     }
@@ -436,13 +483,13 @@ esd_status esd_plan_create_batched(const esd_batch_desc* d, const esd_scheme_des
     P->vjp_ws_bytes = P->rk_vjp_ws_bytes = 0;
     if (!host_only) {
       if (hipGetDevice(&P->device) != hipSuccess) return bail(ESD_EHIP, "no HIP device");
-      esd_status st = upload(&P->d_flag, std::vector<int>(1, 0));
-      if (st == ESD_OK && !mats.empty()) st = upload(&P->d_mats, mats);
-      if (st == ESD_OK && !mat_off.empty()) st = upload(&P->d_mat_off, mat_off);
-      if (st == ESD_OK) st = upload(&P->d_wt_off, wt_off);
+      esd_status st = upload(P, &P->d_flag, std::vector<int>(1, 0));
+      if (st == ESD_OK && !mats.empty()) st = upload(P, &P->d_mats, mats);
+      if (st == ESD_OK && !mat_off.empty()) st = upload(P, &P->d_mat_off, mat_off);
+      if (st == ESD_OK) st = upload(P, &P->d_wt_off, wt_off);
       if (st != ESD_OK) return bail(st, "upload failed");
       for (esd_plan* sp : P->sub) {
-        (void)hipFree(sp->d_flag);
+        dev_free(sp, sp->d_flag);
         sp->d_flag = P->d_flag;
         sp->flag_owned = false;
       }

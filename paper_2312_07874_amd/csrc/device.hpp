@@ -37,7 +37,7 @@ struct Shape {
   static constexpr int SCR = (T1 + T2 > 8 * NQ) ? (T1 + T2) : 8 * NQ;   // and the right-hand side's node records
   // the right-hand-side kernel keeps the own facet node records in LDS when
   // node data, r, facet records and facet sums fit the 160 KB of a CU
-  static constexpr bool K2_FACET_LDS = 8 * (SCR + NC * NQ + (DIM == 3 ? 7 : 8) * NFQ + NC * NFQ) <= 160 * 1024;
+  static constexpr bool K2_FACET_LDS = 8 * (SCR + NC * NQ + 8 * NFQ + NC * NFQ) <= 160 * 1024;
 };
 
 template <int DIM, int P>
@@ -52,10 +52,6 @@ struct Launch<3, P> {
   // K1 and K2 are compiled for up to BSMAX threads and launched with BS or with
   // the block size the autotuner picked (their loops take any size)
   static constexpr int BSMAX = 512;
-  // waves per SIMD the right-hand-side kernel's registers must allow: at p = 6
-  // its LDS fits three workgroups per CU, which 4-wave workgroups reach only
-  // at <= 168 VGPRs
-  static constexpr int K2_MINW = P == 6 ? 3 : 1;
   static_assert(P <= 10, "tetrahedra up to p = 10");
 };
 template <int P>
@@ -66,7 +62,6 @@ struct Launch<2, P> {
   static constexpr int NQ = (P + 1) * (P + 1);
   static constexpr int BS = ((EPB * NQ + 63) / 64) * 64;
   static constexpr int BSMAX = 2 * BS < 768 ? 2 * BS : (BS > 768 ? BS : 768);   // <= 3 waves per SIMD
-  static constexpr int K2_MINW = 1;
 };
 
 __device__ __forceinline__ int pair_index(int P, int a1, int a2) { return a1 * (P + 1) - a1 * (a1 - 1) / 2 + a2; }
@@ -543,32 +538,6 @@ __device__ __forceinline__ void store_node(double* s, int stride, int k, const N
   s[4 * stride + k] = n.p;
 #pragma unroll
   for (int i = 0; i < DIM; ++i) s[(5 + i) * stride + k] = n.v[i];
-}
-
-// own facet node records of the right-hand side: 7 numbers per node, p left
-// out and formed on load as rho * (1/b), the product from_entropy forms it
-// by (so the loaded node equals the stored one bit for bit)
-constexpr int FREC = 7;
-template <int DIM>
-__device__ __forceinline__ Node<DIM> load_facet_node(const double* s, int stride, int k) {
-  Node<DIM> n;
-  n.rho = s[0 * stride + k];
-  n.lnrho = s[1 * stride + k];
-  n.b = s[2 * stride + k];
-  n.lnb = s[3 * stride + k];
-#pragma unroll
-  for (int i = 0; i < DIM; ++i) n.v[i] = s[(4 + i) * stride + k];
-  n.p = n.rho * frcp(n.b);
-  return n;
-}
-template <int DIM>
-__device__ __forceinline__ void store_facet_node(double* s, int stride, int k, const Node<DIM>& n) {
-  s[0 * stride + k] = n.rho;
-  s[1 * stride + k] = n.lnrho;
-  s[2 * stride + k] = n.b;
-  s[3 * stride + k] = n.lnb;
-#pragma unroll
-  for (int i = 0; i < DIM; ++i) s[(4 + i) * stride + k] = n.v[i];
 }
 
 // ------------------------------------------------------------------ facet extrapolation and its transpose

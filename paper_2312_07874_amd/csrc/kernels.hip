@@ -216,7 +216,7 @@ __device__ __forceinline__ void facet_task(const Node<DIM>& Vi, const double* gn
                                            const double* __restrict__ gf, int j, double coef, const Scheme& S,
                                            double* racc) {
   constexpr int NC = DIM + 2, NFQ = Shape<DIM, P>::NFQ;
-  const Node<DIM> Fj = load_facet_node<DIM>(sF, NFQ, j);
+  const Node<DIM> Fj = load_node<DIM>(sF, NFQ, j);
   double n[DIM];
 #pragma unroll
   for (int i = 0; i < DIM; ++i) n[i] = 0.5 * (gn_i[i] + gf[i * NFQ + j]);
@@ -302,7 +302,7 @@ __device__ __forceinline__ void dense_facet_task(const Node<DIM>& Vi, const doub
       else if (z == 0 && jj == i1 + Q * i3) coef = T.lgm1[i2] * T.wf[j];
       else if (z == 3 && jj % Q == i1) coef = T.gjm1[i3] * T.I42[(jj / Q) * Q + i2] * T.wf[j];
     }
-    const Node<DIM> Fj = load_facet_node<DIM>(sF, NFQ, j);
+    const Node<DIM> Fj = load_node<DIM>(sF, NFQ, j);
     double n[DIM];
 #pragma unroll
     for (int m = 0; m < DIM; ++m) n[m] = 0.5 * (gn[z][m] + gf[m * NFQ + j]);
@@ -319,7 +319,7 @@ __device__ __forceinline__ void dense_facet_task(const Node<DIM>& Vi, const doub
 
 // ------------------------------------------------------------------ K2: right-hand side
 template <int DIM, int P, int FLUX, bool NEXT, bool DENSE = false>
-__global__ void __launch_bounds__((Launch<DIM, P>::BSMAX), (Launch<DIM, P>::K2_MINW))
+__global__ void __launch_bounds__((Launch<DIM, P>::BSMAX))
 k_rhs(const double* __restrict__ wt, const double* __restrict__ wfb, double* __restrict__ dudt,
       const double* __restrict__ gvol, const double* __restrict__ gfac, const int32_t* __restrict__ conn,
       DevTables T0, Scheme S, int64_t ne, int* flag, double* frec, RkEpilogue epi) {
@@ -330,11 +330,9 @@ k_rhs(const double* __restrict__ wt, const double* __restrict__ wfb, double* __r
   // own facet node records live in LDS when everything fits, else in this
   // element's slice of the workspace (frec, [e][8][NFQ]; read through the caches)
   constexpr bool FLDS = Sh::K2_FACET_LDS;
-  // facet record slots per node (7 used; triangles keep 8 for the modal staging at high degree)
-  constexpr int FRA = DIM == 3 ? FREC : 8;
   __shared__ double sN[EPB * Sh::SCR];      // node data [el][8][NQ]; transform scratch
   __shared__ double sR[EPB * NC * NQ];      // w at nodes, then r
-  __shared__ double sF[FLDS ? EPB * FRA * NFQ : 1];   // own facet node records (LDS case)
+  __shared__ double sF[FLDS ? EPB * 8 * NFQ : 1];   // own facet node records (LDS case)
   __shared__ double sT[EPB * NC * NFQ];     // C^T 1, then s = B J_f f* - C^T 1
   // operator tables in LDS: tetrahedra keep them in the tail of sF beyond the
   // modal staging, free during both transform phases (copied again once the
@@ -345,8 +343,8 @@ k_rhs(const double* __restrict__ wt, const double* __restrict__ wfb, double* __r
   // records, read their tables from T0.
   constexpr unsigned W0 = NEXT ? (TAB_PSI | TAB_FACET) : TAB_PSI;
   constexpr unsigned W1 = W0 | TAB_PSIM;   // with the composed stage of V V^T
-  constexpr int ROOM = (DIM == 3 && FLDS) ? FRA * NFQ - NC * NP : -1;   // doubles free in sF's tail
-  constexpr int KB = 8 * (EPB * (Sh::SCR + NC * NQ + NC * NFQ) + (FLDS ? EPB * FRA * NFQ : 1));
+  constexpr int ROOM = (DIM == 3 && FLDS) ? 8 * NFQ - NC * NP : -1;   // doubles free in sF's tail
+  constexpr int KB = 8 * (EPB * (Sh::SCR + NC * NQ + NC * NFQ) + (FLDS ? EPB * 8 * NFQ : 1));
   constexpr unsigned TM =
       DIM == 2 ? (tab_keeps_wgs<DIM, P, W0, W1>(KB, wave_cap<DIM, P>()) ? W1 : tab_mask<DIM, P, W0>(KB))
                : (TabLds<DIM, P, W1>::SIZE <= ROOM   ? W1
@@ -358,14 +356,14 @@ k_rhs(const double* __restrict__ wt, const double* __restrict__ wfb, double* __r
   __shared__ double sTab[DIM == 2 && TM ? TabLds<DIM, P, TM>::SIZE : 1];
   double* const tab_buf = TAB_SF ? sF + NC * NP : sTab;
   const DevTables T = stage_tables<DIM, P, TM>(T0, tab_buf);
-  static_assert(FLDS ? FRA * NFQ >= NC * NP : NFQ >= NP, "modal staging must fit the facet buffers");
+  static_assert(FLDS ? 8 * NFQ >= NC * NP : NFQ >= NP, "modal staging must fit the facet buffers");
   // modal w~ before the facet data exist, du~/dt after they are dead
   double* sM = FLDS ? sF : sT;
   double* lift_scratch = FLDS ? sF : sN;
   const int64_t e0 = (int64_t)blockIdx.x * EPB;
   const int nel = (int)((ne - e0) < EPB ? (ne - e0) : EPB);
   const int nec = nel * NC;
-  double* fr = FLDS ? sF : frec + e0 * FRA * NFQ;
+  double* fr = FLDS ? sF : frec + e0 * 8 * NFQ;
   const int tid = threadIdx.x, nth = blockDim.x;
   double* T1 = sN;
   double* T2 = sN + EPB * Sh::T1;
@@ -405,7 +403,7 @@ k_rhs(const double* __restrict__ wt, const double* __restrict__ wfb, double* __r
     Node<DIM> Um, Up;
     bad |= !from_entropy<DIM>(w, S.gamma, S.gm1_inv, Um);
     bad |= !from_entropy<DIM>(wn, S.gamma, S.gm1_inv, Up);
-    store_facet_node<DIM>(fr + el * FRA * NFQ, NFQ, j, Um);
+    store_node<DIM>(fr + el * 8 * NFQ, NFQ, j, Um);
     double F[NC];
     interface_flux<DIM, FLUX>(Um, Up, nJ, Jf, S.gamma, S.gm1_inv, S.dissipation, F, w, wn);
     const double wj = T0.wf[j];
@@ -439,7 +437,8 @@ k_rhs(const double* __restrict__ wt, const double* __restrict__ wfb, double* __r
       const int fam = lt / NQ, rem = lt % NQ;
       // lanes run along a line (a fastest) for the families of stride 1 and Q,
       // across lines (L fastest) for the family of stride Q^2: consecutive
-      // lanes then address distinct LDS banks
+      // lanes then address distinct LDS banks (measured: across lines also for
+      // the stride-Q family, tri p4 0.031 -> 0.038 ms, tet p6 2.42 -> 2.48 ms)
       const bool across = DIM == 3 && fam == 2;
       const int L = across ? rem % LPF : rem / Q, a = across ? rem / LPF : rem % Q;
       const double* sNe = sN + el * Sh::SCR;
@@ -469,7 +468,7 @@ k_rhs(const double* __restrict__ wt, const double* __restrict__ wfb, double* __r
   for (int task = tid; task < nel * NQ; task += nth) {
     const int el = task / NQ, t = task % NQ;
     const double* sNe = sN + el * Sh::SCR;
-    const double* sFe = fr + el * FRA * NFQ;
+    const double* sFe = fr + el * 8 * NFQ;
     double* sTe = sT + el * NC * NFQ;
     const double* g = gvol + (e0 + el) * NGV * NQ;
     const double* gf = gfac + (e0 + el) * (DIM + 1) * NFQ;

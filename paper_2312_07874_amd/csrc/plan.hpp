@@ -92,6 +92,10 @@ struct esd_plan {
   double* d_xvol = nullptr;
   int* d_flag = nullptr;
   bool flag_owned = true;         // false for buckets sharing the batched plan's flag
+  // device allocator of the plan's own arrays (null members: hipMalloc / hipFree)
+  void* (*dev_alloc)(size_t, void*) = nullptr;
+  void (*dev_free)(void*, void*) = nullptr;
+  void* alloc_ctx = nullptr;
   size_t ws_bytes = 0;
   size_t frec_bytes = 0;          // tail of the residual workspace holding Workspace::frec
   size_t rk_ws_bytes = 0;
