@@ -79,8 +79,8 @@ typedef void (*esd_warp_fn)(int64_t n, const double* x_in, double* x_out, void* 
 typedef struct {
   int32_t dim;                         /* 2 (triangles) or 3 (tetrahedra)          */
   int32_t degree;                      /* p = q = p_g for every element (Sec. 7.3); built:
-                                          1..10 (triangles and tetrahedra); the VJP
-                                          entry points: tetrahedra up to 8         */
+                                          1..10 (triangles and tetrahedra), the VJP
+                                          entry points included                     */
   int64_t n_elements;
   const int64_t* elem_vertex_ids;      /* host [n_elements][dim+1] global ids; periodic
                                           images of a vertex share one id           */
@@ -280,7 +280,9 @@ esd_status esd_plan_get_tuning(const esd_plan* plan, int32_t* k2_block, int32_t 
  * arguments agree: where they agree to 1e-10 relative (a tie up to rounding)
  * the derivative is the mean of the two one-sided derivatives, elsewhere that
  * of the larger argument (|x| has derivative 0 at 0).  grad_dev must not overlap
- * u_dev or vbar_dev; ws_dev holds info.vjp_workspace_bytes (256-byte aligned).
+ * u_dev or vbar_dev; ws_dev holds info.vjp_workspace_bytes (256-byte aligned;
+ * for tetrahedra at p = 9, 10 it includes a slice per element for the arrays
+ * of the adjoint kernels that do not fit in LDS).
  * Errors: ESD_EINVAL, ESD_EUNSUPPORTED (degree not built, or facet nodes not
  * paired both ways), ESD_EHIP; inadmissible states set the sticky flag. */
 esd_status esd_residual_vjp(const esd_plan* plan, const double* u_dev, const double* vbar_dev,

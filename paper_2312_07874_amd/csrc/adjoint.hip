@@ -35,6 +35,25 @@ struct VjpLaunch {
   static constexpr int BS = Launch<DIM, P>::BS > 256 ? 256 : Launch<DIM, P>::BS;
 };
 
+// Where the adjoint kernels keep their per-element arrays.  Up to tet p = 8
+// everything is in LDS; above, VK2 moves its facet arrays (node records,
+// t_bar, facet x_bar) and, at p = 10, r_bar to this element's slice of the
+// VJP workspace, and VK1 its gathered facet cotangents at p = 10 (read
+// through the caches, written and read by the element's own workgroup).
+template <int DIM, int P>
+struct VjpMem {
+  using Sh = Shape<DIM, P>;
+  static constexpr int NC = Sh::NC, NQ = Sh::NQ, NP = Sh::NP, NFQ = Sh::NFQ;
+  static constexpr int NB = NQ > NFQ ? NQ : NFQ;
+  static constexpr bool FG = 8 * (Sh::SCR + 2 * NC * NQ + 8 * NFQ + 2 * NC * NFQ) > LDS_BYTES;
+  static constexpr bool RG = FG && 8 * (Sh::SCR + 2 * NC * NQ) > LDS_BYTES;
+  static constexpr bool BG = 8 * (NC * NP + NC * NQ + NC * NB + Sh::XSCR) > LDS_BYTES;
+  // doubles of the workspace slice per element (VK1 reuses VK2's slice)
+  static constexpr int VK2_SLICE = (FG ? (8 + 2 * NC) * NFQ : 0) + (RG ? NC * NQ : 0);
+  static constexpr int VK1_SLICE = BG ? NC * NB : 0;
+  static constexpr int SLICE = VK2_SLICE > VK1_SLICE ? VK2_SLICE : VK1_SLICE;
+};
+
 // One volume adjoint task: node a of the line base + stride*k and the same
 // partners as the forward task; F_bar = r_bar_b - r_bar_a.
 template <int DIM, int P, int FLUX, int NA>
@@ -122,23 +141,30 @@ __global__ void __launch_bounds__((VjpLaunch<DIM, P>::BS))
 k_rhs_vjp(const double* __restrict__ wt, const double* __restrict__ wfb, const double* __restrict__ vbar,
           double* __restrict__ gpart, double* __restrict__ xbar, const double* __restrict__ gvol,
           const double* __restrict__ gfac, const int32_t* __restrict__ conn, DevTables T0, Scheme S, int64_t ne,
-          int* flag) {
+          int* flag, double* gscr) {
   using Sh = Shape<DIM, P>;
   constexpr int EPB = Launch<DIM, P>::EPB;
   constexpr int Q = Sh::Q, NC = Sh::NC, NQ = Sh::NQ, NP = Sh::NP, NQF = Sh::NQF, NFQ = Sh::NFQ, NGV = Sh::NGV;
   constexpr int LPF = Sh::LPF;
+  using VM = VjpMem<DIM, P>;
+  static_assert(!VM::FG || EPB == 1, "workspace slices are per element");
   __shared__ double sN[EPB * Sh::SCR];      // transform scratch; node data [el][8][NQ]
-  __shared__ double sR[EPB * NC * NQ];      // r_bar
   __shared__ double sX[EPB * NC * NQ];      // modal / nodal staging; x_bar, then w_bar at volume nodes
-  __shared__ double sF[EPB * 8 * NFQ];      // own facet node data; later R^T scratch
-  __shared__ double sT[EPB * NC * NFQ];     // t_bar = R r_bar
-  __shared__ double sXF[EPB * NC * NFQ];    // x_bar, then w_bar at own facet nodes
+  __shared__ double sR_l[VM::RG ? 1 : EPB * NC * NQ];       // r_bar
+  __shared__ double sF_l[VM::FG ? 1 : EPB * 8 * NFQ];       // own facet node data; later R^T scratch
+  __shared__ double sT_l[VM::FG ? 1 : EPB * NC * NFQ];      // t_bar = R r_bar
+  __shared__ double sXF_l[VM::FG ? 1 : EPB * NC * NFQ];     // x_bar, then w_bar at own facet nodes
+  double* const slice = gscr + (int64_t)blockIdx.x * VM::SLICE;
+  double* const sF = VM::FG ? slice : sF_l;
+  double* const sT = VM::FG ? slice + 8 * NFQ : sT_l;
+  double* const sXF = VM::FG ? slice + (8 + NC) * NFQ : sXF_l;
+  double* const sR = VM::RG ? slice + (8 + 2 * NC) * NFQ : sR_l;
   // staged tables only where they do not lower the workgroups per CU: this
   // kernel is bound by its pair adjoints, not by the transforms, and runs at
   // about 2 waves per SIMD (about 225 VGPRs), which caps the workgroups per CU
   // at 8 waves' worth (measured at tet p = 6: VJP 8.17 -> 6.28 ms without the
   // tables, 1 -> 2 workgroups per CU; at p = 4 the tables stay)
-  constexpr int VB = 8 * EPB * (Sh::SCR + 2 * NC * NQ + 8 * NFQ + 2 * NC * NFQ);
+  constexpr int VB = 8 * EPB * (Sh::SCR + NC * NQ + (VM::RG ? 0 : NC * NQ) + (VM::FG ? 0 : 8 * NFQ + 2 * NC * NFQ));
   constexpr int VT = 8 * TabLds<DIM, P, TAB_PSI | TAB_FACET>::SIZE;
   constexpr int CAP = 8 / ((VjpLaunch<DIM, P>::BS + 63) / 64);
   constexpr int WG_T = LDS_BYTES / (VB + VT) < CAP ? LDS_BYTES / (VB + VT) : CAP;
@@ -204,6 +230,10 @@ k_rhs_vjp(const double* __restrict__ wt, const double* __restrict__ wfb, const d
   __syncthreads();
   for (int o = tid; o < nec * NQ; o += nth) sX[o] = 0.0;
   for (int o = tid; o < nec * NFQ; o += nth) sXF[o] = 0.0;
+  // with the facet x_bar in global memory, the atomics below act in L2 and
+  // the plain accesses around them go through the CU's L1: device-scope fences
+  // (L1 written back and invalidated) before the barriers that order them
+  if constexpr (VM::FG) __threadfence();
   __syncthreads();
 
   // ---- volume pairs, same task decomposition as the forward kernel
@@ -322,6 +352,7 @@ k_rhs_vjp(const double* __restrict__ wt, const double* __restrict__ wfb, const d
       for (int c = 0; c < NC; ++c) sX[(el * NC + c) * NQ + i] += xi[c];
     }
   }
+  if constexpr (VM::FG) __threadfence();
   __syncthreads();
 
   // ---- interface flux: f*_bar = -B_j t_bar_j; own side into LDS, neighbour side
@@ -359,6 +390,7 @@ k_rhs_vjp(const double* __restrict__ wt, const double* __restrict__ wfb, const d
     for (int c = 0; c < NC; ++c) xbar[(e * NC + c) * NFQ + j] = wp[c];
   }
   if (bad) atomicOr(flag, 1);
+  if constexpr (VM::FG) __threadfence();
   __syncthreads();
 
   // ---- x_bar -> w_bar at volume and own facet nodes
@@ -397,16 +429,19 @@ template <int DIM, int P>
 __global__ void __launch_bounds__((VjpLaunch<DIM, P>::BS))
 k_projection_vjp(const double* __restrict__ u, double* g, const double* __restrict__ xbar,
                  const double* __restrict__ gvol, const int32_t* __restrict__ conn, DevTables T0, Scheme S,
-                 int64_t ne) {
+                 int64_t ne, double* gscr) {
   using Sh = Shape<DIM, P>;
   constexpr int EPB = Launch<DIM, P>::EPB;
   constexpr int NC = Sh::NC, NQ = Sh::NQ, NP = Sh::NP, NFQ = Sh::NFQ, NGV = Sh::NGV;
-  constexpr int NB = NQ > NFQ ? NQ : NFQ;
+  using VM = VjpMem<DIM, P>;
+  constexpr int NB = VM::NB;
+  static_assert(!VM::BG || EPB == 1, "workspace slices are per element");
   __shared__ double sM[EPB * NC * NP];
   __shared__ double sA[EPB * NC * NQ];
-  __shared__ double sB[EPB * NC * NB];      // gathered facet cotangents, later u at the nodes
-  __shared__ double sS[EPB * Sh::SCR];
-  constexpr int KB = 8 * EPB * (NC * NP + NC * NQ + NC * NB + Sh::SCR);
+  __shared__ double sB_l[VM::BG ? 1 : EPB * NC * NB];      // gathered facet cotangents, later u at the nodes
+  __shared__ double sS[EPB * Sh::XSCR];
+  double* const sB = VM::BG ? gscr + (int64_t)blockIdx.x * VM::SLICE : sB_l;
+  constexpr int KB = 8 * EPB * (NC * NP + NC * NQ + (VM::BG ? 0 : NC * NB) + Sh::XSCR);
   constexpr unsigned TM =
       tab_keeps_wgs<DIM, P, TAB_PSI | TAB_FACET, TAB_PSI | TAB_FACET | TAB_PSIM>(KB, wave_cap<DIM, P>())
           ? (TAB_PSI | TAB_FACET | TAB_PSIM)
@@ -499,13 +534,23 @@ static int run_vjp(const esd_plan* pl, const double* u, const double* vbar, doub
   if (rc != 0) return rc;
   if (pl->scheme.ecflux == FLUX_RANOCHA)
     hipLaunchKernelGGL((k_rhs_vjp<DIM, P, FLUX_RANOCHA>), dim3(nb), dim3(L::BS), 0, s, ws.wt, ws.wf, vbar, grad,
-                       ws.xbar, pl->d_gvol, pl->d_gfac, pl->d_conn, pl->tab, pl->scheme, pl->ne, pl->d_flag);
+                       ws.xbar, pl->d_gvol, pl->d_gfac, pl->d_conn, pl->tab, pl->scheme, pl->ne, pl->d_flag, ws.vscr);
   else
     hipLaunchKernelGGL((k_rhs_vjp<DIM, P, FLUX_CHANDRASHEKAR>), dim3(nb), dim3(L::BS), 0, s, ws.wt, ws.wf, vbar,
-                       grad, ws.xbar, pl->d_gvol, pl->d_gfac, pl->d_conn, pl->tab, pl->scheme, pl->ne, pl->d_flag);
+                       grad, ws.xbar, pl->d_gvol, pl->d_gfac, pl->d_conn, pl->tab, pl->scheme, pl->ne, pl->d_flag,
+                       ws.vscr);
   hipLaunchKernelGGL((k_projection_vjp<DIM, P>), dim3(nb), dim3(L::BS), 0, s, u, grad, ws.xbar, pl->d_gvol,
-                     pl->d_conn, pl->tab, pl->scheme, pl->ne);
+                     pl->d_conn, pl->tab, pl->scheme, pl->ne, ws.vscr);
   return (int)hipGetLastError();
+}
+
+int vjp_scratch_doubles(int dim, int p) {
+#define X(D, PP) \
+  if (dim == D && p == PP) return VjpMem<D, PP>::SLICE;
+  ESD_TRI_DEGREES(X)
+  ESD_TET_VJP_DEGREES(X)
+#undef X
+  return 0;
 }
 
 int launch_vjp(const esd_plan* pl, const double* u, const double* vbar, double* grad, Workspace ws, hipStream_t s) {

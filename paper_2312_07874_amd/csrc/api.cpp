@@ -171,7 +171,8 @@ esd_status create_single(const esd_mesh_desc* mesh, const esd_scheme_desc* schem
     P->ws_bytes = align256(ndof * sizeof(double)) + fbytes + P->frec_bytes;
     P->rk_ws_bytes = 2 * P->ws_bytes + 3 * align256(ndof * sizeof(double));
     P->fuse_next = P->dim == 2;
-    P->vjp_ws_bytes = P->ws_bytes + fbytes;
+    P->vscr_bytes = align256((size_t)P->ne * esd::vjp_scratch_doubles(P->dim, P->p) * sizeof(double));
+    P->vjp_ws_bytes = P->ws_bytes + fbytes + P->vscr_bytes;
     P->rk_vjp_ws_bytes = P->vjp_ws_bytes + 3 * align256(ndof * sizeof(double));
     if (P->host_only) {
       *out = P;
@@ -691,6 +692,7 @@ static esd::Workspace split_ws(const esd_plan* P, void* ws) {
   w.wf = (double*)((char*)ws + align256(ndof * sizeof(double)));
   w.frec = P->frec_bytes ? (double*)((char*)ws + P->ws_bytes - P->frec_bytes) : nullptr;
   w.xbar = (double*)((char*)ws + P->ws_bytes);   // inside the workspace only for the VJP entry points
+  w.vscr = (double*)((char*)ws + P->vjp_ws_bytes - P->vscr_bytes);
   return w;
 }
 

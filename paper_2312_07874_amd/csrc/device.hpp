@@ -14,8 +14,8 @@ namespace esd {
 // degrees built into the library, per dimension
 #define ESD_TRI_DEGREES(X) X(2, 1) X(2, 2) X(2, 3) X(2, 4) X(2, 5) X(2, 6) X(2, 7) X(2, 8) X(2, 9) X(2, 10)
 #define ESD_TET_DEGREES(X) X(3, 1) X(3, 2) X(3, 3) X(3, 4) X(3, 5) X(3, 6) X(3, 7) X(3, 8) X(3, 9) X(3, 10)
-// the adjoint kernels hold more state per element in LDS: tetrahedra up to p = 8
-#define ESD_TET_VJP_DEGREES(X) X(3, 1) X(3, 2) X(3, 3) X(3, 4) X(3, 5) X(3, 6) X(3, 7) X(3, 8)
+// the adjoint kernels (at p = 9, 10 part of their per-element arrays in the workspace)
+#define ESD_TET_VJP_DEGREES(X) X(3, 1) X(3, 2) X(3, 3) X(3, 4) X(3, 5) X(3, 6) X(3, 7) X(3, 8) X(3, 9) X(3, 10)
 
 // ------------------------------------------------------------------ shapes
 template <int DIM, int P>

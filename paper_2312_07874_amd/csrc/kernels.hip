@@ -751,7 +751,7 @@ std::vector<int> rhs_block_candidates(int dim, int p) {
 
 bool vjp_degree_supported(int dim, int p) {
   if (dim == 2) return p >= 1 && p <= 10;
-  if (dim == 3) return p >= 1 && p <= 8;
+  if (dim == 3) return p >= 1 && p <= 10;
   return false;
 }
 

@@ -70,6 +70,7 @@ struct Workspace {
   double* wt;     // [ne][NC][NP]  projected entropy variables (modal)
   double* wf;     // [ne][NC][NFQ] projected entropy variables at facet nodes
   double* xbar;   // [ne][NC][NFQ] VJP only: cotangent of the neighbour's facet value seen at each own facet node
+  double* vscr;   // VJP only: per-element slices for the adjoint arrays that do not fit LDS (high degree)
   double* frec;   // [ne][8][NFQ] own facet node records, only for degrees whose right-hand side
                   // does not fit them in LDS (else nullptr)
 };
@@ -100,6 +101,7 @@ struct esd_plan {
   size_t frec_bytes = 0;          // tail of the residual workspace holding Workspace::frec
   size_t rk_ws_bytes = 0;
   size_t vjp_ws_bytes = 0;
+  size_t vscr_bytes = 0;          // tail of the VJP workspace holding Workspace::vscr
   size_t rk_vjp_ws_bytes = 0;
   bool conn_involutive = false;   // facet permutation pairs nodes both ways (needed by the VJP gather)
   // measurement: events bracketing each K1 / K2 launch (mutable: recorded by const calls)
@@ -172,5 +174,6 @@ int launch_diagnostics(const esd_plan* P, const double* u, const double* dudt, d
 bool degree_supported(int dim, int p);
 bool vjp_degree_supported(int dim, int p);
 bool needs_facet_records(int dim, int p);   // the residual workspace holds Workspace::frec
+int vjp_scratch_doubles(int dim, int p);    // per element, of Workspace::vscr (0 if none)
 std::vector<int> rhs_block_candidates(int dim, int p);
 }  // namespace esd

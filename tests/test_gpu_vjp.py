@@ -154,10 +154,11 @@ def test_vjp_matches_central_differences_full_size():
     plan.sync_status()
 
 
-@pytest.mark.parametrize("p", [6, 7, 8])
+@pytest.mark.parametrize("p", [6, 7, 8, 9, 10])
 def test_vjp_matches_central_differences_high_degree(p):
-    """The same identity on a small curved tetrahedral mesh at p = 6-8 (the
-    adjoint kernels' LDS-table and composed-transform variants there), library
+    """The same identity on a small curved tetrahedral mesh at p = 6-10 (the
+    adjoint kernels' LDS-table and composed-transform variants there, and at
+    p = 9, 10 their per-element slices of the global workspace), library
     only.  The interface flux is the entropy-conservative one: with the Davis
     wave speed (a maximum of two states that nearly agree on a smooth field)
     the residual has kinks, and central differences there stall near 1e-5
@@ -193,6 +194,24 @@ def test_vjp_parity_tet_p7_lax_friedrichs_sampled():
     out = plan.vjp(ut.cuda().contiguous(), vbar.cuda().contiguous()).cpu()
     plan.sync_status()
     el = np.random.default_rng(5).choice(prob.ne, 4, replace=False)
+    ref = oracle_vjp_pair(prob, ut, vbar, el)
+    assert_close(out[el], ref, wk.name)
+
+
+@pytest.mark.parametrize("p", [9, 10])
+def test_vjp_parity_tet_top_degrees_sampled(p):
+    """Tet p = 9 and 10 with the Davis dissipation against the oracle on 2
+    sampled elements: the adjoint kernels keep part of their per-element
+    arrays in a global workspace slice at these degrees."""
+    wk = wl.random_tet(M=3, degree=p, seed=50 + p)
+    log(f"case tet p{p}: M=3, dissipation {wk.dissipation}")
+    prob = oracle_problem(wk)
+    ut = oracle_state(prob, wk)
+    vbar = cotangent(ut.shape, 37)
+    plan = gpu_plan(wk)
+    out = plan.vjp(ut.cuda().contiguous(), vbar.cuda().contiguous()).cpu()
+    plan.sync_status()
+    el = np.random.default_rng(7).choice(prob.ne, 2, replace=False)
     ref = oracle_vjp_pair(prob, ut, vbar, el)
     assert_close(out[el], ref, wk.name)
 
