@@ -180,18 +180,33 @@ class RandomSmooth:
             cs /= np.sum(np.abs(cs))
             self._coef.append(cs)
 
-    def _phi(self, k, x):
-        arg = 2.0 * math.pi / self.L * (x @ self._modes.T)
-        cs = self._coef[k]
-        return np.cos(arg) @ cs[:, 0] + np.sin(arg) @ cs[:, 1]
+    def _phis(self, x, chunk=1 << 18):
+        """All dim + 2 polynomials at the points x [n][dim]: a cos(k.x) +
+        b sin(k.x) = Re((a - i b) exp(i k.x)), exp(i k.x) the product of the
+        per-direction factors (no transcendental per mode), in chunks of points."""
+        ks = np.arange(-self.kmax, self.kmax + 1, dtype=np.float64)
+        nk = ks.size
+        C = np.stack([cs[:, 0] - 1j * cs[:, 1] for cs in self._coef], axis=1)   # [mode][polynomial]
+        out = np.empty((x.shape[0], len(self._coef)))
+        w = 2.0 * math.pi / self.L
+        for s in range(0, x.shape[0], chunk):
+            xc = x[s:s + chunk]
+            e = [np.exp(1j * w * np.multiply.outer(xc[:, d], ks)) for d in range(self.dim)]
+            E = e[0]
+            for d in range(1, self.dim):   # modes in the order of itertools.product
+                E = (E[:, :, None] * e[d][:, None, :]).reshape(xc.shape[0], -1)
+            assert E.shape[1] == nk ** self.dim
+            out[s:s + chunk] = (E @ C).real
+        return out
 
     def __call__(self, x, gamma=GAMMA):
         x = np.asarray(x, dtype=np.float64)
         shp = x.shape[:-1]
         xf = x.reshape(-1, self.dim)
-        rho = 1.0 + 0.2 * self._phi(0, xf)
-        v = np.stack([0.299 / math.sqrt(3.0) * self._phi(1 + k, xf) for k in range(self.dim)], axis=-1)
-        p = 1.0 + 0.2 * self._phi(self.dim + 1, xf)
+        ph = self._phis(xf)
+        rho = 1.0 + 0.2 * ph[:, 0]
+        v = np.stack([0.299 / math.sqrt(3.0) * ph[:, 1 + k] for k in range(self.dim)], axis=-1)
+        p = 1.0 + 0.2 * ph[:, self.dim + 1]
         return prim_to_cons(rho, v, p, gamma).reshape(shp + (self.dim + 2,))
 
 
