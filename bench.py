@@ -210,9 +210,8 @@ def run_single(name: str, steps: int, warmup: int, autotune: bool = True):
     if autotune:
         plan.autotune(u)
         log(f"[bench] {name}: autotuned at {time.perf_counter() - t0:.1f}s")
-    vjp = wk.dim == 2 or wk.degree <= 8
     r = _measure(plan, u, name, [(wk.degree, plan.info.n_elements)], wk.dim, wk.ecflux, wk.dissipation, steps,
-                 warmup, vjp)
+                 warmup, True)
     log(f"[bench] {name}: measured at {time.perf_counter() - t0:.1f}s")
     r["degree"] = wk.degree
     r["k2_block_autotuned"] = plan.tuning()[0]

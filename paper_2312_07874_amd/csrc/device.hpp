@@ -193,7 +193,12 @@ __device__ __forceinline__ DevTables stage_tables(const DevTables& T, double* bu
 // after each.
 //
 // Stage layouts: triangles T1 [ec][a1][i2]; tetrahedra T1 [ec][(a1,a2)][i3],
-// T2 [ec][a1][i2 + Q i3].
+// T2 [ec][l][a1 rotated by i2] with l = i2 + Q i3: the P + 1 = Q values of
+// the eta1 line l occupy the same Q doubles as that line's nodal values, so
+// the last stage of V and the first of V^T may run in place (T2 equal to the
+// nodal array): each thread reads its whole line before writing it, and no
+// other thread touches it.  Entry a1 of line l sits at (a1 + i2) mod Q, which
+// spreads the lanes of a wave (consecutive lines) over the LDS banks.
 template <int P>
 struct Unroll {
   static constexpr int Q = P + 1;
@@ -254,7 +259,7 @@ __device__ __forceinline__ void v_first(const double* uh, double* T1, const DevT
   }
 }
 
-// V, middle stage of tetrahedra: T2[ec][a1][i2 + Q i3] = sum_a2 psi2[a1][a2][i2] T1[ec][(a1,a2)][i3]
+// V, middle stage of tetrahedra: T2(ec, a1, i2 + Q i3) = sum_a2 psi2[a1][a2][i2] T1[ec][(a1,a2)][i3]
 template <int P>
 __device__ __forceinline__ void v_second(const double* T1, double* T2, const DevTables& T, int nec) {
   using S = Shape<3, P>;
@@ -275,8 +280,10 @@ __device__ __forceinline__ void v_second(const double* T1, double* T2, const Dev
         for (int i = 0; i < Q; ++i) acc[i] += ps[i] * x;
       }
     }
+    // line l = i + Q i3 of T2, entry a1 at (a1 + i) mod Q
+    double* t2 = T2 + ((int64_t)ec * Q * Q + Q * i3) * Q;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) T2[(ec * (P + 1) + a1) * Q * Q + i + Q * i3] = acc[i];
+    for (int i = 0; i < Q; ++i) t2[i * Q + (a1 + i < Q ? a1 + i : a1 + i - Q)] = acc[i];
   }
 }
 
@@ -288,17 +295,29 @@ __device__ __forceinline__ void v_last(const double* Tin, double* out, const Dev
   constexpr int Q = S::Q, XU = Unroll<P>::XU;
   constexpr int L = DIM == 2 ? Q : Q * Q;   // lines of the last stage per (element, variable)
   const int tid = threadIdx.x, nth = blockDim.x;
-  // out[ec][i1 + Q l] = sum_a1 psi1[a1][i1] Tin[ec][a1][l]
+  // out[ec][i1 + Q l] = sum_a1 psi1[a1][i1] Tin(ec, a1, l); on tetrahedra Tin
+  // may equal out (the line is read whole before it is written)
   for (int o = tid; o < nec * L; o += nth) {
     const int l = o % L, ec = o / L;
     double acc[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) acc[i] = 0.0;
+    if constexpr (DIM == 3) {
+      const double* t = Tin + (int64_t)o * Q;
+      const int r = l % Q;
 #pragma unroll XU
-    for (int a1 = 0; a1 <= P; ++a1) {
-      const double x = Tin[(ec * (P + 1) + a1) * L + l];
+      for (int a1 = 0; a1 <= P; ++a1) {
+        const double x = t[a1 + r < Q ? a1 + r : a1 + r - Q];
 #pragma unroll
-      for (int i = 0; i < Q; ++i) acc[i] += T.psi1[a1 * Q + i] * x;
+        for (int i = 0; i < Q; ++i) acc[i] += T.psi1[a1 * Q + i] * x;
+      }
+    } else {
+#pragma unroll XU
+      for (int a1 = 0; a1 <= P; ++a1) {
+        const double x = Tin[(ec * (P + 1) + a1) * L + l];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) acc[i] += T.psi1[a1 * Q + i] * x;
+      }
     }
 #pragma unroll
     for (int i = 0; i < Q; ++i) out[ec * S::NQ + i + Q * l] = acc[i];
@@ -312,7 +331,8 @@ __device__ __forceinline__ void vt_first(const double* in, double* Tout, const D
   constexpr int Q = S::Q, XU = Unroll<P>::XU;
   constexpr int L = DIM == 2 ? Q : Q * Q;
   const int tid = threadIdx.x, nth = blockDim.x;
-  // Tout[ec][a1][l] = sum_i1 psi1[a1][i1] in[ec][i1 + Q l]
+  // Tout(ec, a1, l) = sum_i1 psi1[a1][i1] in[ec][i1 + Q l]; on tetrahedra Tout
+  // may equal in (the line is read whole before it is written)
   for (int o = tid; o < nec * L; o += nth) {
     const int l = o % L, ec = o / L;
     double acc[P + 1];
@@ -324,12 +344,19 @@ __device__ __forceinline__ void vt_first(const double* in, double* Tout, const D
 #pragma unroll
       for (int a = 0; a <= P; ++a) acc[a] += T.psi1[a * Q + i1] * x;
     }
+    if constexpr (DIM == 3) {
+      double* t = Tout + (int64_t)o * Q;
+      const int r = l % Q;
 #pragma unroll
-    for (int a = 0; a <= P; ++a) Tout[(ec * (P + 1) + a) * L + l] = acc[a];
+      for (int a = 0; a <= P; ++a) t[a + r < Q ? a + r : a + r - Q] = acc[a];
+    } else {
+#pragma unroll
+      for (int a = 0; a <= P; ++a) Tout[(ec * (P + 1) + a) * L + l] = acc[a];
+    }
   }
 }
 
-// V^T, middle stage of tetrahedra: T1[ec][(a1,a2)][i3] = sum_i2 psi2[a1][a2][i2] T2[ec][a1][i2 + Q i3]
+// V^T, middle stage of tetrahedra: T1[ec][(a1,a2)][i3] = sum_i2 psi2[a1][a2][i2] T2(ec, a1, i2 + Q i3)
 template <int P>
 __device__ __forceinline__ void vt_second(const double* T2, double* T1, const DevTables& T, int nec) {
   using S = Shape<3, P>;
@@ -341,9 +368,10 @@ __device__ __forceinline__ void vt_second(const double* T2, double* T1, const De
     double acc[P + 1];
 #pragma unroll
     for (int a = 0; a <= P; ++a) acc[a] = 0.0;
+    const double* t2 = T2 + ((int64_t)ec * Q * Q + Q * i3) * Q;
 #pragma unroll XL
     for (int i2 = 0; i2 < Q; ++i2) {
-      const double x = T2[(ec * (P + 1) + a1) * Q * Q + i2 + Q * i3];
+      const double x = t2[i2 * Q + (a1 + i2 < Q ? a1 + i2 : a1 + i2 - Q)];
 #pragma unroll
       for (int a = 0; a <= P; ++a) acc[a] += T.psi2[(a1 * (P + 1) + a) * Q + i2] * x;
     }

@@ -41,7 +41,7 @@ __device__ __forceinline__ void weight_adjusted_projection(double* sM, double* s
   constexpr int NC = Sh::NC, NQ = Sh::NQ, NGV = Sh::NGV;
   const int nec = nel * NC;
   double* T1 = sS;
-  double* T2 = sS + EPB * Sh::T1;
+  double* T2 = sA;   // the tetrahedral middle layout runs in place over the nodal values
   auto ld_wi = [&](int o) { return gvol[((e0 + o / NQ) * NGV + NGV - 1) * NQ + o % NQ]; };
   if constexpr (VVT) {
     xform_VVt<DIM, P>(sA, T1, T2, sA, T, nec);
@@ -74,7 +74,7 @@ __device__ __forceinline__ void project_block(double* sM, double* sA, double* sS
   const int nec = nel * NC;
   const int tid = threadIdx.x, nth = blockDim.x;
   double* T1 = sS;
-  double* T2 = sS + EPB * Sh::T1;
+  double* T2 = sA;
   auto ld_wJ = [&](int o) { return gvol[((e0 + o / NQ) * NGV + NGV - 2) * NQ + o % NQ]; };
   xform_V<DIM, P>(sM, T1, T2, sA, T, nec);
   // entropy variables times w J at every volume node
@@ -114,10 +114,17 @@ k_entropy_projection(const double* __restrict__ u, double* __restrict__ wt, doub
   using Sh = Shape<DIM, P>;
   constexpr int EPB = Launch<DIM, P>::EPB;
   constexpr int NC = Sh::NC, NQ = Sh::NQ, NP = Sh::NP, NGV = Sh::NGV;
-  __shared__ double sM[EPB * NC * NP];
+  // the modal arrays share sA's storage: each transform reads its input in
+  // its first stage and writes its output in its last, so the modal input of
+  // V and the modal output of V^T never coexist with the nodal values; the
+  // tetrahedral middle stage runs in place over sA too, so the transform
+  // scratch is the first stage's alone (which also holds the facet scratch)
   __shared__ double sA[EPB * NC * NQ];
-  __shared__ double sS[EPB * Sh::XSCR];
-  constexpr int KB = 8 * EPB * (NC * NP + NC * NQ + Sh::XSCR);
+  __shared__ double sS[EPB * Sh::T1];
+  double* const sM = sA;
+  static_assert(NP <= NQ, "modal arrays fit in the nodal array");
+  static_assert(DIM == 2 || Sh::T1 >= NC * Sh::Q * Sh::Q, "facet scratch fits in the transform scratch");
+  constexpr int KB = 8 * EPB * (NC * NQ + Sh::T1);
   // the composed V V^T table only where it keeps the workgroups per CU; where
   // the two PKD tables do not fit (tetrahedra at p = 10), psi2 alone
   constexpr unsigned TM0 = tab_keeps_wgs<DIM, P, TAB_PSI | TAB_FACET, TAB_PSI | TAB_FACET | TAB_PSIM>(KB, wave_cap<DIM, P>())
