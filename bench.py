@@ -237,7 +237,7 @@ def run_batched(steps: int, warmup: int, autotune: bool = True):
     plan.sync_status()
     blocks = plan.autotune(u) if autotune else plan.tuning()
     buckets = [(int(b["degree"]), int(b["n_elements"])) for b in plan.buckets]
-    r = _measure(plan, u, bt.name, buckets, 3, bt.ecflux, bt.dissipation, steps, warmup, False)
+    r = _measure(plan, u, bt.name, buckets, 3, bt.ecflux, bt.dissipation, steps, warmup, True)
     r["buckets"] = [list(b) for b in buckets]
     r["k2_blocks_autotuned"] = list(blocks)
     return r, plan, u

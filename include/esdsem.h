@@ -161,9 +161,13 @@ typedef struct {
  * [bucket][element-in-bucket][variable][mode], nodal arrays (esd_project,
  * esd_node_coords) are [bucket][element-in-bucket][node][...]; offsets from
  * esd_plan_buckets.  esd_residual, esd_rk4, esd_project, esd_node_coords,
- * esd_diagnostics and esd_sync_status accept it; the VJP entry points return
- * ESD_EUNSUPPORTED and esd_plan_host_array ESD_EINVAL.  Errors as
- * esd_plan_create. */
+ * esd_diagnostics, esd_sync_status and the VJP entry points accept it (the
+ * VJP also differentiates the exterior values of mixed-degree facets with
+ * respect to the neighbour's w~); esd_plan_host_array returns ESD_EINVAL.
+ * Its VJP workspace is the residual workspace followed by, per bucket, the
+ * exterior cotangents (n_elements N_c N_fq doubles, 256-byte aligned) and
+ * then, per bucket, the adjoint kernels' slices (tetrahedra at p = 9, 10).
+ * Errors as esd_plan_create. */
 esd_status esd_plan_create_batched(const esd_batch_desc* batch, const esd_scheme_desc* scheme, uint32_t flags,
                                    esd_plan** out);
 esd_status esd_plan_create_batched_ex(const esd_batch_desc* batch, const esd_scheme_desc* scheme, uint32_t flags,

@@ -459,9 +459,6 @@ class BatchedPlan(Plan):
         _check(_lib.esd_node_coords(self._h, _ptr(x), _stream()), "esd_node_coords")
         return x
 
-    def vjp(self, *a, **k):
-        raise EsdError(-4, "BatchedPlan.vjp")
-
 
 def _autograd_residual():
     import torch

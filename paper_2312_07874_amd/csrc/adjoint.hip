@@ -457,11 +457,16 @@ k_projection_vjp(const double* __restrict__ u, double* g, const double* __restri
 
   // ---- cotangents of this element's facet values written by its neighbours:
   //      the facet permutation is an involution, so the neighbour of node j
-  //      stored them at the address conn gives for j
+  //      stored them at the address conn gives for j.  In a mixed-degree
+  //      batch, a facet whose neighbour has another degree points at this
+  //      element's exterior slot (addresses from ne NC NFQ on): that neighbour
+  //      reads this element's w~, not its facet values, so nothing is gathered
+  //      there (its cotangent reaches w~_bar through the mixed-interface adjoint)
+  const int64_t own_end = ne * NC * NFQ;
   for (int o = tid; o < nec * NFQ; o += nth) {
     const int j = o % NFQ, c = (o / NFQ) % NC, el = o / (NC * NFQ);
     const int32_t addr = conn[(e0 + el) * NFQ + j];
-    sB[o] = xbar[addr + c * NFQ];
+    sB[o] = addr < own_end ? xbar[addr + c * NFQ] : 0.0;
   }
   __syncthreads();
   facet_lift<DIM, P>(sB, sS, T, nec, [&](int o, double d) { sA[o] = d; });
@@ -525,22 +530,26 @@ __global__ void k_scale(double* __restrict__ y, const double* __restrict__ x, do
 }
 
 // ------------------------------------------------------------------ dispatch
+// VK2 (which = 0) or VK1 (which = 1) of one plan; K1 (and, in a batch, the
+// mixed-interface exterior values) must have run before VK2
 template <int DIM, int P>
-static int run_vjp(const esd_plan* pl, const double* u, const double* vbar, double* grad, Workspace ws,
-                   hipStream_t s) {
+static int run_vjp_part(const esd_plan* pl, int which, const double* u, const double* vbar, double* grad,
+                        Workspace ws, hipStream_t s) {
   using L = VjpLaunch<DIM, P>;
   const int64_t nb = (pl->ne + L::EPB - 1) / L::EPB;
-  int rc = launch_entropy_projection(pl, u, ws, s);
-  if (rc != 0) return rc;
-  if (pl->scheme.ecflux == FLUX_RANOCHA)
-    hipLaunchKernelGGL((k_rhs_vjp<DIM, P, FLUX_RANOCHA>), dim3(nb), dim3(L::BS), 0, s, ws.wt, ws.wf, vbar, grad,
-                       ws.xbar, pl->d_gvol, pl->d_gfac, pl->d_conn, pl->tab, pl->scheme, pl->ne, pl->d_flag, ws.vscr);
-  else
-    hipLaunchKernelGGL((k_rhs_vjp<DIM, P, FLUX_CHANDRASHEKAR>), dim3(nb), dim3(L::BS), 0, s, ws.wt, ws.wf, vbar,
-                       grad, ws.xbar, pl->d_gvol, pl->d_gfac, pl->d_conn, pl->tab, pl->scheme, pl->ne, pl->d_flag,
-                       ws.vscr);
-  hipLaunchKernelGGL((k_projection_vjp<DIM, P>), dim3(nb), dim3(L::BS), 0, s, u, grad, ws.xbar, pl->d_gvol,
-                     pl->d_conn, pl->tab, pl->scheme, pl->ne, ws.vscr);
+  if (which == 0) {
+    if (pl->scheme.ecflux == FLUX_RANOCHA)
+      hipLaunchKernelGGL((k_rhs_vjp<DIM, P, FLUX_RANOCHA>), dim3(nb), dim3(L::BS), 0, s, ws.wt, ws.wf, vbar, grad,
+                         ws.xbar, pl->d_gvol, pl->d_gfac, pl->d_conn, pl->tab, pl->scheme, pl->ne, pl->d_flag,
+                         ws.vscr);
+    else
+      hipLaunchKernelGGL((k_rhs_vjp<DIM, P, FLUX_CHANDRASHEKAR>), dim3(nb), dim3(L::BS), 0, s, ws.wt, ws.wf, vbar,
+                         grad, ws.xbar, pl->d_gvol, pl->d_gfac, pl->d_conn, pl->tab, pl->scheme, pl->ne, pl->d_flag,
+                         ws.vscr);
+  } else {
+    hipLaunchKernelGGL((k_projection_vjp<DIM, P>), dim3(nb), dim3(L::BS), 0, s, u, grad, ws.xbar, pl->d_gvol,
+                       pl->d_conn, pl->tab, pl->scheme, pl->ne, ws.vscr);
+  }
   return (int)hipGetLastError();
 }
 
@@ -553,13 +562,22 @@ int vjp_scratch_doubles(int dim, int p) {
   return 0;
 }
 
-int launch_vjp(const esd_plan* pl, const double* u, const double* vbar, double* grad, Workspace ws, hipStream_t s) {
+int launch_vjp_part(const esd_plan* pl, int which, const double* u, const double* vbar, double* grad, Workspace ws,
+                    hipStream_t s) {
 #define X(D, PP) \
-  if (pl->dim == D && pl->p == PP) return run_vjp<D, PP>(pl, u, vbar, grad, ws, s);
+  if (pl->dim == D && pl->p == PP) return run_vjp_part<D, PP>(pl, which, u, vbar, grad, ws, s);
   ESD_TRI_DEGREES(X)
   ESD_TET_VJP_DEGREES(X)
 #undef X
   return -1;
+}
+
+int launch_vjp(const esd_plan* pl, const double* u, const double* vbar, double* grad, Workspace ws, hipStream_t s) {
+  if (!vjp_degree_supported(pl->dim, pl->p)) return -1;
+  int rc = launch_entropy_projection(pl, u, ws, s);
+  if (rc == 0) rc = launch_vjp_part(pl, 0, u, vbar, grad, ws, s);
+  if (rc == 0) rc = launch_vjp_part(pl, 1, u, vbar, grad, ws, s);
+  return rc;
 }
 
 int launch_adj_stage(double* acc, double* kb, const double* ubar, const double* G, double cu, double cg, int first,

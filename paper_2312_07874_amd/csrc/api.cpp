@@ -77,9 +77,12 @@ void free_device(esd_plan* p) {
   dev_free(p, p->d_mats);
   dev_free(p, p->d_mat_off);
   dev_free(p, p->d_wt_off);
+  dev_free(p, p->d_arecs);
+  dev_free(p, p->d_asegs);
+  dev_free(p, p->d_xbar_off);
   p->d_tables = p->d_gvol = p->d_gfac = p->d_xvol = p->d_mats = nullptr;
-  p->d_conn = p->d_tasks = nullptr;
-  p->d_mat_off = p->d_wt_off = nullptr;
+  p->d_conn = p->d_tasks = p->d_arecs = p->d_asegs = nullptr;
+  p->d_mat_off = p->d_wt_off = p->d_xbar_off = nullptr;
   p->d_flag = nullptr;
 }
 
@@ -394,7 +397,9 @@ esd_status esd_plan_create_batched(const esd_batch_desc* d, const esd_scheme_des
       }
       P->sub.push_back(sp);
     }
-    // ---- facet permutation tables, mixed-interface tasks and matrices
+    // ---- facet permutation tables, mixed-interface tasks and matrices; the
+    //      adjoint records of each task, keyed by the element whose w~ it reads
+    std::vector<std::map<int64_t, std::vector<std::array<int32_t, 8>>>> arec(nb_);
     std::map<std::array<int, 4>, int> matid;
     std::vector<double> mats;
     std::vector<int64_t> mat_off;
@@ -453,12 +458,41 @@ esd_status esd_plan_create_batched(const esd_batch_desc* d, const esd_scheme_des
           }
           const int32_t t[8] = {(int32_t)i, f, bn, (int32_t)in, it->second, 0, esd::n_modes(dim, pn), 0};
           tasks.insert(tasks.end(), t, t + 8);
+          arec[bn][in].push_back({b, (int32_t)i, f, it->second, (int32_t)in, NQF, NFQ, 0});
         }
       }
       sp->n_tasks = (int64_t)tasks.size() / 8;
+      // the VJP gathers exterior cotangents through the same permutation on
+      // facets between equal degrees: it must pair those nodes both ways
+      sp->conn_involutive = true;
+      for (int64_t i = 0; i < ne_b && sp->conn_involutive; ++i)
+        for (int j = 0; j < NFQ; ++j) {
+          const int64_t a = conn[i * NFQ + j];
+          if (a >= ne_b * stride) continue;   // exterior slot of a mixed-degree facet
+          const int64_t i2 = a / stride, j2 = a % stride;
+          if (j2 >= NFQ || conn[i2 * NFQ + j2] != (int32_t)(i * stride + j)) {
+            sp->conn_involutive = false;
+            break;
+          }
+        }
       if (!host_only) {
         esd_status st = upload(sp, &sp->d_conn, conn);
         if (st == ESD_OK && !tasks.empty()) st = upload(sp, &sp->d_tasks, tasks);
+        if (st != ESD_OK) return bail(st, "upload failed");
+      }
+    }
+    for (int b = 0; b < nb_; ++b) {
+      esd_plan* sp = P->sub[b];
+      std::vector<int32_t> recs, segs;
+      for (const auto& kv : arec[b]) {   // target slots in increasing order
+        segs.push_back((int32_t)(recs.size() / 8));
+        segs.push_back((int32_t)kv.second.size());
+        for (const auto& r : kv.second) recs.insert(recs.end(), r.begin(), r.end());
+      }
+      sp->n_asegs = (int64_t)segs.size() / 2;
+      if (!host_only && sp->n_asegs > 0) {
+        esd_status st = upload(sp, &sp->d_arecs, recs);
+        if (st == ESD_OK) st = upload(sp, &sp->d_asegs, segs);
         if (st != ESD_OK) return bail(st, "upload failed");
       }
     }
@@ -481,13 +515,30 @@ esd_status esd_plan_create_batched(const esd_batch_desc* d, const esd_scheme_des
     P->ws_bytes = ws;
     P->rk_ws_bytes = 2 * ws + 3 * align256(ndof * sizeof(double));
     P->fuse_next = dim == 2;
-    P->vjp_ws_bytes = P->rk_vjp_ws_bytes = 0;
+    // VJP: the residual workspace, every bucket's x_bar, every bucket's slices
+    P->xbar_off.assign(nb_, 0);
+    P->vscr_off.assign(nb_, 0);
+    std::vector<int64_t> xbar_off(nb_);
+    size_t vws = ws;
+    for (int b = 0; b < nb_; ++b) {
+      const esd_plan* sp = P->sub[b];
+      P->xbar_off[b] = vws;
+      xbar_off[b] = (int64_t)(vws / sizeof(double));
+      vws += align256((size_t)sp->ne * nc * sp->ref.NFQ * sizeof(double));
+    }
+    for (int b = 0; b < nb_; ++b) {
+      P->vscr_off[b] = vws;
+      vws += align256(P->sub[b]->vscr_bytes);
+    }
+    P->vjp_ws_bytes = vws;
+    P->rk_vjp_ws_bytes = vws + 3 * align256(ndof * sizeof(double));
     if (!host_only) {
       if (hipGetDevice(&P->device) != hipSuccess) return bail(ESD_EHIP, "no HIP device");
       esd_status st = upload(P, &P->d_flag, std::vector<int>(1, 0));
       if (st == ESD_OK && !mats.empty()) st = upload(P, &P->d_mats, mats);
       if (st == ESD_OK && !mat_off.empty()) st = upload(P, &P->d_mat_off, mat_off);
       if (st == ESD_OK) st = upload(P, &P->d_wt_off, wt_off);
+      if (st == ESD_OK) st = upload(P, &P->d_xbar_off, xbar_off);
       if (st != ESD_OK) return bail(st, "upload failed");
       for (esd_plan* sp : P->sub) {
         dev_free(sp, sp->d_flag);
@@ -593,6 +644,8 @@ esd_status esd_plan_query(const esd_plan* P, esd_plan_info* out) {
     }
     out->workspace_bytes = P->ws_bytes;
     out->rk4_workspace_bytes = P->rk_ws_bytes;
+    out->vjp_workspace_bytes = P->vjp_ws_bytes;
+    out->rk4_vjp_workspace_bytes = P->rk_vjp_ws_bytes;
     return ESD_OK;
   }
   const esd::RefTables& R = P->ref;
@@ -1090,6 +1143,49 @@ esd_status esd_plan_get_tuning(const esd_plan* P, int32_t* k2_block, int32_t cap
   return ESD_OK;
 }
 
+// what the VJP entry points need of a plan (every bucket of a batch)
+static esd_status vjp_check(const esd_plan* P) {
+  if (P->scheme.dissipation > 1)
+    return fail(ESD_EUNSUPPORTED, "VJP built for the entropy-conservative and Lax-Friedrichs interface fluxes");
+  const int nbk = P->batched ? (int)P->sub.size() : 1;
+  for (int b = 0; b < nbk; ++b) {
+    const esd_plan* B = P->batched ? P->sub[b] : P;
+    if (!B->conn_involutive) return fail(ESD_EUNSUPPORTED, "facet permutation is not an involution");
+    if (!esd::vjp_degree_supported(B->dim, B->p)) return fail(ESD_EUNSUPPORTED, "VJP not built for this degree");
+  }
+  return ESD_OK;
+}
+
+// the VJP workspace slices of bucket b of a batch
+static esd::Workspace vjp_ws_bucket(const esd_plan* P, int b, void* ws) {
+  esd::Workspace w = split_ws(P->sub[b], (char*)ws + P->ws_off[b]);
+  w.xbar = (double*)((char*)ws + P->xbar_off[b]);
+  w.vscr = (double*)((char*)ws + P->vscr_off[b]);
+  return w;
+}
+
+// one VJP; for a batch: K1 of every bucket, the mixed-interface exterior
+// values, VK2 of every bucket, the mixed-interface adjoint (into the w~_bar
+// of the elements the exterior values were read from), VK1 of every bucket
+static int vjp_any(const esd_plan* P, const double* u, const double* vbar, double* grad, void* ws, hipStream_t s) {
+  if (!P->batched) return esd::launch_vjp(P, u, vbar, grad, split_ws(P, ws), s);
+  const int nb = (int)P->sub.size();
+  int rc = 0;
+  for (int b = 0; b < nb && rc == 0; ++b)
+    rc = esd::launch_entropy_projection(P->sub[b], u + P->dof_off[b], vjp_ws_bucket(P, b, ws), s);
+  for (int b = 0; b < nb && rc == 0; ++b)
+    rc = esd::launch_mixed_exterior(P->sub[b], P, (const double*)ws, vjp_ws_bucket(P, b, ws), s);
+  for (int b = 0; b < nb && rc == 0; ++b)
+    rc = esd::launch_vjp_part(P->sub[b], 0, u + P->dof_off[b], vbar + P->dof_off[b], grad + P->dof_off[b],
+                              vjp_ws_bucket(P, b, ws), s);
+  for (int b = 0; b < nb && rc == 0; ++b)
+    rc = esd::launch_mixed_exterior_vjp(P->sub[b], P, (const double*)ws, grad + P->dof_off[b], s);
+  for (int b = 0; b < nb && rc == 0; ++b)
+    rc = esd::launch_vjp_part(P->sub[b], 1, u + P->dof_off[b], vbar + P->dof_off[b], grad + P->dof_off[b],
+                              vjp_ws_bucket(P, b, ws), s);
+  return rc;
+}
+
 esd_status esd_residual_vjp(const esd_plan* P, const double* u_dev, const double* vbar_dev, double* grad_dev,
                             void* ws_dev, void* stream) {
   esd_status st = check_device(P);
@@ -1098,12 +1194,9 @@ esd_status esd_residual_vjp(const esd_plan* P, const double* u_dev, const double
   if ((const void*)grad_dev == (const void*)u_dev || (const void*)grad_dev == (const void*)vbar_dev)
     return fail(ESD_EINVAL, "grad overlaps u or vbar");
   if (((uintptr_t)ws_dev) % 256 != 0) return fail(ESD_EINVAL, "workspace not 256-byte aligned");
-  if (P->batched) return fail(ESD_EUNSUPPORTED, "VJP of a batched plan");
-  if (P->scheme.dissipation > 1)
-    return fail(ESD_EUNSUPPORTED, "VJP built for the entropy-conservative and Lax-Friedrichs interface fluxes");
-  if (!P->conn_involutive) return fail(ESD_EUNSUPPORTED, "facet permutation is not an involution");
-  if (!esd::vjp_degree_supported(P->dim, P->p)) return fail(ESD_EUNSUPPORTED, "VJP not built for this degree");
-  const int rc = esd::launch_vjp(P, u_dev, vbar_dev, grad_dev, split_ws(P, ws_dev), (hipStream_t)stream);
+  st = vjp_check(P);
+  if (st != ESD_OK) return st;
+  const int rc = vjp_any(P, u_dev, vbar_dev, grad_dev, ws_dev, (hipStream_t)stream);
   if (rc < 0) return fail(ESD_EUNSUPPORTED, "degree not built");
   if (rc != 0) return fail(ESD_EHIP, std::string("VJP launch failed: ") + hipGetErrorString((hipError_t)rc));
   return ESD_OK;
@@ -1116,15 +1209,11 @@ esd_status esd_rk4_vjp(const esd_plan* P, const double* stage_ckpt_dev, double d
   if (!stage_ckpt_dev || !ubar_dev || !ws_dev || nsteps < 0 || !std::isfinite(dt))
     return fail(ESD_EINVAL, "bad argument");
   if (((uintptr_t)ws_dev) % 256 != 0) return fail(ESD_EINVAL, "workspace not 256-byte aligned");
-  if (P->scheme.dissipation > 1)
-    return fail(ESD_EUNSUPPORTED, "VJP built for the entropy-conservative and Lax-Friedrichs interface fluxes");
-  if (P->batched) return fail(ESD_EUNSUPPORTED, "VJP of a batched plan");
-  if (!P->conn_involutive) return fail(ESD_EUNSUPPORTED, "facet permutation is not an involution");
-  if (!esd::vjp_degree_supported(P->dim, P->p)) return fail(ESD_EUNSUPPORTED, "VJP not built for this degree");
+  st = vjp_check(P);
+  if (st != ESD_OK) return st;
   hipStream_t s = (hipStream_t)stream;
-  const int64_t n = P->ne * P->nc * P->ref.NP;
+  const int64_t n = total_dof(P);
   const size_t nb = align256((size_t)n * sizeof(double));
-  esd::Workspace w = split_ws(P, ws_dev);
   double* kb = (double*)((char*)ws_dev + P->vjp_ws_bytes);
   double* G = (double*)((char*)ws_dev + P->vjp_ws_bytes + nb);
   double* acc = (double*)((char*)ws_dev + P->vjp_ws_bytes + 2 * nb);
@@ -1135,7 +1224,7 @@ esd_status esd_rk4_vjp(const esd_plan* P, const double* stage_ckpt_dev, double d
     int rc = esd::launch_scale(kb, ubar_dev, cu[3], n, s);
     for (int stg = 3; stg >= 0 && rc == 0; --stg) {
       const double* U = stage_ckpt_dev + ((int64_t)4 * step + stg) * n;
-      rc = esd::launch_vjp(P, U, kb, G, w, s);
+      rc = vjp_any(P, U, kb, G, ws_dev, s);
       if (rc != 0) break;
       if (stg > 0)
         rc = esd::launch_adj_stage(acc, kb, ubar_dev, G, cu[stg - 1], cs[stg - 1], stg == 3, n, s);

@@ -111,6 +111,11 @@ struct esd_plan {
   bool wext = false;
   int32_t* d_tasks = nullptr;     // [n_tasks][8] mixed-interface tasks (see batch.hip)
   int64_t n_tasks = 0;
+  // their adjoint, gathered per element of this bucket that some task reads
+  // (see batch.hip): records [n_arecs][8], segments [n_asegs][2] (first, count)
+  int32_t* d_arecs = nullptr;
+  int32_t* d_asegs = nullptr;
+  int64_t n_asegs = 0;
   // batched plan: container of one single-degree plan per bucket
   bool batched = false;
   std::vector<esd_plan*> sub;
@@ -122,6 +127,10 @@ struct esd_plan {
   double* d_mats = nullptr;       // mixed-interface evaluation matrices
   int64_t* d_mat_off = nullptr;   // [n_mats] offsets into d_mats
   int64_t* d_wt_off = nullptr;    // [nb] offsets (doubles) of each bucket's w~ in the workspace
+  // VJP workspace of a batch: the residual workspace, then per bucket its
+  // x_bar (ne NC NFQ doubles) and its adjoint scratch slices
+  std::vector<size_t> xbar_off, vscr_off;   // [nb] bytes from the workspace start
+  int64_t* d_xbar_off = nullptr;  // [nb] the x_bar offsets in doubles
   int k2_block = 0;               // right-hand-side block size chosen by esd_plan_autotune (0: default)
   int k1_block = 0;               // entropy-projection block size chosen likewise
   // RK4 steps replayed from a captured graph (no checkpoints, no timing)
@@ -159,6 +168,9 @@ int launch_entropy_projection(const esd_plan* P, const double* u, Workspace ws, 
 // adjoint.hip
 int launch_vjp(const esd_plan* P, const double* u, const double* vbar, double* grad, Workspace ws,
                hipStream_t s);
+// VK2 (which = 0: partial w~_bar into grad, x_bar) or VK1 (which = 1) alone
+int launch_vjp_part(const esd_plan* P, int which, const double* u, const double* vbar, double* grad, Workspace ws,
+                    hipStream_t s);
 int launch_adj_stage(double* acc, double* kb, const double* ubar, const double* G, double cu, double cg, int first,
                      int64_t n, hipStream_t s);
 int launch_scale(double* y, const double* x, double a, int64_t n, hipStream_t s);
@@ -167,6 +179,10 @@ int launch_rhs(const esd_plan* P, double* dudt, Workspace ws, hipStream_t s, con
 // batch.hip: exterior facet values of mixed-degree interfaces of one bucket
 int launch_mixed_exterior(const esd_plan* bucket, const esd_plan* top, const double* ws_base, Workspace ws,
                           hipStream_t s);
+// and its adjoint: w~_bar of this bucket's elements (grad, the bucket's slice)
+// += I^T x_bar of the facets that read them (VJP workspace at ws_base)
+int launch_mixed_exterior_vjp(const esd_plan* bucket, const esd_plan* top, const double* ws_base, double* grad,
+                              hipStream_t s);
 hipEvent_t timing_event(const esd_plan* pl, hipStream_t s);
 // diagnostics.hip: part [ne][dim+4] partial sums, out [dim+4] (device)
 int launch_diagnostics(const esd_plan* P, const double* u, const double* dudt, double* part, double* out,

@@ -224,3 +224,158 @@ def test_batched_rk4_step_matches_oracle():
         scale = np.maximum(scale, ref[e].abs().amax(1).numpy())
     log(f"batched RK4 step: max err / ||u_e||_inf per var {['%.1e' % x for x in err / scale]}")
     assert float((err / scale).max()) <= 1e-12
+
+
+# ---------------------------------------------------------------- VJP of batched plans
+def _flat_state(plan, meshes, degrees, utss):
+    """One flat batched state from the oracle's per-degree tensors."""
+    u = torch.zeros(plan.state_shape, dtype=torch.float64)
+    base = 0
+    for k, (m, deg) in enumerate(zip(meshes, degrees)):
+        for e in range(m.n_elements):
+            g = base + e
+            b, s = int(plan.elem_bucket[g]), int(plan.elem_slot[g])
+            plan.bucket_view(u, b)[s] = utss[k][int(deg[e])][e]
+        base += m.n_elements
+    return u
+
+
+def _mixed_oracle_vjp(mp, uts, vbar_of, elems):
+    """Rows elems of (dR/du~)^T vbar for the oracle's mixed-degree residual, by
+    reverse-mode autodiff: the residual is evaluated on the 1-ring of elems
+    (every element whose residual reads their w~: face neighbours, across a
+    change of degree too), vbar_of(e) the cotangent of element e."""
+    con = next(iter(mp.probs.values())).con
+    elems = np.asarray(elems, dtype=np.int64)
+    ring = np.unique(np.concatenate([elems, con.nbr_elem[elems].reshape(-1)]))
+    leaves = {p: t.detach().clone().requires_grad_(True) for p, t in uts.items()}
+    from oracle import mixed as MX
+    res = MX.residual(mp, leaves, ring)
+    obj = sum((r * vbar_of(int(e))).sum() for r, e in zip(res, ring))
+    grads = torch.autograd.grad(obj, list(leaves.values()), allow_unused=True)
+    gd = {p: (g if g is not None else torch.zeros_like(leaves[p])) for p, g in zip(leaves, grads)}
+    return [gd[int(mp.degrees[e])][e] for e in elems]
+
+
+def _vjp_compare(dim, meshes, degrees, warp, state, ecflux, diss, what, sample=None, seed=71):
+    from oracle import mixed as MX
+    plan = batched(dim, meshes, degrees, warp, ecflux, diss)
+    log(f"batched VJP {what}: buckets {[(b['degree'], b['n_elements']) for b in plan.buckets]}")
+    mps = [MX.setup(m, d, warp, 1.4, ecflux, diss) for m, d in zip(meshes, degrees)]
+    utss = [MX.project(mp, state) for mp in mps]
+    u = _flat_state(plan, meshes, degrees, utss)
+    vbar = torch.randn(plan.state_shape, generator=torch.Generator().manual_seed(seed), dtype=torch.float64)
+    g = plan.vjp(u.cuda().contiguous(), vbar.cuda().contiguous())
+    plan.sync_status()
+    g = g.cpu()
+    nc = plan.info.n_vars
+    worst = 0.0
+    base = 0
+    for k, (m, deg) in enumerate(zip(meshes, degrees)):
+        def vbar_of(e, base=base):
+            b, s = int(plan.elem_bucket[base + e]), int(plan.elem_slot[base + e])
+            return plan.bucket_view(vbar, b)[s]
+        el = np.arange(m.n_elements) if sample is None else np.asarray(sample)
+        ref = _mixed_oracle_vjp(mps[k], utss[k], vbar_of, el)
+        err, scale = np.zeros(nc), np.zeros(nc)
+        for i, e in enumerate(el):
+            b, s = int(plan.elem_bucket[base + e]), int(plan.elem_slot[base + e])
+            got = plan.bucket_view(g, b)[s]
+            scale = np.maximum(scale, ref[i].abs().amax(1).numpy())
+            err = np.maximum(err, (got - ref[i]).abs().amax(1).numpy())
+        log(f"batched VJP {what} mesh {k}: max err / ||g_e||_inf per var {['%.2e' % x for x in err / scale]}")
+        worst = max(worst, float((err / scale).max()))
+        base += m.n_elements
+    assert worst <= 1e-12, worst
+    return plan
+
+
+@pytest.mark.parametrize("dim,M,lo,hi,ecflux,diss", [(2, 3, 1, 5, 0, 1), (3, 3, 1, 4, 0, 1), (3, 3, 2, 4, 1, 0)])
+def test_batched_vjp_parity_with_oracle(dim, M, lo, hi, ecflux, diss):
+    """The batched VJP (with the adjoint of the mixed-degree exterior values)
+    against reverse-mode autodiff of the oracle's mixed-degree residual, every
+    element, 1e-12 per variable relative to ||g_e||_inf."""
+    L = 2.0 if dim == 2 else 2 * math.pi
+    warp = wl.make_warp_sinprod(L, 0.05)
+    mesh = wl.split_box_mesh(dim, M, L)
+    deg = wl.mixed_degrees(mesh.n_elements, 31 + dim, lo, hi)
+    _vjp_compare(dim, [mesh], [deg], warp, wl.RandomSmooth(dim, L, 6), ecflux, diss, f"dim{dim}_p{lo}-{hi}")
+
+
+def test_batched_vjp_two_meshes_and_high_degrees_sampled():
+    """Two triangle meshes in one batch in full; tetrahedra at degrees 5..10 on
+    6 sampled elements (the oracle differentiates their 1-ring)."""
+    L = 2.0
+    warp = wl.make_warp_sinprod(L, 0.05)
+    m1, m2 = wl.split_box_mesh(2, 3, L), wl.split_box_mesh(2, 4, L)
+    d1, d2 = wl.mixed_degrees(m1.n_elements, 41, 1, 4), wl.mixed_degrees(m2.n_elements, 42, 2, 6)
+    _vjp_compare(2, [m1, m2], [d1, d2], warp, wl.RandomSmooth(2, L, 9), 0, 1, "two meshes")
+    L = 2 * math.pi
+    warp = wl.make_warp_sinprod(L, 0.05)
+    mesh = wl.split_box_mesh(3, 3, L)
+    deg = wl.mixed_degrees(mesh.n_elements, 43, 5, 10)
+    el = np.random.default_rng(4).choice(mesh.n_elements, 6, replace=False)
+    _vjp_compare(3, [mesh], [deg], warp, wl.RandomSmooth(3, L, 6), 0, 1, "dim3_p5-10", sample=el)
+
+
+def test_batched_vjp_equal_degree_buckets_equal_the_single_plans():
+    """Buckets that each cover a whole mesh of one degree: the batched VJP is
+    the single-degree plans' VJP (no mixed-degree facet), up to the order of
+    the LDS atomic sums."""
+    import paper_2312_07874_amd as esd
+    L = 2 * math.pi
+    warp = wl.make_warp_sinprod(L, 0.05)
+    st = wl.RandomSmooth(3, L, 3)
+    m1, m2 = wl.split_box_mesh(3, 3, L), wl.split_box_mesh(3, 4, L)
+    plan = batched(3, [m1, m2], [np.full(m1.n_elements, 3), np.full(m2.n_elements, 9)], warp)
+    u = project_state(plan, st)
+    vbar = torch.randn(plan.state_shape, generator=torch.Generator().manual_seed(5), dtype=torch.float64).cuda()
+    g = plan.vjp(u, vbar)
+    plan.sync_status()
+    for b, (m, p) in enumerate(((m1, 3), (m2, 9))):
+        single = esd.Plan(3, p, m.elem_vertex_ids, m.elem_vertex_coords, warp, 1.4, 0, 1)
+        ref = single.vjp(plan.bucket_view(u, b).contiguous(), plan.bucket_view(vbar, b).contiguous())
+        single.sync_status()
+        got = plan.bucket_view(g, b)
+        for c in range(ref.shape[1]):
+            err = float((got[:, c] - ref[:, c]).abs().max())
+            scale = float(ref[:, c].abs().max())
+            log(f"VJP bucket {b} (p {p}) variable {c}: max |batched - single| / ||g||_inf = {err / scale:.2e}")
+            assert err <= 1e-13 * scale, f"bucket {b}"
+
+
+def test_batched_vjp_central_differences_benchmark_batch():
+    """<vbar, R(u + h d) - R(u - h d)> / (2h) = <VJP(vbar), d> on the 4-mesh
+    batch (35,904 curved tetrahedra, p = 2..10) with the entropy-conservative
+    interface flux (smooth residual), and the discrete RK4 adjoint of one step
+    against the same identity; library only."""
+    bt = wl.batched_tets()
+    plan = batched(3, bt.meshes, bt.degrees, bt.warp, 0, 0)
+    u = project_state(plan, bt.state)
+    vbar = torch.randn(plan.state_shape, generator=torch.Generator().manual_seed(8), dtype=torch.float64).cuda()
+    g = plan.vjp(u, vbar)
+    h = 1e-6
+    for k in range(3):
+        d = torch.randn(plan.state_shape, generator=torch.Generator().manual_seed(300 + k), dtype=torch.float64).cuda()
+        fp = (plan.residual((u + h * d).contiguous()) * vbar).sum()
+        fm = (plan.residual((u - h * d).contiguous()) * vbar).sum()
+        fd = float((fp - fm) / (2 * h))
+        ad = float((g * d).sum())
+        log(f"batch direction {k}: fd {fd:.12e} adjoint {ad:.12e} rel {abs(fd - ad) / abs(ad):.2e}")
+        assert abs(fd - ad) <= 1e-6 * abs(ad)
+    # one RK4 step: d/du0 <vbar, u1(u0)>
+    dt = 1e-4
+    ckpt = torch.empty((4,) + plan.state_shape, dtype=torch.float64, device="cuda")
+    u1 = u.clone()
+    plan.rk4(u1, dt, 1, ckpt)
+    ubar = vbar.clone()
+    plan.rk4_vjp(ckpt, dt, 1, ubar)
+    d = torch.randn(plan.state_shape, generator=torch.Generator().manual_seed(400), dtype=torch.float64).cuda()
+    up, um = (u + h * d).contiguous(), (u - h * d).contiguous()
+    plan.rk4(up, dt, 1)
+    plan.rk4(um, dt, 1)
+    fd = float(((up - um) * vbar).sum() / (2 * h))
+    ad = float((ubar * d).sum())
+    log(f"batch RK4 step: fd {fd:.12e} adjoint {ad:.12e} rel {abs(fd - ad) / abs(ad):.2e}")
+    assert abs(fd - ad) <= 1e-6 * abs(ad)
+    plan.sync_status()

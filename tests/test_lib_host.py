@@ -137,3 +137,23 @@ def test_batched_plan_buckets_and_element_map():
         assert b["nodes"][1] - b["nodes"][0] == len(members) * (b["degree"] + 1) ** 3
     assert plan.info.n_dof == plan.buckets[-1]["dof"][1]
     assert plan.info.n_elements == len(degs)
+
+
+def test_batched_vjp_workspace_layout():
+    """The batched VJP workspace: the residual workspace, then per bucket
+    n_elements N_c N_fq doubles of exterior cotangents (256-byte aligned), then
+    the adjoint kernels' per-element slices (tetrahedra at p = 9, 10 only);
+    the RK4 adjoint adds three state arrays.  Host-only: the entry points
+    refuse with ESD_EINVAL."""
+    esd = _lib()
+    L = 2 * math.pi
+    m1 = wl.split_box_mesh(3, 3, L)
+    d1 = wl.mixed_degrees(m1.n_elements, 1, 2, 5)
+    plan = esd.BatchedPlan(3, [(m1.elem_vertex_ids, m1.elem_vertex_coords, d1)], host_only=True)
+    a256 = lambda n: (n + 255) // 256 * 256
+    xbar = sum(a256(b["n_elements"] * 5 * 4 * (b["degree"] + 1) ** 2 * 8) for b in plan.buckets)
+    i = plan.info
+    assert i.vjp_workspace_bytes == i.workspace_bytes + xbar
+    assert i.rk4_vjp_workspace_bytes == i.vjp_workspace_bytes + 3 * a256(i.n_dof * 8)
+    fake = 256
+    assert esd._lib.esd_residual_vjp(plan._h, fake, 2 * fake, 3 * fake, 4 * fake, None) == -1
