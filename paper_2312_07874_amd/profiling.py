@@ -96,12 +96,18 @@ def _short(name):
 def _per_residual(rows, prefix):
     """Sums over each run of consecutive dispatches of kernels with the prefix
     (one run per residual: K1 of every bucket, then the interface kernels,
-    then K2 of every bucket)."""
-    sums, cur, inside = [], 0.0, False
-    for _, n, v in rows:
+    then K2 of every bucket).  A run also ends where the dispatch ids jump,
+    so that runs with counters taken on a subset of the kernels
+    (--kernel-include-regex) still split per residual."""
+    sums, cur, inside, last = [], 0.0, False, None
+    for d, n, v in rows:
         if _short(n).startswith(prefix):
+            if inside and last is not None and d != last + 1:
+                sums.append(cur)
+                cur = 0.0
             cur += v
             inside = True
+            last = d
         elif inside:
             sums.append(cur)
             cur, inside = 0.0, False

@@ -120,3 +120,13 @@ def test_batched_k2_dispatches_are_summed_per_residual():
             (8, "void esd::k_rhs<3, 3, 0, false>(x)", 21.0)]
     assert prof._per_residual(rows, prof.K2_PREFIX) == [30.0, 32.0]
     assert prof._per_residual(rows, prof.K1_PREFIX) == [3.0, 1.0]
+
+
+def test_per_residual_sums_split_at_dispatch_id_gaps():
+    """Counters taken on K2 alone (--kernel-include-regex): consecutive rows of
+    different residuals are split where the dispatch ids jump."""
+    rows = [(4, "void esd::k_rhs<3, 2, 0, false>(x)", 10.0),
+            (5, "void esd::k_rhs<3, 3, 0, false>(x)", 20.0),
+            (9, "void esd::k_rhs<3, 2, 0, false>(x)", 11.0),
+            (10, "void esd::k_rhs<3, 3, 0, false>(x)", 21.0)]
+    assert prof._per_residual(rows, prof.K2_PREFIX) == [30.0, 32.0]
