@@ -170,6 +170,26 @@ def traffic(workload, fetch_csv, write_csv):
     with open(TRAFFIC_FILE, "w") as fh:
         json.dump(t, fh, indent=1)
     meas = rec["read_bytes_per_residual"] + rec["write_bytes_per_residual"]
+    # per degree bucket (one K2 instantiation each), last 5 residuals
+    if len(items) > 1:
+        import re
+        per_f, per_w = {}, {}
+        for rows, dst in ((_counter(fetch_csv, "FETCH_SIZE"), per_f), (_counter(write_csv, "WRITE_SIZE"), per_w)):
+            for _, n, v in rows:
+                m = re.match(r"esd::k_rhs<\d+, (\d+), ", _short(n))
+                if m:
+                    dst.setdefault(int(m.group(1)), []).append(v)
+        print("| p | elements | K2 read MB | K2 write MB | layout MB | measured / layout |")
+        print("|---|---|---|---|---|---|")
+        for p, n in items:
+            rb = statistics.fmean(per_f[p][-5:]) * 1024.0 * fetch_scale
+            wb = statistics.fmean(per_w[p][-5:]) * 1024.0 * write_scale
+            lb = n * pm.k2_bytes(dim, p)
+            print(f"| {p} | {n} | {rb / 1e6:.1f} | {wb / 1e6:.1f} | {lb / 1e6:.1f} | {(rb + wb) / lb:.2f} |")
+        print()
+    print("| workload | FETCH KiB | WRITE KiB | scale (fetch / write) | read | written | layout bytes | "
+          "minimum bytes | measured / layout |")
+    print("|---|---|---|---|---|---|---|---|---|")
     print(f"| {workload} | {statistics.fmean(k2f):.1f} | {statistics.fmean(k2w):.1f} | "
           f"{fetch_scale:.3f} / {write_scale:.3f} | {rec['read_bytes_per_residual'] / 1e6:.2f} MB | "
           f"{rec['write_bytes_per_residual'] / 1e6:.2f} MB | {rec['layout_bytes_k2_per_residual'] / 1e6:.2f} MB | "
@@ -194,6 +214,13 @@ def counters(paths):
 
 
 def stats(trace_csv):
+    """Per kernel instantiation: the block size the plan ran with (the most
+    launches; the autotuner's trial launches at other sizes aside), its launch
+    count and average duration; then the per-residual sums of K1 (with the
+    mixed-degree interface kernel) and K2 over the degree buckets; then every
+    (kernel, block) pair."""
+    import re
+
     by = {}
     for r in _rows(trace_csv):
         name = _short(r.get("Kernel_Name", ""))
@@ -202,6 +229,30 @@ def stats(trace_csv):
         bs = int(r.get("Workgroup_Size_X") or r.get("Workgroup_Size") or 0)
         dur = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
         by.setdefault((name, bs), []).append(dur)
+    chosen = {}
+    for (name, bs), d in by.items():
+        if name not in chosen or len(d) > len(by[(name, chosen[name])]):
+            chosen[name] = bs
+    print("| kernel | block (most launches) | launches | average us |")
+    print("|---|---|---|---|")
+    k1 = k2 = mixed = 0.0
+    nbuckets = sum(1 for n in chosen if n.startswith(K2_PREFIX) and ", false, false>" in n)
+    for name in sorted(chosen, key=lambda n: [int(x) if x.isdigit() else x for x in re.split(r"(\d+)", n)]):
+        d = by[(name, chosen[name])]
+        avg = statistics.fmean(d) / 1e3
+        print(f"| `{name}` | {chosen[name]} | {len(d)} | {avg:.2f} |")
+        # the plain residual's kernels: K1 without the projection-only variant,
+        # K2 without the stage-combination variant (RK4)
+        if name.startswith(K1_PREFIX) and name.endswith("false>"):
+            k1 += avg
+        elif name.startswith("esd::k_mixed_exterior<"):
+            mixed += avg * nbuckets   # one launch per bucket and residual
+        elif name.startswith(K2_PREFIX) and ", false, false>" in name:
+            k2 += avg
+    print()
+    print(f"Per residual (sum over buckets of the averages above): K1 {k1 / 1e3:.3f} ms, mixed-degree "
+          f"interface {mixed / 1e3:.3f} ms, K2 {k2 / 1e3:.3f} ms.")
+    print()
     print("| kernel | block | launches | average us | total us |")
     print("|---|---|---|---|---|")
     for (name, bs), d in sorted(by.items()):
