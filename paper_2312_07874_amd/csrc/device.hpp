@@ -202,7 +202,13 @@ __device__ __forceinline__ DevTables stage_tables(const DevTables& T, double* bu
 template <int P>
 struct Unroll {
   static constexpr int Q = P + 1;
-  static constexpr int XU = Q <= 7 ? Q : 1;   // contraction unrolled while its table fits scalar registers
+  // contractions unrolled fully while the psi1 table fits scalar registers,
+  // partly above (loads of the next iterations overlap the multiply-adds).
+  // Measured on MI355X, K1 / K2 per residual against the rolled loop: tet p8
+  // (24,576 elements) 2.15 / 6.25 -> 2.00 / 6.04 ms with 6, p9 (10,368)
+  // 1.19 / 3.78 -> 1.04 / 3.51 ms with 2 (6: 1.31 / 3.54), p10 2.86 / 7.54 ->
+  // 2.56 / 7.06 ms with 6; full unrolling is slower at p9 and p10
+  static constexpr int XU = Q <= 7 ? Q : (Q == 10 ? 2 : 6);
 };
 
 // V, first stage: the modes of the last direction to its nodes
