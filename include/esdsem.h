@@ -263,6 +263,21 @@ esd_status esd_plan_set_graphs(esd_plan* plan, int32_t enable);
  * fused for triangles; esd_plan_autotune keeps the faster of the two. */
 esd_status esd_plan_set_fused(esd_plan* plan, int32_t enable);
 
+/* Bitwise-repeatable right-hand side (default off).  The sums of
+ * eqs. (flux_differencing) and (facet_correction) then run in a fixed order:
+ * the volume pairs of one line family at a time, each node's pairs summed in
+ * registers by the lane that owns it (partners' data passed between the lanes
+ * of a line), and C^T 1 summed per facet node over its partners (each facet
+ * pair evaluated twice, once from each side) instead of through LDS atomics,
+ * whose order varies from run to run.  Results of esd_residual, esd_rk4 and
+ * esd_diagnostics are then identical bit for bit across runs on the same
+ * device and build; they differ from the default at rounding level.  RK4
+ * stages run unfused; the VJP entry points are unaffected (their sums keep
+ * LDS atomics).  Applies to every bucket of a batch; drops the plan's captured
+ * RK4 graphs (after waiting for their replays).  Call while no other work of
+ * the plan is in flight. */
+esd_status esd_plan_set_deterministic(esd_plan* plan, int32_t enable);
+
 /* Chooses the block sizes of the right-hand-side kernel (K2) and of the
  * entropy-projection kernel (K1) for every bucket by timing the candidates
  * (multiples of 64 up to their compiled bound) on the state u_dev, then

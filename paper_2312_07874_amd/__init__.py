@@ -103,6 +103,7 @@ EXPORTS = {
     "esd_sync_status": (_c, [_vp, _vp]),
     "esd_plan_set_graphs": (_c, [_vp, ctypes.c_int32]),
     "esd_plan_set_fused": (_c, [_vp, ctypes.c_int32]),
+    "esd_plan_set_deterministic": (_c, [_vp, ctypes.c_int32]),
     "esd_plan_autotune": (_c, [_vp, _vp, _vp, _vp]),
     "esd_plan_get_tuning": (_c, [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]),
     "esd_plan_set_timing": (_c, [_vp, ctypes.c_int32]),
@@ -333,6 +334,11 @@ class Plan:
     def set_fused(self, enable: bool):
         """RK4 stages as one launch that also projects the next stage input."""
         _check(_lib.esd_plan_set_fused(self._h, int(bool(enable))), "esd_plan_set_fused")
+
+    def set_deterministic(self, enable: bool):
+        """esd_plan_set_deterministic: fixed-order sums in the right-hand side
+        (bitwise-repeatable residuals and RK4 steps)."""
+        _check(_lib.esd_plan_set_deterministic(self._h, int(bool(enable))), "esd_plan_set_deterministic")
 
     def autotune(self, u):
         """Times the right-hand-side block-size candidates of every bucket on u

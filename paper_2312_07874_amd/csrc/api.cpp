@@ -940,9 +940,12 @@ static int rk4_step_fused(const esd_plan* P, double* u_dev, double dt, void* ws_
   return 0;
 }
 
+// whether RK4 stages run fused (deterministic plans run them unfused)
+static bool fused(const esd_plan* P) { return P->fuse_next && !P->deterministic; }
+
 // nsteps RK4 steps launched kernel by kernel, fused or not as the plan says
 static int rk4_eager(const esd_plan* P, double* u_dev, double dt, int nsteps, void* ws_dev, hipStream_t s) {
-  if (P->fuse_next) {
+  if (fused(P)) {
     int rc = project_all(P, u_dev, ws_dev, s);
     for (int step = 0; step < nsteps && rc == 0; ++step) rc = rk4_step_fused(P, u_dev, dt, ws_dev, s);
     return rc;
@@ -956,7 +959,7 @@ static int rk4_eager(const esd_plan* P, double* u_dev, double dt, int nsteps, vo
 // plan's own stream at first use
 static esd_status step_graph(const esd_plan* P, double* u_dev, double dt, void* ws_dev, hipGraphExec_t* exec) {
   for (const auto& g : P->graphs)
-    if (g.u == u_dev && g.ws == ws_dev && g.dt == dt && g.fused == P->fuse_next) {
+    if (g.u == u_dev && g.ws == ws_dev && g.dt == dt && g.fused == fused(P)) {
       *exec = g.exec;
       return ESD_OK;
     }
@@ -967,7 +970,7 @@ static esd_status step_graph(const esd_plan* P, double* u_dev, double dt, void* 
   }
   hipGraph_t graph = nullptr;
   HIP_TRY(hipStreamBeginCapture(P->gstream, hipStreamCaptureModeThreadLocal));
-  const int rc = P->fuse_next ? rk4_step_fused(P, u_dev, dt, ws_dev, P->gstream)
+  const int rc = fused(P) ? rk4_step_fused(P, u_dev, dt, ws_dev, P->gstream)
                               : rk4_step(P, u_dev, dt, ws_dev, nullptr, P->gstream);
   const hipError_t ec = hipStreamEndCapture(P->gstream, &graph);
   if (rc != 0 || ec != hipSuccess) {
@@ -982,7 +985,7 @@ static esd_status step_graph(const esd_plan* P, double* u_dev, double dt, void* 
     (void)hipGraphExecDestroy(P->graphs.front().exec);
     P->graphs.erase(P->graphs.begin());
   }
-  P->graphs.push_back({u_dev, ws_dev, dt, P->fuse_next, ex});
+  P->graphs.push_back({u_dev, ws_dev, dt, fused(P), ex});
   *exec = ex;
   return ESD_OK;
 }
@@ -1011,7 +1014,7 @@ esd_status esd_rk4(const esd_plan* P, double* u_dev, double dt, int32_t nsteps, 
   if (!P->timing && P->use_graphs) {
     // with fused stages the step starts from the projection of u in the first
     // residual workspace: project once, then replay
-    if (P->fuse_next) {
+    if (fused(P)) {
       const int rc = project_all(P, u_dev, ws_dev, s);
       if (rc != 0) return launch_rc(rc);
     }
@@ -1033,6 +1036,17 @@ esd_status esd_rk4(const esd_plan* P, double* u_dev, double dt, int32_t nsteps, 
 esd_status esd_plan_set_fused(esd_plan* P, int32_t enable) {
   if (!P) return fail(ESD_EINVAL, "plan is NULL");
   P->fuse_next = enable != 0;
+  return ESD_OK;
+}
+
+esd_status esd_plan_set_deterministic(esd_plan* P, int32_t enable) {
+  if (!P) return fail(ESD_EINVAL, "plan is NULL");
+  P->deterministic = enable != 0;
+  for (esd_plan* b : P->sub) b->deterministic = P->deterministic;
+  // graphs captured before the change launch the other right-hand side
+  if (P->gstream) (void)hipStreamSynchronize(P->gstream);
+  for (auto& g : P->graphs) (void)hipGraphExecDestroy(g.exec);
+  P->graphs.clear();
   return ESD_OK;
 }
 
@@ -1100,7 +1114,7 @@ esd_status esd_plan_autotune(esd_plan* P, const double* u_dev, void* ws_dev, voi
     const int64_t n = total_dof(P);
     float best = 1e30f;
     bool best_f = P->fuse_next;
-    for (int f = 1; f >= 0 && trial == ESD_OK; --f) {
+    for (int f = P->deterministic ? 0 : 1; f >= 0 && trial == ESD_OK; --f) {
       P->fuse_next = f != 0;
       HIP_TRY(hipMemcpyAsync(dudt, u_dev, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
       trial = esd_rk4(P, dudt, 0.0, 1, ws_dev, nullptr, stream);
@@ -1139,7 +1153,7 @@ esd_status esd_plan_get_tuning(const esd_plan* P, int32_t* k2_block, int32_t cap
     k2_block[b] = B->k2_block > 0 ? B->k2_block : esd::rhs_block_candidates(B->dim, B->p)[0];
     if (capacity >= 2 * nbk) k2_block[nbk + b] = B->k1_block > 0 ? B->k1_block : esd::rhs_block_candidates(B->dim, B->p)[0];
   }
-  if (capacity > 2 * nbk) k2_block[2 * nbk] = P->fuse_next ? 1 : 0;
+  if (capacity > 2 * nbk) k2_block[2 * nbk] = fused(P) ? 1 : 0;
   return ESD_OK;
 }
 

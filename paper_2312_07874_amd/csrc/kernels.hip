@@ -216,9 +216,71 @@ __device__ __forceinline__ void vol_task(const double* sN, const double* __restr
   for (int c = 0; c < NC; ++c) atomicAdd(&sR[c * NQ + na], racc[c]);
 }
 
+// Volume pairs of one line family, deterministic form: the Q lanes of a
+// line sit in one wave (64 / Q whole lines per wave), lane a owning node a of
+// the line base + stride*k.  In step k = 1..(Q-1)/2 lane a evaluates the pair
+// (a, a+k mod Q) exactly as vol_task does, keeps -F and passes F to the
+// partner's lane (a rotation of the line's lanes, through ds_bpermute), which
+// also hands it the partner's metrics; for even Q step Q/2 pairs a < Q/2 with
+// a + Q/2.  r_a is summed in registers in a fixed order and added to LDS once
+// (the caller runs one family at a time, so each node has one owner).  Lanes
+// of no line (ok false) shadow a valid line and drop their result.
+template <int DIM, int P, int FLUX, int NA>
+__device__ __forceinline__ void vol_line(const double* sN, const double* __restrict__ g, double* sR, int base,
+                                         int stride, int a, int lbase, bool ok, const double* __restrict__ A0,
+                                         const double* __restrict__ A1, int hc0, int hc1, const Scheme& S) {
+  using Sh = Shape<DIM, P>;
+  constexpr int Q = Sh::Q, NQ = Sh::NQ, NC = Sh::NC;
+  const int na = base + stride * a;
+  const Node<DIM> Na = load_node<DIM>(sN, NQ, na);
+  double h0a[DIM], h1a[DIM];
+#pragma unroll
+  for (int i = 0; i < DIM; ++i) {
+    h0a[i] = g[(hc0 + i) * NQ + na];
+    h1a[i] = NA == 2 ? g[(hc1 + i) * NQ + na] : 0.0;
+  }
+  double racc[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) racc[c] = 0.0;
+  auto step = [&](int k, bool half) {
+    int b = a + k;
+    b = b >= Q ? b - Q : b;
+    int src = a - k;
+    src = src < 0 ? src + Q : src;
+    const int nb = base + stride * b;
+    const Node<DIM> Nb = load_node<DIM>(sN, NQ, nb);
+    double n[DIM];
+    const double c0 = A0[a * Q + b];
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) n[i] = c0 * (h0a[i] + __shfl(h0a[i], lbase + b));
+    if constexpr (NA == 2) {
+      const double c1 = A1[a * Q + b];
+#pragma unroll
+      for (int i = 0; i < DIM; ++i) n[i] += c1 * (h1a[i] + __shfl(h1a[i], lbase + b));
+    }
+    double F[NC];
+    ec_flux<DIM, FLUX>(Na, Nb, n, S.gm1_inv, F);
+    const bool keep = !half || a < Q / 2;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const double f = keep ? F[c] : 0.0;
+      racc[c] += __shfl(f, lbase + src) - f;
+    }
+  };
+#pragma unroll
+  for (int k = 1; k <= (Q - 1) / 2; ++k) step(k, false);
+  if constexpr (Q % 2 == 0) step(Q / 2, true);
+  if (ok) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) sR[c * NQ + na] += racc[c];
+  }
+}
+
 // One facet-correction pair (eq. facet_correction): C = coef f#(u_i, u^z_j, (gn_i + nJ_j)/2);
-// r_i -= C (registers), s_j -= C (LDS atomics; s_j starts as the interface term).
-template <int DIM, int P, int FLUX>
+// r_i -= C (registers), and with ATOM s_j -= C (LDS atomics; s_j starts as the
+// interface term).  Without ATOM the caller sums s_j by facet node
+// (facet_node_sum).
+template <int DIM, int P, int FLUX, bool ATOM = true>
 __device__ __forceinline__ void facet_task(const Node<DIM>& Vi, const double* gn_i, const double* sF, double* sT,
                                            const double* __restrict__ gf, int j, double coef, const Scheme& S,
                                            double* racc) {
@@ -233,8 +295,116 @@ __device__ __forceinline__ void facet_task(const Node<DIM>& Vi, const double* gn
   for (int c = 0; c < NC; ++c) {
     const double C = coef * F[c];
     racc[c] -= C;
-    atomicAdd(&sT[c * NFQ + j], -C);
+    if constexpr (ATOM) atomicAdd(&sT[c * NFQ + j], -C);
   }
+}
+
+// G^T nhat at volume node i for the facets its lines reach (facet_correction's
+// {J n} on the volume side), from the pre-scaled metric rows: triangles
+// gA (facet 2), gB (facet 3), gC (facet 1); tetrahedra also gD (facet 4).
+template <int P>
+__device__ __forceinline__ void tri_volume_normals(const double* __restrict__ g, int i, int b1, int b2,
+                                                   const DevTables& T0, double* gA, double* gB, double* gC) {
+  constexpr int NQ = Shape<2, P>::NQ;
+  const double w1 = T0.wl[b1], w2 = T0.wl[b2];
+#pragma unroll
+  for (int m = 0; m < 2; ++m) {
+    const double g1 = g[(0 + m) * NQ + i] / w2;
+    const double g2 = 2.0 * g[(2 + m) * NQ + i] / w2;
+    gA[m] = (g1 + g2) * 0.70710678118654752440;     // facet 2: G^T nhat, nhat = (1,1)/sqrt 2
+    gB[m] = -g1;                                     // facet 3: nhat = (-1, 0)
+    gC[m] = -2.0 * g[(4 + m) * NQ + i] / w1;         // facet 1: nhat = (0, -1)
+  }
+}
+template <int P>
+__device__ __forceinline__ void tet_volume_normals(const double* __restrict__ g, int i, int b1, int b2, int b3,
+                                                   const DevTables& T0, double* gA, double* gB, double* gC,
+                                                   double* gD) {
+  constexpr int NQ = Shape<3, P>::NQ;
+  const double inv23 = 1.0 / (T0.wl[b2] * T0.wj[b3]);
+  const double inv13 = 1.0 / (T0.wl[b1] * T0.wj[b3]);
+  const double inv12 = 1.0 / (T0.wl[b1] * T0.wl[b2] * (1.0 - T0.xl[b2]));
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    const double g1 = 2.0 * g[(0 + m) * NQ + i] * inv23;
+    const double g23 = 4.0 * g[(3 + m) * NQ + i] * inv23;
+    gA[m] = (g1 + g23) * 0.57735026918962576451;    // facet 2: nhat = (1,1,1)/sqrt 3
+    gB[m] = -g1;                                     // facet 3: nhat = (-1,0,0)
+    gC[m] = -4.0 * g[(6 + m) * NQ + i] * inv13;      // facet 1: nhat = (0,-1,0)
+    gD[m] = -8.0 * g[(12 + m) * NQ + i] * inv12;     // facet 4: nhat = (0,0,-1)
+  }
+}
+
+// C^T 1 at facet node j (face z, node jf of the face) summed by the facet
+// node in a fixed order over its partners (the volume nodes whose lines reach
+// it: Q along a line for faces 1-3, the Q^2 nodes of an eta2-eta3 plane for
+// tet face 4), each pair re-evaluated exactly as the volume node's task
+// evaluates it: s_j -= sum_i C_ij.  The deterministic form of the atomics.
+template <int DIM, int P, int FLUX>
+__device__ __forceinline__ void facet_node_sum(const double* sN, const double* sF, double* sT,
+                                               const double* __restrict__ g, const double* __restrict__ gf, int j,
+                                               const DevTables& T0, const Scheme& S) {
+  using Sh = Shape<DIM, P>;
+  constexpr int Q = Sh::Q, NQ = Sh::NQ, NC = Sh::NC, NQF = Sh::NQF, NFQ = Sh::NFQ;
+  const int z = j / NQF, jf = j % NQF;
+  const Node<DIM> Fj = load_node<DIM>(sF, NFQ, j);
+  double gfj[DIM];
+#pragma unroll
+  for (int m = 0; m < DIM; ++m) gfj[m] = gf[m * NFQ + j];
+  double acc[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+  auto pair = [&](int i, const double* gn, double coef) {
+    const Node<DIM> Vi = load_node<DIM>(sN, NQ, i);
+    double n[DIM];
+#pragma unroll
+    for (int m = 0; m < DIM; ++m) n[m] = 0.5 * (gn[m] + gfj[m]);
+    double F[NC];
+    ec_flux<DIM, FLUX>(Vi, Fj, n, S.gm1_inv, F);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[c] += coef * F[c];
+  };
+  // loops kept rolled: one flux in flight per thread (unrolled, the compiler
+  // holds several and spills)
+  if constexpr (DIM == 2) {
+#pragma unroll 1
+    for (int k = 0; k < Q; ++k) {
+      const int b1 = z == 0 ? jf : k, b2 = z == 0 ? k : jf;
+      double gA[2], gB[2], gC[2];
+      tri_volume_normals<P>(g, b1 + Q * b2, b1, b2, T0, gA, gB, gC);
+      if (z == 1) pair(b1 + Q * b2, gA, T0.lgp1[b1] * T0.wf[j]);
+      else if (z == 2) pair(b1 + Q * b2, gB, T0.lgm1[b1] * T0.wf[j]);
+      else pair(b1 + Q * b2, gC, T0.lgm1[b2] * T0.wf[j]);
+    }
+  } else {
+    if (z < 3) {
+#pragma unroll 1
+      for (int k = 0; k < Q; ++k) {
+        // faces 1, 2: jf = b2 + Q b3, partners along b1; face 0: jf = b1 + Q b3, along b2
+        const int b3 = jf / Q, b1 = z == 0 ? jf % Q : k, b2 = z == 0 ? k : jf % Q;
+        double gA[3], gB[3], gC[3], gD[3];
+        const int i = b1 + Q * (b2 + Q * b3);
+        tet_volume_normals<P>(g, i, b1, b2, b3, T0, gA, gB, gC, gD);
+        if (z == 1) pair(i, gA, T0.lgp1[b1] * T0.wf[j]);
+        else if (z == 2) pair(i, gB, T0.lgm1[b1] * T0.wf[j]);
+        else pair(i, gC, T0.lgm1[b2] * T0.wf[j]);
+      }
+    } else {
+      // face 4: jf = b1 + Q a2, partners over the (b2, b3) plane
+      const int b1 = jf % Q, a2 = jf / Q;
+#pragma unroll 1
+      for (int b3 = 0; b3 < Q; ++b3)
+#pragma unroll 1
+        for (int b2 = 0; b2 < Q; ++b2) {
+          double gA[3], gB[3], gC[3], gD[3];
+          const int i = b1 + Q * (b2 + Q * b3);
+          tet_volume_normals<P>(g, i, b1, b2, b3, T0, gA, gB, gC, gD);
+          pair(i, gD, T0.gjm1[b3] * T0.I42[a2 * Q + b2] * T0.wf[j]);
+        }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < NC; ++c) sT[c * NFQ + j] -= acc[c];
 }
 
 // ------------------------------------------------------------------ K2, all-pairs variant
@@ -325,7 +495,7 @@ __device__ __forceinline__ void dense_facet_task(const Node<DIM>& Vi, const doub
 }
 
 // ------------------------------------------------------------------ K2: right-hand side
-template <int DIM, int P, int FLUX, bool NEXT, bool DENSE = false>
+template <int DIM, int P, int FLUX, bool NEXT, bool DENSE = false, bool DET = false>
 __global__ void __launch_bounds__((Launch<DIM, P>::BSMAX))
 k_rhs(const double* __restrict__ wt, const double* __restrict__ wfb, double* __restrict__ dudt,
       const double* __restrict__ gvol, const double* __restrict__ gfac, const int32_t* __restrict__ conn,
@@ -427,7 +597,46 @@ k_rhs(const double* __restrict__ wt, const double* __restrict__ wfb, double* __r
   //      registers, r_b through LDS atomics.
   for (int o = tid; o < nec * NQ; o += nth) sR[o] = 0.0;
   __syncthreads();
-  if constexpr (DENSE) {
+  if constexpr (DET) {
+    // one family at a time, its lines 64 / Q to a wave (blockDim is a
+    // multiple of 64); every node has one owner per family
+    constexpr int LPW = 64 / Q;
+    static_assert(LPW >= 1, "a line fits in a wave");
+    const int lane = tid & 63, wv = tid >> 6, nwv = nth >> 6;
+    const int grp = lane / Q;
+    const bool lane_ok = grp < LPW;
+    // lanes past the last whole group pair with themselves
+    const int a = lane_ok ? lane - grp * Q : 0, lbase = lane_ok ? lane - a : lane;
+    const int nlines = nel * LPF;
+#pragma unroll 1
+    for (int fam = 0; fam < DIM; ++fam) {
+      for (int wt = wv; wt * LPW < nlines; wt += nwv) {
+        const int gl0 = wt * LPW + grp;
+        const bool ok = lane_ok && gl0 < nlines;
+        const int gl = ok ? gl0 : wt * LPW;   // groups without a line shadow the wave's first
+        const int el = gl / LPF, L = gl % LPF;
+        const double* sNe = sN + el * Sh::SCR;
+        double* sRe = sR + el * NC * NQ;
+        const double* g = gvol + (e0 + el) * NGV * NQ;
+        if constexpr (DIM == 2) {
+          if (fam == 0)
+            vol_line<DIM, P, FLUX, 2>(sNe, g, sRe, Q * L, 1, a, lbase, ok, T.A + 0 * Q * Q, T.A + 1 * Q * Q, 0, 2, S);
+          else
+            vol_line<DIM, P, FLUX, 1>(sNe, g, sRe, L, Q, a, lbase, ok, T.A + 2 * Q * Q, nullptr, 4, 0, S);
+        } else {
+          if (fam == 0)
+            vol_line<DIM, P, FLUX, 2>(sNe, g, sRe, Q * L, 1, a, lbase, ok, T.A + 0 * Q * Q, T.A + 1 * Q * Q, 0, 3,
+                                      S);
+          else if (fam == 1)
+            vol_line<DIM, P, FLUX, 2>(sNe, g, sRe, (L % Q) + Q * Q * (L / Q), Q, a, lbase, ok, T.A + 2 * Q * Q,
+                                      T.A + 3 * Q * Q, 6, 9, S);
+          else
+            vol_line<DIM, P, FLUX, 1>(sNe, g, sRe, L, Q * Q, a, lbase, ok, T.A + 4 * Q * Q, nullptr, 12, 0, S);
+        }
+      }
+      __syncthreads();
+    }
+  } else if constexpr (DENSE) {
     for (int task = tid; task < nel * NQ; task += nth) {
       const int el = task / NQ, i = task % NQ;
       double racc[NC];
@@ -483,68 +692,67 @@ k_rhs(const double* __restrict__ wt, const double* __restrict__ wfb, double* __r
 #pragma unroll
     for (int c = 0; c < NC; ++c) racc[c] = 0.0;
     int i;
+    constexpr bool ATOM = !DET;   // C^T 1 through LDS atomics, or summed by facet node below
     if constexpr (DIM == 2) {
       const int b2 = t % Q, b1 = t / Q;     // b2 fastest: neighbouring lanes hit different facet nodes
       i = b1 + Q * b2;
       const Node<DIM> Vi = load_node<DIM>(sNe, NQ, i);
-      const double w1 = T0.wl[b1], w2 = T0.wl[b2];
       double gA[2], gB[2], gC[2];
-#pragma unroll
-      for (int m = 0; m < 2; ++m) {
-        const double g1 = g[(0 + m) * NQ + i] / w2;
-        const double g2 = 2.0 * g[(2 + m) * NQ + i] / w2;
-        gA[m] = (g1 + g2) * 0.70710678118654752440;     // facet 2: G^T nhat, nhat = (1,1)/sqrt 2
-        gB[m] = -g1;                                     // facet 3: nhat = (-1, 0)
-        gC[m] = -2.0 * g[(4 + m) * NQ + i] / w1;         // facet 1: nhat = (0, -1)
-      }
+      tri_volume_normals<P>(g, i, b1, b2, T0, gA, gB, gC);
       if constexpr (DENSE) {
         const double gn[3][2] = {{gC[0], gC[1]}, {gA[0], gA[1]}, {gB[0], gB[1]}};
         dense_facet_task<DIM, P, FLUX>(Vi, gn, sFe, sTe, gf, i, T0, S, racc);
       } else {
-        facet_task<DIM, P, FLUX>(Vi, gA, sFe, sTe, gf, 1 * NQF + b2, T0.lgp1[b1] * T0.wf[1 * NQF + b2], S, racc);
-        facet_task<DIM, P, FLUX>(Vi, gB, sFe, sTe, gf, 2 * NQF + b2, T0.lgm1[b1] * T0.wf[2 * NQF + b2], S, racc);
-        facet_task<DIM, P, FLUX>(Vi, gC, sFe, sTe, gf, 0 * NQF + b1, T0.lgm1[b2] * T0.wf[0 * NQF + b1], S, racc);
+        facet_task<DIM, P, FLUX, ATOM>(Vi, gA, sFe, sTe, gf, 1 * NQF + b2, T0.lgp1[b1] * T0.wf[1 * NQF + b2], S,
+                                       racc);
+        facet_task<DIM, P, FLUX, ATOM>(Vi, gB, sFe, sTe, gf, 2 * NQF + b2, T0.lgm1[b1] * T0.wf[2 * NQF + b2], S,
+                                       racc);
+        facet_task<DIM, P, FLUX, ATOM>(Vi, gC, sFe, sTe, gf, 0 * NQF + b1, T0.lgm1[b2] * T0.wf[0 * NQF + b1], S,
+                                       racc);
       }
     } else {
       const int b3 = t % Q, b2 = (t / Q) % Q, b1 = t / (Q * Q);
       i = b1 + Q * (b2 + Q * b3);
       const Node<DIM> Vi = load_node<DIM>(sNe, NQ, i);
-      const double inv23 = 1.0 / (T0.wl[b2] * T0.wj[b3]);
-      const double inv13 = 1.0 / (T0.wl[b1] * T0.wj[b3]);
-      const double inv12 = 1.0 / (T0.wl[b1] * T0.wl[b2] * (1.0 - T0.xl[b2]));
       double gA[3], gB[3], gC[3], gD[3];
-#pragma unroll
-      for (int m = 0; m < 3; ++m) {
-        const double g1 = 2.0 * g[(0 + m) * NQ + i] * inv23;
-        const double g23 = 4.0 * g[(3 + m) * NQ + i] * inv23;
-        gA[m] = (g1 + g23) * 0.57735026918962576451;    // facet 2: nhat = (1,1,1)/sqrt 3
-        gB[m] = -g1;                                     // facet 3: nhat = (-1,0,0)
-        gC[m] = -4.0 * g[(6 + m) * NQ + i] * inv13;      // facet 1: nhat = (0,-1,0)
-        gD[m] = -8.0 * g[(12 + m) * NQ + i] * inv12;     // facet 4: nhat = (0,0,-1)
-      }
+      tet_volume_normals<P>(g, i, b1, b2, b3, T0, gA, gB, gC, gD);
       if constexpr (DENSE) {
         const double gn[4][3] = {{gC[0], gC[1], gC[2]}, {gA[0], gA[1], gA[2]}, {gB[0], gB[1], gB[2]},
                                  {gD[0], gD[1], gD[2]}};
         dense_facet_task<DIM, P, FLUX>(Vi, gn, sFe, sTe, gf, i, T0, S, racc);
       } else {
         const int j23 = b2 + Q * b3;
-        facet_task<DIM, P, FLUX>(Vi, gA, sFe, sTe, gf, 1 * NQF + j23, T0.lgp1[b1] * T0.wf[1 * NQF + j23], S, racc);
-        facet_task<DIM, P, FLUX>(Vi, gB, sFe, sTe, gf, 2 * NQF + j23, T0.lgm1[b1] * T0.wf[2 * NQF + j23], S, racc);
+        facet_task<DIM, P, FLUX, ATOM>(Vi, gA, sFe, sTe, gf, 1 * NQF + j23, T0.lgp1[b1] * T0.wf[1 * NQF + j23], S,
+                                       racc);
+        facet_task<DIM, P, FLUX, ATOM>(Vi, gB, sFe, sTe, gf, 2 * NQF + j23, T0.lgm1[b1] * T0.wf[2 * NQF + j23], S,
+                                       racc);
         const int j13 = b1 + Q * b3;
-        facet_task<DIM, P, FLUX>(Vi, gC, sFe, sTe, gf, 0 * NQF + j13, T0.lgm1[b2] * T0.wf[0 * NQF + j13], S, racc);
+        facet_task<DIM, P, FLUX, ATOM>(Vi, gC, sFe, sTe, gf, 0 * NQF + j13, T0.lgm1[b2] * T0.wf[0 * NQF + j13], S,
+                                       racc);
         const double cz = T0.gjm1[b3];
-#pragma unroll
+        // without the atomics the compiler would overlap all Q pairs of an
+        // unrolled loop and spill: rolled in the deterministic form
+        constexpr int U4 = DET ? 1 : Q;
+#pragma unroll U4
         for (int m = 0; m < Q; ++m) {
           int a2 = m + b2 + b3;                 // rotated so that neighbouring lanes hit different facet nodes
           a2 = a2 % Q;
           const int j = 3 * NQF + b1 + Q * a2;
-          facet_task<DIM, P, FLUX>(Vi, gD, sFe, sTe, gf, j, cz * T0.I42[a2 * Q + b2] * T0.wf[j], S, racc);
+          facet_task<DIM, P, FLUX, ATOM>(Vi, gD, sFe, sTe, gf, j, cz * T0.I42[a2 * Q + b2] * T0.wf[j], S, racc);
         }
       }
     }
     double* r = sR + el * NC * NQ;
 #pragma unroll
     for (int c = 0; c < NC; ++c) r[c * NQ + i] += racc[c];
+  }
+  if constexpr (DET) {
+    // C^T 1 by facet node (the loop above wrote r only, this one s only)
+    for (int task = tid; task < nel * NFQ; task += nth) {
+      const int el = task / NFQ, j = task % NFQ;
+      facet_node_sum<DIM, P, FLUX>(sN + el * Sh::SCR, fr + el * 8 * NFQ, sT + el * NC * NFQ,
+                                   gvol + (e0 + el) * NGV * NQ, gfac + (e0 + el) * (DIM + 1) * NFQ, j, T0, S);
+    }
   }
   __syncthreads();
 
@@ -657,7 +865,13 @@ static void launch_k2(const esd_plan* pl, double* dudt, Workspace ws, hipStream_
 #define K2_ARGS \
   dim3(nb), dim3(bs), 0, s, ws.wt, ws.wf, dudt, pl->d_gvol, pl->d_gfac, pl->d_conn, pl->tab, pl->scheme, pl->ne, \
       pl->d_flag, ws.frec, epi
-  if (pl->scheme.ecflux == FLUX_RANOCHA) {
+  if (pl->deterministic) {
+    // fixed-order sums; the RK4 driver runs unfused stages for such plans
+    if (pl->scheme.ecflux == FLUX_RANOCHA)
+      hipLaunchKernelGGL((k_rhs<DIM, P, FLUX_RANOCHA, false, false, true>), K2_ARGS);
+    else
+      hipLaunchKernelGGL((k_rhs<DIM, P, FLUX_CHANDRASHEKAR, false, false, true>), K2_ARGS);
+  } else if (pl->scheme.ecflux == FLUX_RANOCHA) {
     if (next) hipLaunchKernelGGL((k_rhs<DIM, P, FLUX_RANOCHA, true>), K2_ARGS);
     else hipLaunchKernelGGL((k_rhs<DIM, P, FLUX_RANOCHA, false>), K2_ARGS);
   } else {

@@ -140,6 +140,9 @@ struct esd_plan {
   // input (else K1 and K2 per stage); set at creation (triangles), by
   // esd_plan_autotune (the faster on the device) or esd_plan_set_fused
   bool fuse_next = false;
+  // right-hand side with fixed-order sums instead of LDS atomics (bitwise
+  // repeatable); set by esd_plan_set_deterministic; RK4 stages then unfused
+  bool deterministic = false;
   mutable hipStream_t gstream = nullptr;
   mutable hipEvent_t gev[2] = {nullptr, nullptr};
   struct GraphEntry {
