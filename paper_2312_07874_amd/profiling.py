@@ -236,7 +236,13 @@ def stats(trace_csv):
     print("| kernel | block (most launches) | launches | average us |")
     print("|---|---|---|---|")
     k1 = k2 = mixed = 0.0
-    nbuckets = sum(1 for n in chosen if n.startswith(K2_PREFIX) and ", false, false>" in n)
+
+    def plain_k2(n):
+        # k_rhs<dim, p, flux, NEXT, DENSE[, DET]>: the plain residual's right-hand side
+        m = re.match(r"esd::k_rhs<\d+, \d+, \d+, (true|false), (true|false)(?:, (true|false))?>$", n)
+        return bool(m) and m.group(1) == "false" and m.group(2) == "false" and m.group(3) in (None, "false")
+
+    nbuckets = sum(1 for n in chosen if plain_k2(n))
     for name in sorted(chosen, key=lambda n: [int(x) if x.isdigit() else x for x in re.split(r"(\d+)", n)]):
         d = by[(name, chosen[name])]
         avg = statistics.fmean(d) / 1e3
@@ -247,7 +253,7 @@ def stats(trace_csv):
             k1 += avg
         elif name.startswith("esd::k_mixed_exterior<"):
             mixed += avg * nbuckets   # one launch per bucket and residual
-        elif name.startswith(K2_PREFIX) and ", false, false>" in name:
+        elif plain_k2(name):
             k2 += avg
     print()
     print(f"Per residual (sum over buckets of the averages above): K1 {k1 / 1e3:.3f} ms, mixed-degree "

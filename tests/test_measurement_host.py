@@ -130,3 +130,22 @@ def test_per_residual_sums_split_at_dispatch_id_gaps():
             (9, "void esd::k_rhs<3, 2, 0, false>(x)", 11.0),
             (10, "void esd::k_rhs<3, 3, 0, false>(x)", 21.0)]
     assert prof._per_residual(rows, prof.K2_PREFIX) == [30.0, 32.0]
+
+
+def test_stats_picks_the_plain_right_hand_side(tmp_path, capsys):
+    """Kernel-trace summary: per-residual K2 sums take k_rhs<..., false, false[, false]>
+    only (not the fused-stage, dense or deterministic variants)."""
+    path = tmp_path / "trace.csv"
+    rows = [("void esd::k_rhs<3, 6, 0, false, false, false>(double const*)", 256, 0, 2000),
+            ("void esd::k_rhs<3, 6, 0, false, false, false>(double const*)", 256, 0, 2000),
+            ("void esd::k_rhs<3, 6, 0, true, false, false>(double const*)", 256, 0, 9000),
+            ("void esd::k_rhs<3, 6, 0, false, false, true>(double const*)", 256, 0, 7000),
+            ("void esd::k_entropy_projection<3, 6, false>(double const*)", 128, 0, 500)]
+    with open(path, "w", newline="") as fh:
+        w = csv.writer(fh)
+        w.writerow(["Kernel_Name", "Workgroup_Size_X", "Start_Timestamp", "End_Timestamp"])
+        for r in rows:
+            w.writerow(r)
+    prof.stats(str(path))
+    out = capsys.readouterr().out
+    assert "K1 0.001 ms, mixed-degree interface 0.000 ms, K2 0.002 ms" in out
