@@ -332,7 +332,10 @@ esd_status esd_diagnostics(const esd_plan* plan, const double* u_dev, double* ou
                            void* stream);
 
 /* Synchronises the stream and returns ESD_EADMISSIBLE if any kernel since the
- * last call saw an inadmissible state (the flag is cleared), else ESD_OK. */
+ * last call saw an inadmissible state, ESD_EINVAL if an entropy projection
+ * was launched with fewer threads than its in-place transform stages need
+ * (tetrahedra at p = 10; the library's own launches never do), else ESD_OK;
+ * the flag is cleared. */
 esd_status esd_sync_status(const esd_plan* plan, void* stream);
 
 /* Kernel timing for measurement: when enabled, every K1 (entropy projection)

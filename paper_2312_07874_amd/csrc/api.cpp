@@ -1082,7 +1082,7 @@ esd_status esd_plan_autotune(esd_plan* P, const double* u_dev, void* ws_dev, voi
     for (int which = 2; which >= 1 && rc == 0; --which) {
       float best = 1e30f;
       int best_bs = 0;
-      for (int bs : esd::rhs_block_candidates(B->dim, B->p)) {
+      for (int bs : which == 2 ? esd::rhs_block_candidates(B->dim, B->p) : esd::k1_block_candidates(B->dim, B->p)) {
         (which == 2 ? B->k2_block : B->k1_block) = bs;
         auto launch = [&]() {
           return which == 2 ? esd::launch_rhs(B, out, split_ws(B, wsb), s)
@@ -1295,6 +1295,7 @@ esd_status esd_sync_status(const esd_plan* P, void* stream) {
   if (flag) {
     const int zero = 0;
     HIP_TRY(hipMemcpy(P->d_flag, &zero, sizeof(int), hipMemcpyHostToDevice));
+    if (flag & 2) return fail(ESD_EINVAL, "entropy projection launched with fewer threads than its in-place stages need");
     return fail(ESD_EADMISSIBLE, "inadmissible state (rho <= 0, p <= 0 or non-finite) seen by a kernel");
   }
   return ESD_OK;

@@ -522,6 +522,117 @@ __device__ __forceinline__ void xform_VVt(const double* in, double* T1, double* 
   __syncthreads();
 }
 
+// ------------------------------------------------------------------ transforms inside the nodal array
+// V and V^T on tetrahedra with every stage inside one nodal array A
+// [nec][NQ]: the modal values in its first nec*NP doubles, the first stage's
+// T1 right after them (NP + NPAIR Q <= Q^3 from p = 3 on), the middle stage's
+// T2 over all of it.  The middle stage therefore overwrites its own input: it
+// reads all of its inputs into registers (at most MAXT tasks per thread,
+// MAXT * blockDim >= nec (P+1) Q, which the launch guarantees), waits at a
+// barrier, then writes.  Used where the transform scratch would cost a
+// workgroup per CU.
+template <int P, int MAXT>
+__device__ __forceinline__ void v_second_staged(const double* T1, double* T2, const DevTables& T, int nec) {
+  using S = Shape<3, P>;
+  constexpr int Q = S::Q;
+  const int tid = threadIdx.x, nth = blockDim.x, total = nec * (P + 1) * Q;
+  double xs[MAXT][P + 1];
+#pragma unroll
+  for (int t = 0; t < MAXT; ++t) {
+    const int o = tid + t * nth;
+    if (o < total) {
+      const int i3 = o % Q, a1 = (o / Q) % (P + 1), ec = o / (Q * (P + 1));
+      const int pb = pair_index(P, a1, 0);
+#pragma unroll
+      for (int a2 = 0; a2 <= P; ++a2) xs[t][a2] = a2 <= P - a1 ? T1[(ec * S::NPAIR + pb + a2) * Q + i3] : 0.0;
+    }
+  }
+  __syncthreads();
+  // one output at a time (a rolled loop; the register-held inputs are
+  // indexed by unrolled constants only)
+#pragma unroll
+  for (int t = 0; t < MAXT; ++t) {
+    const int o = tid + t * nth;
+    if (o < total) {
+      const int i3 = o % Q, a1 = (o / Q) % (P + 1), ec = o / (Q * (P + 1));
+      double* t2 = T2 + ((int64_t)ec * Q * Q + Q * i3) * Q;
+      const double* ps = T.psi2 + a1 * (P + 1) * Q;
+#pragma unroll 1
+      for (int i = 0; i < Q; ++i) {
+        double acc = 0.0;
+#pragma unroll
+        for (int a2 = 0; a2 <= P; ++a2)
+          if (a2 <= P - a1) acc += ps[a2 * Q + i] * xs[t][a2];
+        t2[i * Q + (a1 + i < Q ? a1 + i : a1 + i - Q)] = acc;
+      }
+    }
+  }
+}
+
+template <int P, int MAXT>
+__device__ __forceinline__ void vt_second_staged(const double* T2, double* T1, const DevTables& T, int nec) {
+  using S = Shape<3, P>;
+  constexpr int Q = S::Q;
+  const int tid = threadIdx.x, nth = blockDim.x, total = nec * (P + 1) * Q;
+  double xs[MAXT][Q];
+#pragma unroll
+  for (int t = 0; t < MAXT; ++t) {
+    const int o = tid + t * nth;
+    if (o < total) {
+      const int i3 = o % Q, a1 = (o / Q) % (P + 1), ec = o / (Q * (P + 1));
+      const double* t2 = T2 + ((int64_t)ec * Q * Q + Q * i3) * Q;
+#pragma unroll
+      for (int i2 = 0; i2 < Q; ++i2) xs[t][i2] = t2[i2 * Q + (a1 + i2 < Q ? a1 + i2 : a1 + i2 - Q)];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int t = 0; t < MAXT; ++t) {
+    const int o = tid + t * nth;
+    if (o < total) {
+      const int i3 = o % Q, a1 = (o / Q) % (P + 1), ec = o / (Q * (P + 1));
+      const int pb = pair_index(P, a1, 0);
+#pragma unroll 1
+      for (int a = 0; a <= P - a1; ++a) {
+        const double* ps = T.psi2 + (a1 * (P + 1) + a) * Q;
+        double acc = 0.0;
+#pragma unroll
+        for (int i2 = 0; i2 < Q; ++i2) acc += ps[i2] * xs[t][i2];
+        T1[(ec * S::NPAIR + pb + a) * Q + i3] = acc;
+      }
+    }
+  }
+}
+
+// u = V u~ with A holding u~ in its first nec NP doubles on entry and u on
+// exit; ends with a barrier
+template <int P, int MAXT>
+__device__ __forceinline__ void xform_V_inplace(double* A, const DevTables& T, int nec) {
+  using S = Shape<3, P>;
+  static_assert(S::NP + S::NPAIR * S::Q <= S::NQ, "first-stage scratch fits after the modal values");
+  double* T1 = A + nec * S::NP;
+  v_first<3, P>(A, T1, T, nec);
+  __syncthreads();
+  v_second_staged<P, MAXT>(T1, A, T, nec);
+  __syncthreads();
+  v_last<3, P>(A, A, T, nec);
+  __syncthreads();
+}
+
+// V^T of the nodal fields in A, the result in A's first nec NP doubles; ends
+// with a barrier
+template <int P, int MAXT>
+__device__ __forceinline__ void xform_Vt_inplace(double* A, const DevTables& T, int nec) {
+  using S = Shape<3, P>;
+  double* T1 = A + nec * S::NP;
+  vt_first<3, P>(A, A, T, nec);
+  __syncthreads();
+  vt_second_staged<P, MAXT>(A, T1, T, nec);
+  __syncthreads();
+  vt_last<3, P>(T1, A, T, nec);
+  __syncthreads();
+}
+
 // ------------------------------------------------------------------ loads issued ahead of their use
 // Values of a block-strided loop over n items (o = tid, tid + nth, ...) for
 // this thread's first PF iterations, loaded before the phases that precede

@@ -28,11 +28,26 @@
 namespace esd {
 
 // ------------------------------------------------------------------ K1: entropy projection
+// K1 keeps every transform stage inside its nodal array (xform_V_inplace) at
+// tet p = 10: the separate first-stage scratch would leave one workgroup per
+// CU (115 KB of LDS); inside, 80.6 KB with both PKD tables staged, two.  Each
+// thread then holds K1_MAXT middle-stage tasks, so K1 launches with at least
+// k1_min_block threads there.
+template <int DIM, int P>
+struct K1Inplace {
+  static constexpr bool ON = DIM == 3 && P == 10;
+  static constexpr int MAXT = 2;
+  static constexpr int TASKS = (DIM + 2) * (P + 1) * (P + 1);   // middle-stage tasks per element
+  static constexpr int MIN_BLOCK = ON ? ((TASKS + MAXT - 1) / MAXT + 63) / 64 * 64 : 64;
+  static constexpr int WAVES = ON ? 4 : 1;   // waves per SIMD the registers must allow
+};
+
 // w~ = V^T (w/J) V V^T b for b = (w J W) at the volume nodes in sA [nel*NC][NQ]
 // (eqs. entropy_expansion, matvec_entropy_projection); result in sM; aI holds
 // w/J at this thread's first nodes; VVT: V V^T as one composed transform (its
-// table staged).  Ends with a barrier.
-template <int DIM, int P, bool VVT>
+// table staged); INPLACE: every stage inside sA (xform_V_inplace, K1 only:
+// sM is then sA's start and sS unused).  Ends with a barrier.
+template <int DIM, int P, bool VVT, bool INPLACE = false>
 __device__ __forceinline__ void weight_adjusted_projection(double* sM, double* sA, double* sS, const DevTables& T,
                                                            const double* __restrict__ gvol, int64_t e0, int nel,
                                                            const Ahead<2>& aI) {
@@ -42,8 +57,13 @@ __device__ __forceinline__ void weight_adjusted_projection(double* sM, double* s
   const int nec = nel * NC;
   double* T1 = sS;
   double* T2 = sA;   // the tetrahedral middle layout runs in place over the nodal values
+  using IP = K1Inplace<DIM, P>;
   auto ld_wi = [&](int o) { return gvol[((e0 + o / NQ) * NGV + NGV - 1) * NQ + o % NQ]; };
-  if constexpr (VVT) {
+  if constexpr (INPLACE) {
+    static_assert(!VVT && IP::ON, "in-place stages: tet p = 10, without the composed transform");
+    xform_Vt_inplace<P, IP::MAXT>(sA, T, nec);
+    xform_V_inplace<P, IP::MAXT>(sA, T, nec);
+  } else if constexpr (VVT) {
     xform_VVt<DIM, P>(sA, T1, T2, sA, T, nec);
   } else {
     xform_Vt<DIM, P>(sA, T1, T2, sM, T, nec);
@@ -55,7 +75,8 @@ __device__ __forceinline__ void weight_adjusted_projection(double* sM, double* s
     for (int c = 0; c < NC; ++c) sA[(el * NC + c) * NQ + k] *= wi;
   });
   __syncthreads();
-  xform_Vt<DIM, P>(sA, T1, T2, sM, T, nec);
+  if constexpr (INPLACE) xform_Vt_inplace<P, IP::MAXT>(sA, T, nec);
+  else xform_Vt<DIM, P>(sA, T1, T2, sM, T, nec);
 }
 
 // Entropy projection of a block of elements whose modal state u~ is in sM
@@ -63,7 +84,7 @@ __device__ __forceinline__ void weight_adjusted_projection(double* sM, double* s
 // weight-adjusted projection, written to wt, and the facet values R V w~
 // (eqs. r_2d, r_3d) to wf.  aJ and aI hold w J and w/J at this thread's first
 // nodes.  Uses sA [nel*NC][NQ] and the transform scratch sS.
-template <int DIM, int P, bool VVT>
+template <int DIM, int P, bool VVT, bool INPLACE = false>
 __device__ __forceinline__ void project_block(double* sM, double* sA, double* sS, const DevTables& T,
                                               const double* __restrict__ gvol, const Scheme& S, int64_t e0,
                                               int nel, int* flag, double* __restrict__ wt, double* __restrict__ wf,
@@ -75,8 +96,10 @@ __device__ __forceinline__ void project_block(double* sM, double* sA, double* sS
   const int tid = threadIdx.x, nth = blockDim.x;
   double* T1 = sS;
   double* T2 = sA;
+  using IP = K1Inplace<DIM, P>;
   auto ld_wJ = [&](int o) { return gvol[((e0 + o / NQ) * NGV + NGV - 2) * NQ + o % NQ]; };
-  xform_V<DIM, P>(sM, T1, T2, sA, T, nec);
+  if constexpr (INPLACE) xform_V_inplace<P, IP::MAXT>(sA, T, nec);
+  else xform_V<DIM, P>(sM, T1, T2, sA, T, nec);
   // entropy variables times w J at every volume node
   bool bad = false;
   aJ.each(nel * NQ, ld_wJ, [&](int o, double wJ) {
@@ -99,16 +122,18 @@ __device__ __forceinline__ void project_block(double* sM, double* sA, double* sS
   });
   if (bad) atomicOr(flag, 1);
   __syncthreads();
-  weight_adjusted_projection<DIM, P, VVT>(sM, sA, sS, T, gvol, e0, nel, aI);
+  weight_adjusted_projection<DIM, P, VVT, INPLACE>(sM, sA, sS, T, gvol, e0, nel, aI);
   for (int o = tid; o < nec * NP; o += nth) wt[e0 * NC * NP + o] = sM[o];
   // facet values of the projected entropy variables, w^z = R^z V w~
-  xform_V<DIM, P>(sM, T1, T2, sA, T, nec);
+  if constexpr (INPLACE) xform_V_inplace<P, IP::MAXT>(sA, T, nec);
+  else xform_V<DIM, P>(sM, T1, T2, sA, T, nec);
   double* wfe = wf + e0 * NC * NFQ;
   facet_values<DIM, P>(sA, sS, T, nec, [&](int o, double v) { wfe[o] = v; });
 }
 
 template <int DIM, int P, bool PROJECT_ONLY>
 __global__ void __launch_bounds__((Launch<DIM, P>::BSMAX))
+__attribute__((amdgpu_waves_per_eu(K1Inplace<DIM, P>::WAVES)))   // in place: two 512-thread workgroups per CU
 k_entropy_projection(const double* __restrict__ u, double* __restrict__ wt, double* __restrict__ wf,
                      const double* __restrict__ gvol, DevTables T0, Scheme S, int64_t ne, int* flag) {
   using Sh = Shape<DIM, P>;
@@ -119,12 +144,16 @@ k_entropy_projection(const double* __restrict__ u, double* __restrict__ wt, doub
   // V and the modal output of V^T never coexist with the nodal values; the
   // tetrahedral middle stage runs in place over sA too, so the transform
   // scratch is the first stage's alone (which also holds the facet scratch)
+  using IP = K1Inplace<DIM, P>;
+  // with in-place stages the scratch is only the facet extrapolation's
+  constexpr int SS = IP::ON ? NC * Sh::Q * Sh::Q : Sh::T1;
   __shared__ double sA[EPB * NC * NQ];
-  __shared__ double sS[EPB * Sh::T1];
+  __shared__ double sS[EPB * SS];
   double* const sM = sA;
   static_assert(NP <= NQ, "modal arrays fit in the nodal array");
-  static_assert(DIM == 2 || Sh::T1 >= NC * Sh::Q * Sh::Q, "facet scratch fits in the transform scratch");
-  constexpr int KB = 8 * EPB * (NC * NQ + Sh::T1);
+  static_assert(DIM == 2 || SS >= NC * Sh::Q * Sh::Q, "facet scratch fits in the transform scratch");
+  static_assert(!IP::ON || EPB == 1, "in-place stages assume one element per workgroup");
+  constexpr int KB = 8 * EPB * (NC * NQ + SS);
   // the composed V V^T table only where it keeps the workgroups per CU; where
   // the two PKD tables do not fit (tetrahedra at p = 10), psi2 alone
   constexpr unsigned TM0 = tab_keeps_wgs<DIM, P, TAB_PSI | TAB_FACET, TAB_PSI | TAB_FACET | TAB_PSIM>(KB, wave_cap<DIM, P>())
@@ -138,6 +167,14 @@ k_entropy_projection(const double* __restrict__ u, double* __restrict__ wt, doub
   const int nel = (int)((ne - e0) < EPB ? (ne - e0) : EPB);
   const int nec = nel * NC;
   const int tid = threadIdx.x, nth = blockDim.x;
+  if constexpr (IP::ON) {
+    // the launch keeps blockDim >= IP::MIN_BLOCK; refuse (flag bit 2) rather
+    // than skip middle-stage tasks
+    if (nth * IP::MAXT < IP::TASKS) {
+      if (tid == 0) atomicOr(flag, 2);
+      return;
+    }
+  }
   // w J and w/J at this thread's nodes, used after the first transforms
   auto ld_wJ = [&](int o) { return gvol[((e0 + o / NQ) * NGV + NGV - 2) * NQ + o % NQ]; };
   auto ld_wi = [&](int o) { return gvol[((e0 + o / NQ) * NGV + NGV - 1) * NQ + o % NQ]; };
@@ -151,14 +188,14 @@ k_entropy_projection(const double* __restrict__ u, double* __restrict__ wt, doub
       sA[(el * NC + c) * NQ + k] = wJ * u[(e0 * NQ) * NC + o];
     }
     __syncthreads();
-    weight_adjusted_projection<DIM, P, VVT>(sM, sA, sS, T, gvol, e0, nel, aI);
+    weight_adjusted_projection<DIM, P, VVT, IP::ON>(sM, sA, sS, T, gvol, e0, nel, aI);
     for (int o = tid; o < nec * NP; o += nth) wt[e0 * NC * NP + o] = sM[o];
   } else {
     aJ.load(nel * NQ, ld_wJ);
     aI.load(nel * NQ, ld_wi);
     for (int o = tid; o < nec * NP; o += nth) sM[o] = u[e0 * NC * NP + o];
     __syncthreads();
-    project_block<DIM, P, VVT>(sM, sA, sS, T, gvol, S, e0, nel, flag, wt, wf, aJ, aI);
+    project_block<DIM, P, VVT, IP::ON>(sM, sA, sS, T, gvol, S, e0, nel, flag, wt, wf, aJ, aI);
   }
 }
 
@@ -967,6 +1004,21 @@ std::vector<int> rhs_block_candidates(int dim, int p) {
   ESD_TRI_DEGREES(X)
   ESD_TET_DEGREES(X)
 #undef X
+  return c;
+}
+
+// block sizes the entropy-projection kernel may be launched with (the right-
+// hand side's, from the in-place stages' minimum up)
+std::vector<int> k1_block_candidates(int dim, int p) {
+  int lo = 64;
+#define X(D, PP) \
+  if (dim == D && p == PP) lo = K1Inplace<D, PP>::MIN_BLOCK;
+  ESD_TRI_DEGREES(X)
+  ESD_TET_DEGREES(X)
+#undef X
+  std::vector<int> c;
+  for (int b : rhs_block_candidates(dim, p))
+    if (b >= lo) c.push_back(b);
   return c;
 }
 

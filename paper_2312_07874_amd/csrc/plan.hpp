@@ -195,4 +195,5 @@ bool vjp_degree_supported(int dim, int p);
 bool needs_facet_records(int dim, int p);   // the residual workspace holds Workspace::frec
 int vjp_scratch_doubles(int dim, int p);    // per element, of Workspace::vscr (0 if none)
 std::vector<int> rhs_block_candidates(int dim, int p);
+std::vector<int> k1_block_candidates(int dim, int p);
 }  // namespace esd
