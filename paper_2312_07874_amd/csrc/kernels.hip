@@ -548,16 +548,17 @@ k_rhs(const double* __restrict__ wt, const double* __restrict__ wfb, double* __r
   __shared__ double sR[EPB * NC * NQ];      // w at nodes, then r
   __shared__ double sF[FLDS ? EPB * 8 * NFQ : 1];   // own facet node records (LDS case)
   __shared__ double sT[EPB * NC * NFQ];     // C^T 1, then s = B J_f f* - C^T 1
-  // operator tables in LDS: tetrahedra keep them in the tail of sF beyond the
-  // modal staging, free during both transform phases (copied again once the
-  // facet records are dead), so the kernel's LDS and occupancy do not grow;
-  // triangles in an array of their own.  The transforms read psi; the
-  // projection of the next stage also reads the facet tables.  The facet
-  // correction and interface phases, which run while sF holds the facet
-  // records, read their tables from T0.
+  // operator tables in LDS: tetrahedra keep them in space that is free during
+  // both transform phases (copied again once the flux phases are done), so
+  // the kernel's LDS and occupancy do not grow: the tail of sF beyond the
+  // modal staging where the facet records live in LDS, else (tet p = 10) the
+  // tail of sN beyond the first transform stage's scratch, the middle stage
+  // then running in place over sR; triangles in an array of their own.  The
+  // transforms read psi; the projection of the next stage also reads the
+  // facet tables.  The interface and flux phases read theirs from T0.
   constexpr unsigned W0 = NEXT ? (TAB_PSI | TAB_FACET) : TAB_PSI;
   constexpr unsigned W1 = W0 | TAB_PSIM;   // with the composed stage of V V^T
-  constexpr int ROOM = (DIM == 3 && FLDS) ? 8 * NFQ - NC * NP : -1;   // doubles free in sF's tail
+  constexpr int ROOM = DIM != 3 ? -1 : FLDS ? 8 * NFQ - NC * NP : Sh::SCR - Sh::T1;   // doubles free
   constexpr int KB = 8 * (EPB * (Sh::SCR + NC * NQ + NC * NFQ) + (FLDS ? EPB * 8 * NFQ : 1));
   constexpr unsigned TM =
       DIM == 2 ? (tab_keeps_wgs<DIM, P, W0, W1>(KB, wave_cap<DIM, P>()) ? W1 : tab_mask<DIM, P, W0>(KB))
@@ -566,9 +567,9 @@ k_rhs(const double* __restrict__ wt, const double* __restrict__ wfb, double* __r
                   : TabLds<DIM, P, TAB_PSI>::SIZE <= ROOM ? TAB_PSI : 0u);
   constexpr bool TAB_SF = DIM == 3 && TM != 0;
   constexpr bool VVT = (TM & TAB_PSIM) != 0;
-  static_assert(!TAB_SF || EPB == 1, "one element per workgroup when the tables share sF");
+  static_assert(!TAB_SF || EPB == 1, "one element per workgroup when the tables share sF or sN");
   __shared__ double sTab[DIM == 2 && TM ? TabLds<DIM, P, TM>::SIZE : 1];
-  double* const tab_buf = TAB_SF ? sF + NC * NP : sTab;
+  double* const tab_buf = TAB_SF ? (FLDS ? sF + NC * NP : sN + Sh::T1) : sTab;
   const DevTables T = stage_tables<DIM, P, TM>(T0, tab_buf);
   static_assert(FLDS ? 8 * NFQ >= NC * NP : NFQ >= NP, "modal staging must fit the facet buffers");
   // modal w~ before the facet data exist, du~/dt after they are dead
@@ -580,7 +581,9 @@ k_rhs(const double* __restrict__ wt, const double* __restrict__ wfb, double* __r
   double* fr = FLDS ? sF : frec + e0 * 8 * NFQ;
   const int tid = threadIdx.x, nth = blockDim.x;
   double* T1 = sN;
-  double* T2 = sN + EPB * Sh::T1;
+  // the middle transform stage in sN, or in place over sR where sN's tail
+  // holds the tables
+  double* T2 = (DIM == 3 && !FLDS) ? sR : sN + EPB * Sh::T1;
 
   // ---- w = V w~ at the volume nodes
   for (int o = tid; o < nec * NP; o += nth) sM[o] = wt[e0 * NC * NP + o];
@@ -794,7 +797,7 @@ k_rhs(const double* __restrict__ wt, const double* __restrict__ wfb, double* __r
   __syncthreads();
 
   if constexpr (TAB_SF) {
-    (void)stage_tables<DIM, P, TM>(T0, tab_buf);   // over the dead facet records
+    (void)stage_tables<DIM, P, TM>(T0, tab_buf);   // over the dead facet (or node) records
     // the lift below reads the facet tables when they are staged
     if constexpr ((TM & TAB_FACET) != 0) __syncthreads();
   }
