@@ -548,17 +548,17 @@ k_rhs(const double* __restrict__ wt, const double* __restrict__ wfb, double* __r
   __shared__ double sR[EPB * NC * NQ];      // w at nodes, then r
   __shared__ double sF[FLDS ? EPB * 8 * NFQ : 1];   // own facet node records (LDS case)
   __shared__ double sT[EPB * NC * NFQ];     // C^T 1, then s = B J_f f* - C^T 1
-  // operator tables in LDS: tetrahedra keep them in space that is free during
-  // both transform phases (copied again once the flux phases are done), so
-  // the kernel's LDS and occupancy do not grow: the tail of sF beyond the
-  // modal staging where the facet records live in LDS, else (tet p = 10) the
-  // tail of sN beyond the first transform stage's scratch, the middle stage
-  // then running in place over sR; triangles in an array of their own.  The
+  // operator tables in LDS: tetrahedra keep them in the tail of sN beyond the
+  // first transform stage's scratch, free during both transform phases (the
+  // middle stage runs in place over sR; copied again once the flux phases are
+  // done), so the kernel's LDS and occupancy do not grow (measured against
+  // the tail of sF, where the composed V V^T table fits only up to p = 6: K2
+  // tet p7 -1%, p8 -3%, p9 -3%); triangles in an array of their own.  The
   // transforms read psi; the projection of the next stage also reads the
   // facet tables.  The interface and flux phases read theirs from T0.
   constexpr unsigned W0 = NEXT ? (TAB_PSI | TAB_FACET) : TAB_PSI;
   constexpr unsigned W1 = W0 | TAB_PSIM;   // with the composed stage of V V^T
-  constexpr int ROOM = DIM != 3 ? -1 : FLDS ? 8 * NFQ - NC * NP : Sh::SCR - Sh::T1;   // doubles free
+  constexpr int ROOM = DIM != 3 ? -1 : Sh::SCR - Sh::T1;   // doubles free
   constexpr int KB = 8 * (EPB * (Sh::SCR + NC * NQ + NC * NFQ) + (FLDS ? EPB * 8 * NFQ : 1));
   constexpr unsigned TM =
       DIM == 2 ? (tab_keeps_wgs<DIM, P, W0, W1>(KB, wave_cap<DIM, P>()) ? W1 : tab_mask<DIM, P, W0>(KB))
@@ -569,7 +569,7 @@ k_rhs(const double* __restrict__ wt, const double* __restrict__ wfb, double* __r
   constexpr bool VVT = (TM & TAB_PSIM) != 0;
   static_assert(!TAB_SF || EPB == 1, "one element per workgroup when the tables share sF or sN");
   __shared__ double sTab[DIM == 2 && TM ? TabLds<DIM, P, TM>::SIZE : 1];
-  double* const tab_buf = TAB_SF ? (FLDS ? sF + NC * NP : sN + Sh::T1) : sTab;
+  double* const tab_buf = TAB_SF ? sN + Sh::T1 : sTab;
   const DevTables T = stage_tables<DIM, P, TM>(T0, tab_buf);
   static_assert(FLDS ? 8 * NFQ >= NC * NP : NFQ >= NP, "modal staging must fit the facet buffers");
   // modal w~ before the facet data exist, du~/dt after they are dead
@@ -583,7 +583,7 @@ k_rhs(const double* __restrict__ wt, const double* __restrict__ wfb, double* __r
   double* T1 = sN;
   // the middle transform stage in sN, or in place over sR where sN's tail
   // holds the tables
-  double* T2 = (DIM == 3 && !FLDS) ? sR : sN + EPB * Sh::T1;
+  double* T2 = DIM == 3 ? sR : sN + EPB * Sh::T1;
 
   // ---- w = V w~ at the volume nodes
   for (int o = tid; o < nec * NP; o += nth) sM[o] = wt[e0 * NC * NP + o];
