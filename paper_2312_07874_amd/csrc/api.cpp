@@ -73,7 +73,7 @@ void free_device(esd_plan* p) {
   dev_free(p, p->d_conn);
   dev_free(p, p->d_xvol);
   if (p->flag_owned) dev_free(p, p->d_flag);
-  dev_free(p, p->d_tasks);
+  dev_free(p, p->d_wext_off);
   dev_free(p, p->d_mats);
   dev_free(p, p->d_mat_off);
   dev_free(p, p->d_wt_off);
@@ -81,8 +81,8 @@ void free_device(esd_plan* p) {
   dev_free(p, p->d_asegs);
   dev_free(p, p->d_xbar_off);
   p->d_tables = p->d_gvol = p->d_gfac = p->d_xvol = p->d_mats = nullptr;
-  p->d_conn = p->d_tasks = p->d_arecs = p->d_asegs = nullptr;
-  p->d_mat_off = p->d_wt_off = p->d_xbar_off = nullptr;
+  p->d_conn = p->d_arecs = p->d_asegs = nullptr;
+  p->d_mat_off = p->d_wt_off = p->d_wext_off = p->d_xbar_off = nullptr;
   p->d_flag = nullptr;
 }
 
@@ -411,7 +411,6 @@ esd_status esd_plan_create_batched(const esd_batch_desc* d, const esd_scheme_des
       if (2 * ne_b * stride >= std::numeric_limits<int32_t>::max())
         return bail(ESD_EUNSUPPORTED, "bucket too large for 32-bit facet addressing");
       std::vector<int32_t> conn(ne_b * NFQ);
-      std::vector<int32_t> tasks;
       for (int64_t i = 0; i < ne_b; ++i) {
         const int m = members[b][i].first;
         const int64_t e = members[b][i].second;
@@ -456,12 +455,9 @@ esd_status esd_plan_create_batched(const esd_batch_desc* d, const esd_scheme_des
             }
             it = matid.emplace(key, (int)mat_off.size() - 1).first;
           }
-          const int32_t t[8] = {(int32_t)i, f, bn, (int32_t)in, it->second, 0, esd::n_modes(dim, pn), 0};
-          tasks.insert(tasks.end(), t, t + 8);
           arec[bn][in].push_back({b, (int32_t)i, f, it->second, (int32_t)in, NQF, NFQ, 0});
         }
       }
-      sp->n_tasks = (int64_t)tasks.size() / 8;
       // the VJP gathers exterior cotangents through the same permutation on
       // facets between equal degrees: it must pair those nodes both ways
       sp->conn_involutive = true;
@@ -477,7 +473,6 @@ esd_status esd_plan_create_batched(const esd_batch_desc* d, const esd_scheme_des
         }
       if (!host_only) {
         esd_status st = upload(sp, &sp->d_conn, conn);
-        if (st == ESD_OK && !tasks.empty()) st = upload(sp, &sp->d_tasks, tasks);
         if (st != ESD_OK) return bail(st, "upload failed");
       }
     }
@@ -501,13 +496,16 @@ esd_status esd_plan_create_batched(const esd_batch_desc* d, const esd_scheme_des
     P->node_off.assign(nb_ + 1, 0);
     P->ws_off.assign(nb_, 0);
     size_t ws = 0;
-    std::vector<int64_t> wt_off(nb_);
+    std::vector<int64_t> wt_off(nb_), wext_off(nb_);
     for (int b = 0; b < nb_; ++b) {
       esd_plan* sp = P->sub[b];
       P->dof_off[b + 1] = P->dof_off[b] + sp->ne * nc * sp->ref.NP;
       P->node_off[b + 1] = P->node_off[b] + sp->ne * sp->ref.NQ;
       P->ws_off[b] = ws;
       wt_off[b] = (int64_t)(ws / sizeof(double));
+      // the exterior slots follow the own facet values (split_ws)
+      wext_off[b] = (int64_t)((ws + align256((size_t)sp->ne * nc * sp->ref.NP * sizeof(double))) / sizeof(double)) +
+                    sp->ne * nc * sp->ref.NFQ;
       ws += align256(sp->ws_bytes);
     }
     P->ne = first.back();
@@ -538,6 +536,7 @@ esd_status esd_plan_create_batched(const esd_batch_desc* d, const esd_scheme_des
       if (st == ESD_OK && !mats.empty()) st = upload(P, &P->d_mats, mats);
       if (st == ESD_OK && !mat_off.empty()) st = upload(P, &P->d_mat_off, mat_off);
       if (st == ESD_OK) st = upload(P, &P->d_wt_off, wt_off);
+      if (st == ESD_OK) st = upload(P, &P->d_wext_off, wext_off);
       if (st == ESD_OK) st = upload(P, &P->d_xbar_off, xbar_off);
       if (st != ESD_OK) return bail(st, "upload failed");
       for (esd_plan* sp : P->sub) {
@@ -776,8 +775,7 @@ static int residual_any(const esd_plan* P, const double* u, double* dudt, void* 
     if (rc != 0) return rc;
   }
   for (int b = 0; b < nb; ++b) {
-    const int rc = esd::launch_mixed_exterior(P->sub[b], P, (const double*)ws,
-                                              split_ws(P->sub[b], (char*)ws + P->ws_off[b]), s);
+    const int rc = esd::launch_mixed_exterior(P->sub[b], b, P, (const double*)ws, s);
     if (rc != 0) return rc;
   }
   if (P->timing) esd::timing_event(P, s);
@@ -874,8 +872,7 @@ static int project_all(const esd_plan* P, const double* u, void* ws, hipStream_t
     if (rc != 0) return rc;
   }
   for (int b = 0; b < nb; ++b) {
-    const int rc = esd::launch_mixed_exterior(P->sub[b], P, (const double*)ws,
-                                              split_ws(P->sub[b], (char*)ws + P->ws_off[b]), s);
+    const int rc = esd::launch_mixed_exterior(P->sub[b], b, P, (const double*)ws, s);
     if (rc != 0) return rc;
   }
   return 0;
@@ -906,8 +903,7 @@ static int fused_stage(const esd_plan* P, void* cur, void* nxt, const esd::RkEpi
       if (rc != 0) return rc;
     }
     for (int b = 0; b < nb; ++b) {
-      const int rc = esd::launch_mixed_exterior(P->sub[b], P, (const double*)nxt,
-                                                split_ws(P->sub[b], (char*)nxt + P->ws_off[b]), s);
+      const int rc = esd::launch_mixed_exterior(P->sub[b], b, P, (const double*)nxt, s);
       if (rc != 0) return rc;
     }
   }
@@ -1188,7 +1184,7 @@ static int vjp_any(const esd_plan* P, const double* u, const double* vbar, doubl
   for (int b = 0; b < nb && rc == 0; ++b)
     rc = esd::launch_entropy_projection(P->sub[b], u + P->dof_off[b], vjp_ws_bucket(P, b, ws), s);
   for (int b = 0; b < nb && rc == 0; ++b)
-    rc = esd::launch_mixed_exterior(P->sub[b], P, (const double*)ws, vjp_ws_bucket(P, b, ws), s);
+    rc = esd::launch_mixed_exterior(P->sub[b], b, P, (const double*)ws, s);
   for (int b = 0; b < nb && rc == 0; ++b)
     rc = esd::launch_vjp_part(P->sub[b], 0, u + P->dof_off[b], vbar + P->dof_off[b], grad + P->dof_off[b],
                               vjp_ws_bucket(P, b, ws), s);

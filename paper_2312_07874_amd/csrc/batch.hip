@@ -1,7 +1,7 @@
 // Exterior facet values across interfaces between elements of different
 // degree (gfx950, FP64), and their adjoint.
 //
-// Each task is one facet of an element whose neighbour has another degree:
+// Each facet of an element whose neighbour has another degree:
 //   w+[c][j] = sum_k I[j][k] w~_nb[c][k],   j < NQF (this degree), k < NP (neighbour's),
 // I the neighbour's PKD basis at the reference points of this facet's nodes
 // (built on the host).  The result lands in the element's exterior slot, laid
@@ -13,84 +13,89 @@
 
 namespace esd {
 
-// task layout, int32 [8]: slot, face, neighbour bucket, neighbour slot, matrix,
-// unused, neighbour NP, unused.  Matrices are stored transposed, I^T [k][j], so
-// that the threads of a task (one per facet node j) read consecutive words;
-// the neighbour's w~ (at most 5 x 286 values) is staged in LDS.
-constexpr int MIX_MAX_NP = 286;   // PKD modes of a degree-10 tetrahedron
-
-// NC (variables) fixed at compile time and the contraction unrolled, so that
-// several matrix rows are in flight per thread (measured on the batch of 35,904
-// tetrahedra: 2.5 -> 0.8 ms per residual for this kernel).  A facet of few
-// nodes (nqf <= 42: tetrahedra up to p = 5, every triangle) leaves most of the
-// 128 lanes idle and one lane walking all np modes; there the lanes split into
-// S = 128 / nqf >= 3 slices, slice s summing the modes k = s, s + S, ..., and
-// the slices' partial sums are added in LDS.  Same batch, per launch: buckets
-// of p = 2..5 80 -> 50-72 us; p = 6, 7 (one lane per node) 78 -> 88 us, the
-// same with two slices; p = 8..10 unchanged; 0.83 -> 0.76 ms per residual.
-// Both forms in one kernel cost 90 VGPRs and 16.6 KB of LDS (67 and 11.4 KB
-// with one form), 5 waves per SIMD instead of 7, which the one-lane-per-node
-// buckets pay for; a kernel per form would keep them at 7.
+// Matrices are stored transposed, I^T [k][j], so that the threads of a facet
+// (one per facet node j) read consecutive words.
+constexpr int MIX_MAX_NP = 286;    // PKD modes of a degree-10 tetrahedron
+constexpr int MIX_MAX_NQF = 121;   // facet nodes of a degree-10 tetrahedron
 constexpr int MIX_BLOCK = 128;
 
+// The facets are grouped by the element whose w~ they read (up to one per
+// face of it, in the records of adjoint below): one workgroup per such
+// element stages its w~ (at most 5 x 286 values) in LDS once and evaluates
+// every facet of the group, instead of one workgroup per facet staging it
+// again (measured on the batch of 35,904 tetrahedra: K1 with the interface
+// kernels 3.02 -> 2.96 ms per residual).  NC (variables) is fixed at compile time
+// and the contraction unrolled, so that several matrix rows are in flight per
+// thread.  A facet of few nodes (nqf <= 42: tetrahedra up to p = 5, every
+// triangle) would leave most of the 128 lanes idle and one lane walking all np
+// modes; there the lanes split into S = 128 / nqf >= 3 slices, slice s summing
+// the modes k = s, s + S, ..., and the slices' partial sums are added in LDS.
+// Record, int32 [8]: destination bucket b, destination slot e, face f,
+// matrix, source slot (the element whose w~ is read), NQF of b, NFQ of b,
+// unused.
 template <int NC>
 __global__ void __launch_bounds__(MIX_BLOCK)
-k_mixed_exterior(const int32_t* __restrict__ tasks, const double* __restrict__ ws_base,
-                 const int64_t* __restrict__ wt_off, const double* __restrict__ mats,
-                 const int64_t* __restrict__ mat_off, double* __restrict__ wext, int nfq, int nqf) {
+k_mixed_exterior(const int32_t* __restrict__ segs, const int32_t* __restrict__ recs, const double* __restrict__ ws_base,
+                 const int64_t* __restrict__ wt_off, const int64_t* __restrict__ wext_off,
+                 const double* __restrict__ mats, const int64_t* __restrict__ mat_off, int src_bucket, int np) {
   __shared__ double sW[5 * MIX_MAX_NP];
   __shared__ double sR[NC * MIX_BLOCK];
-  const int32_t* t = tasks + 8 * (int64_t)blockIdx.x;
-  const int slot = t[0], face = t[1], nbb = t[2], nbs = t[3], mat = t[4], np = t[6];
-  const double* wtn = ws_base + wt_off[nbb] + (int64_t)nbs * NC * np;
+  const int first = segs[2 * blockIdx.x], count = segs[2 * blockIdx.x + 1];
+  const int slot = recs[8 * first + 4];
+  const double* wtn = ws_base + wt_off[src_bucket] + (int64_t)slot * NC * np;
   for (int o = threadIdx.x; o < NC * np; o += MIX_BLOCK) sW[o] = wtn[o];
   __syncthreads();
-  const double* IT = mats + mat_off[mat];
-  double* dst = wext + (int64_t)slot * NC * nfq + face * nqf;
-  if (3 * nqf > MIX_BLOCK) {
-    for (int j = threadIdx.x; j < nqf; j += MIX_BLOCK) {
-      double acc[NC];
+  for (int r = first; r < first + count; ++r) {
+    const int32_t* t = recs + 8 * (int64_t)r;
+    const int b = t[0], e = t[1], f = t[2], m = t[3], nqf = t[5], nfq = t[6];
+    const double* IT = mats + mat_off[m];
+    double* dst = const_cast<double*>(ws_base) + wext_off[b] + (int64_t)e * NC * nfq + f * nqf;
+    if (3 * nqf > MIX_BLOCK) {
+      for (int j = threadIdx.x; j < nqf; j += MIX_BLOCK) {
+        double acc[NC];
 #pragma unroll
-      for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+        for (int c = 0; c < NC; ++c) acc[c] = 0.0;
 #pragma unroll 8
-      for (int k = 0; k < np; ++k) {
+        for (int k = 0; k < np; ++k) {
+          const double a = IT[(int64_t)k * nqf + j];
+#pragma unroll
+          for (int c = 0; c < NC; ++c) acc[c] += a * sW[c * np + k];
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) dst[c * nfq + j] = acc[c];
+      }
+      continue;
+    }
+    // nqf <= 42: thread = (slice s, node j), s < S = MIX_BLOCK / nqf
+    const int S = MIX_BLOCK / nqf;
+    const int sl = threadIdx.x / nqf, j = threadIdx.x - sl * nqf;
+    double acc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+    if (sl < S) {
+#pragma unroll 4
+      for (int k = sl; k < np; k += S) {
         const double a = IT[(int64_t)k * nqf + j];
 #pragma unroll
         for (int c = 0; c < NC; ++c) acc[c] += a * sW[c * np + k];
       }
-#pragma unroll
-      for (int c = 0; c < NC; ++c) dst[c * nfq + j] = acc[c];
     }
-    return;
-  }
-  // nqf <= 42: thread = (slice s, node j), s < S = MIX_BLOCK / nqf
-  const int S = MIX_BLOCK / nqf;
-  const int s = threadIdx.x / nqf, j = threadIdx.x - s * nqf;
-  double acc[NC];
 #pragma unroll
-  for (int c = 0; c < NC; ++c) acc[c] = 0.0;
-  if (s < S) {
-#pragma unroll 4
-    for (int k = s; k < np; k += S) {
-      const double a = IT[(int64_t)k * nqf + j];
+    for (int c = 0; c < NC; ++c) sR[c * MIX_BLOCK + threadIdx.x] = acc[c];
+    __syncthreads();
+    if (threadIdx.x < nqf) {
 #pragma unroll
-      for (int c = 0; c < NC; ++c) acc[c] += a * sW[c * np + k];
+      for (int c = 0; c < NC; ++c) {
+        double v = 0.0;
+        for (int q = 0; q < S; ++q) v += sR[c * MIX_BLOCK + q * nqf + threadIdx.x];
+        dst[c * nfq + threadIdx.x] = v;
+      }
     }
-  }
-#pragma unroll
-  for (int c = 0; c < NC; ++c) sR[c * MIX_BLOCK + threadIdx.x] = acc[c];
-  __syncthreads();
-  if (threadIdx.x < nqf) {
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      double v = 0.0;
-      for (int r = 0; r < S; ++r) v += sR[c * MIX_BLOCK + r * nqf + threadIdx.x];
-      dst[c * nfq + threadIdx.x] = v;
-    }
+    __syncthreads();   // sR is reused by the next facet
   }
 }
 
-// Adjoint of the task above: w~_bar_nb[c][k] += sum_j I[j][k] x_bar_e[c][j],
+// Adjoint of the facet evaluation above: w~_bar_nb[c][k] += sum_j I[j][k] x_bar_e[c][j],
 // x_bar_e the cotangent of the exterior values of facet f of element e (the
 // right-hand side's adjoint writes it at e's own facet nodes).  One workgroup
 // per element nb of this bucket whose w~ some task reads; it walks the
@@ -99,7 +104,6 @@ k_mixed_exterior(const int32_t* __restrict__ tasks, const double* __restrict__ w
 // no atomic and the result does not depend on scheduling.  Record, int32 [8]:
 // source bucket, source slot e, face f, matrix, target slot nb, source NQF,
 // source NFQ, unused.
-constexpr int MIX_MAX_NQF = 121;   // facet nodes of a degree-10 tetrahedron
 constexpr int MIX_KMAX = (MIX_MAX_NP + MIX_BLOCK - 1) / MIX_BLOCK;
 
 template <int NC>
@@ -165,17 +169,15 @@ int launch_mixed_exterior_vjp(const esd_plan* b, const esd_plan* top, const doub
   return (int)hipGetLastError();
 }
 
-int launch_mixed_exterior(const esd_plan* b, const esd_plan* top, const double* ws_base, Workspace ws,
-                          hipStream_t s) {
-  if (b->n_tasks == 0) return 0;
-  const int nfq = b->ref.NFQ, nqf = b->ref.NQF;
-  double* wext = ws.wf + b->ne * b->nc * nfq;
+int launch_mixed_exterior(const esd_plan* b, int bi, const esd_plan* top, const double* ws_base, hipStream_t s) {
+  if (b->n_asegs == 0) return 0;
+  if (b->ref.NP > MIX_MAX_NP) return -1;
   if (b->nc == 5)
-    hipLaunchKernelGGL(k_mixed_exterior<5>, dim3((unsigned)b->n_tasks), dim3(MIX_BLOCK), 0, s, b->d_tasks, ws_base,
-                       top->d_wt_off, top->d_mats, top->d_mat_off, wext, nfq, nqf);
+    hipLaunchKernelGGL(k_mixed_exterior<5>, dim3((unsigned)b->n_asegs), dim3(MIX_BLOCK), 0, s, b->d_asegs, b->d_arecs,
+                       ws_base, top->d_wt_off, top->d_wext_off, top->d_mats, top->d_mat_off, bi, b->ref.NP);
   else
-    hipLaunchKernelGGL(k_mixed_exterior<4>, dim3((unsigned)b->n_tasks), dim3(MIX_BLOCK), 0, s, b->d_tasks, ws_base,
-                       top->d_wt_off, top->d_mats, top->d_mat_off, wext, nfq, nqf);
+    hipLaunchKernelGGL(k_mixed_exterior<4>, dim3((unsigned)b->n_asegs), dim3(MIX_BLOCK), 0, s, b->d_asegs, b->d_arecs,
+                       ws_base, top->d_wt_off, top->d_wext_off, top->d_mats, top->d_mat_off, bi, b->ref.NP);
   return (int)hipGetLastError();
 }
 

@@ -109,10 +109,10 @@ struct esd_plan {
   // facet-state region of the workspace holds 2 ne slots (own values, then the
   // exterior values of facets whose neighbour has another degree)
   bool wext = false;
-  int32_t* d_tasks = nullptr;     // [n_tasks][8] mixed-interface tasks (see batch.hip)
-  int64_t n_tasks = 0;
-  // their adjoint, gathered per element of this bucket that some task reads
-  // (see batch.hip): records [n_arecs][8], segments [n_asegs][2] (first, count)
+  // the facets of other buckets whose exterior values read the w~ of this
+  // bucket's elements, grouped by that element (see batch.hip): records
+  // [n_arecs][8], segments [n_asegs][2] (first, count); used by the
+  // mixed-interface kernel and its adjoint
   int32_t* d_arecs = nullptr;
   int32_t* d_asegs = nullptr;
   int64_t n_asegs = 0;
@@ -127,6 +127,7 @@ struct esd_plan {
   double* d_mats = nullptr;       // mixed-interface evaluation matrices
   int64_t* d_mat_off = nullptr;   // [n_mats] offsets into d_mats
   int64_t* d_wt_off = nullptr;    // [nb] offsets (doubles) of each bucket's w~ in the workspace
+  int64_t* d_wext_off = nullptr;  // [nb] offsets (doubles) of each bucket's exterior facet values
   // VJP workspace of a batch: the residual workspace, then per bucket its
   // x_bar (ne NC NFQ doubles) and its adjoint scratch slices
   std::vector<size_t> xbar_off, vscr_off;   // [nb] bytes from the workspace start
@@ -180,8 +181,8 @@ int launch_scale(double* y, const double* x, double a, int64_t n, hipStream_t s)
 // K2 alone (K1 must have run for every element whose facet values it reads)
 int launch_rhs(const esd_plan* P, double* dudt, Workspace ws, hipStream_t s, const RkEpilogue& epi = RkEpilogue());
 // batch.hip: exterior facet values of mixed-degree interfaces of one bucket
-int launch_mixed_exterior(const esd_plan* bucket, const esd_plan* top, const double* ws_base, Workspace ws,
-                          hipStream_t s);
+// (bucket bi of top: the facets that read the w~ of its elements)
+int launch_mixed_exterior(const esd_plan* bucket, int bi, const esd_plan* top, const double* ws_base, hipStream_t s);
 // and its adjoint: w~_bar of this bucket's elements (grad, the bucket's slice)
 // += I^T x_bar of the facets that read them (VJP workspace at ws_base)
 int launch_mixed_exterior_vjp(const esd_plan* bucket, const esd_plan* top, const double* ws_base, double* grad,
