@@ -293,6 +293,30 @@ __device__ __forceinline__ void v_second(const double* T1, double* T2, const Dev
   }
 }
 
+// ------------------------------------------------------------------ matrix-core form of the eta1 stages
+// On tetrahedra the last stage of V and the first of V^T contract the Q
+// values of each eta1 line with psi1, the same Q x Q matrix for all N = nec Q^2
+// lines: a dense product that v_mfma_f64_16x16x4 evaluates 16 lines at a time
+// (one wave per tile, ceil(Q / 4) steps of K = 4, rows and steps beyond Q
+// zero).  Register layout of that instruction on gfx950 (measured with one-hot
+// inputs): A[m][k] in lane m + 16 k, B[k][n] in lane n + 16 k, D[m][n] in lane
+// n + 16 (m % 4), element m / 4.  Measured against the lane-per-line loop on
+// the same LDS-staged stage (4,096 elements, measure/transform_mfma.hip):
+// p = 6 0.031 -> 0.023 ms, p = 8 0.072 -> 0.053, p = 10 0.177 -> 0.147 ms.
+// Inside the kernels (tgv on tetrahedra, K1 + K2 per call) it pays from
+// p = 6 on (p = 6 3.28 -> 3.23 ms, p = 8 7.89 -> 7.48, p = 10 8.17 -> 7.40)
+// and costs below (p = 4 0.79 -> 0.91, p = 5 1.50 -> 1.77: few lines per
+// element, tiles half padding, and the extra registers cost occupancy).
+// Each wave reads all Q values of its 16 lines before writing any, so the
+// stages stay in place over a line's own slots.
+typedef double mf_d4 __attribute__((ext_vector_type(4)));
+template <int P>
+struct MfmaEta1 {
+  static constexpr int Q = P + 1;
+  static constexpr bool ON = Q >= 7;
+  static constexpr int KS = (Q + 3) / 4;
+};
+
 // V, last stage: sum over a1 with psi1 into the nodes (Tin is T1 on
 // triangles, T2 on tetrahedra)
 template <int DIM, int P>
@@ -303,6 +327,37 @@ __device__ __forceinline__ void v_last(const double* Tin, double* out, const Dev
   const int tid = threadIdx.x, nth = blockDim.x;
   // out[ec][i1 + Q l] = sum_a1 psi1[a1][i1] Tin(ec, a1, l); on tetrahedra Tin
   // may equal out (the line is read whole before it is written)
+  if constexpr (DIM == 3 && MfmaEta1<P>::ON) {
+    constexpr int KS = MfmaEta1<P>::KS;
+    const int lane = tid & 63, n = lane % 16, kq = lane / 16;
+    double a[KS];
+#pragma unroll
+    for (int st = 0; st < KS; ++st) {
+      const int k = 4 * st + kq;
+      a[st] = (n < Q && k < Q) ? T.psi1[k * Q + n] : 0.0;   // A[m = n][k] = psi1[k][m]
+    }
+    const int ncol = nec * L, tiles = (ncol + 15) / 16;
+    for (int t = tid >> 6; t < tiles; t += nth >> 6) {
+      const int o = t * 16 + n;
+      const bool valid = o < ncol;
+      const double* tl = Tin + (int64_t)(valid ? o : 0) * Q;
+      const int r = (o % L) % Q;
+      mf_d4 d = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int st = 0; st < KS; ++st) {
+        const int k = 4 * st + kq;
+        const double b = (valid && k < Q) ? tl[k + r < Q ? k + r : k + r - Q] : 0.0;
+        d = __builtin_amdgcn_mfma_f64_16x16x4f64(a[st], b, d, 0, 0, 0);
+      }
+      double* ol = out + (int64_t)(valid ? o : 0) * Q;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int m = 4 * i + kq;
+        if (valid && m < Q) ol[m] = d[i];
+      }
+    }
+    return;
+  }
   for (int o = tid; o < nec * L; o += nth) {
     const int l = o % L, ec = o / L;
     double acc[Q];
@@ -339,6 +394,37 @@ __device__ __forceinline__ void vt_first(const double* in, double* Tout, const D
   const int tid = threadIdx.x, nth = blockDim.x;
   // Tout(ec, a1, l) = sum_i1 psi1[a1][i1] in[ec][i1 + Q l]; on tetrahedra Tout
   // may equal in (the line is read whole before it is written)
+  if constexpr (DIM == 3 && MfmaEta1<P>::ON) {
+    constexpr int KS = MfmaEta1<P>::KS;
+    const int lane = tid & 63, n = lane % 16, kq = lane / 16;
+    double a[KS];
+#pragma unroll
+    for (int st = 0; st < KS; ++st) {
+      const int k = 4 * st + kq;
+      a[st] = (n <= P && k < Q) ? T.psi1[n * Q + k] : 0.0;   // A[m = n][k] = psi1[m][k]
+    }
+    const int ncol = nec * L, tiles = (ncol + 15) / 16;
+    for (int t = tid >> 6; t < tiles; t += nth >> 6) {
+      const int o = t * 16 + n;
+      const bool valid = o < ncol;
+      const double* il = in + (int64_t)(valid ? o : 0) * Q;   // in[ec][i1 + Q l] = line o's slots
+      const int r = (o % L) % Q;
+      mf_d4 d = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int st = 0; st < KS; ++st) {
+        const int k = 4 * st + kq;
+        const double b = (valid && k < Q) ? il[k] : 0.0;
+        d = __builtin_amdgcn_mfma_f64_16x16x4f64(a[st], b, d, 0, 0, 0);
+      }
+      double* tl = Tout + (int64_t)(valid ? o : 0) * Q;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int m = 4 * i + kq;
+        if (valid && m <= P) tl[m + r < Q ? m + r : m + r - Q] = d[i];
+      }
+    }
+    return;
+  }
   for (int o = tid; o < nec * L; o += nth) {
     const int l = o % L, ec = o / L;
     double acc[P + 1];
