@@ -314,12 +314,15 @@ template <int P>
 struct MfmaEta1 {
   static constexpr int Q = P + 1;
   static constexpr bool ON = Q >= 7;
+  // the entropy projection alone (K1) loses at p = 6, 7 (0.77 -> 0.86 ms,
+  // 1.55 -> 1.70 ms on 24,576 elements) and gains from p = 8 on
+  static constexpr bool ON_PROJ = Q >= 9;
   static constexpr int KS = (Q + 3) / 4;
 };
 
 // V, last stage: sum over a1 with psi1 into the nodes (Tin is T1 on
 // triangles, T2 on tetrahedra)
-template <int DIM, int P>
+template <int DIM, int P, bool MF = MfmaEta1<P>::ON>
 __device__ __forceinline__ void v_last(const double* Tin, double* out, const DevTables& T, int nec) {
   using S = Shape<DIM, P>;
   constexpr int Q = S::Q, XU = Unroll<P>::XU;
@@ -327,7 +330,7 @@ __device__ __forceinline__ void v_last(const double* Tin, double* out, const Dev
   const int tid = threadIdx.x, nth = blockDim.x;
   // out[ec][i1 + Q l] = sum_a1 psi1[a1][i1] Tin(ec, a1, l); on tetrahedra Tin
   // may equal out (the line is read whole before it is written)
-  if constexpr (DIM == 3 && MfmaEta1<P>::ON) {
+  if constexpr (DIM == 3 && MF) {
     constexpr int KS = MfmaEta1<P>::KS;
     const int lane = tid & 63, n = lane % 16, kq = lane / 16;
     double a[KS];
@@ -386,7 +389,7 @@ __device__ __forceinline__ void v_last(const double* Tin, double* out, const Dev
 }
 
 // V^T, first stage: sum over i1 with psi1 (out is T1 on triangles, T2 on tetrahedra)
-template <int DIM, int P>
+template <int DIM, int P, bool MF = MfmaEta1<P>::ON>
 __device__ __forceinline__ void vt_first(const double* in, double* Tout, const DevTables& T, int nec) {
   using S = Shape<DIM, P>;
   constexpr int Q = S::Q, XU = Unroll<P>::XU;
@@ -394,7 +397,7 @@ __device__ __forceinline__ void vt_first(const double* in, double* Tout, const D
   const int tid = threadIdx.x, nth = blockDim.x;
   // Tout(ec, a1, l) = sum_i1 psi1[a1][i1] in[ec][i1 + Q l]; on tetrahedra Tout
   // may equal in (the line is read whole before it is written)
-  if constexpr (DIM == 3 && MfmaEta1<P>::ON) {
+  if constexpr (DIM == 3 && MF) {
     constexpr int KS = MfmaEta1<P>::KS;
     const int lane = tid & 63, n = lane % 16, kq = lane / 16;
     double a[KS];
@@ -522,7 +525,7 @@ __device__ __forceinline__ void vt_last(const double* T1, double* out, const Dev
 }
 
 // u = V u~ at the volume nodes (eq. modal_to_nodal, Sec. 5.2); ends with a barrier
-template <int DIM, int P>
+template <int DIM, int P, bool MF = MfmaEta1<P>::ON>
 __device__ __forceinline__ void xform_V(const double* uh, double* T1, double* T2, double* out, const DevTables& T,
                                         int nec) {
   v_first<DIM, P>(uh, T1, T, nec);
@@ -530,23 +533,23 @@ __device__ __forceinline__ void xform_V(const double* uh, double* T1, double* T2
   if constexpr (DIM == 3) {
     v_second<P>(T1, T2, T, nec);
     __syncthreads();
-    v_last<DIM, P>(T2, out, T, nec);
+    v_last<DIM, P, MF>(T2, out, T, nec);
   } else {
-    v_last<DIM, P>(T1, out, T, nec);
+    v_last<DIM, P, MF>(T1, out, T, nec);
   }
   __syncthreads();
 }
 
 // V^T applied to nodal fields; ends with a barrier
-template <int DIM, int P>
+template <int DIM, int P, bool MF = MfmaEta1<P>::ON>
 __device__ __forceinline__ void xform_Vt(const double* in, double* T1, double* T2, double* out, const DevTables& T,
                                          int nec) {
   if constexpr (DIM == 3) {
-    vt_first<DIM, P>(in, T2, T, nec);
+    vt_first<DIM, P, MF>(in, T2, T, nec);
     __syncthreads();
     vt_second<P>(T2, T1, T, nec);
   } else {
-    vt_first<DIM, P>(in, T1, T, nec);
+    vt_first<DIM, P, MF>(in, T1, T, nec);
   }
   __syncthreads();
   vt_last<DIM, P>(T1, out, T, nec);
@@ -559,7 +562,7 @@ __device__ __forceinline__ void xform_Vt(const double* in, double* T1, double* T
 // the Q x Q matrix psiM[a] = sum_b psi[a][b] psi[a][b]^T (b over the line's
 // modes, a = a1 on triangles, a1 + a2 on tetrahedra), applied in place by the
 // thread owning the line: one stage and one barrier fewer.  Ends with a barrier.
-template <int DIM, int P>
+template <int DIM, int P, bool MF = MfmaEta1<P>::ON>
 __device__ __forceinline__ void xform_VVt(const double* in, double* T1, double* T2, double* out, const DevTables& T,
                                           int nec) {
   using S = Shape<DIM, P>;
@@ -567,11 +570,11 @@ __device__ __forceinline__ void xform_VVt(const double* in, double* T1, double* 
   constexpr int NL = DIM == 2 ? P + 1 : S::NPAIR;   // lines of the composed direction per (element, variable)
   const int tid = threadIdx.x, nth = blockDim.x;
   if constexpr (DIM == 3) {
-    vt_first<DIM, P>(in, T2, T, nec);
+    vt_first<DIM, P, MF>(in, T2, T, nec);
     __syncthreads();
     vt_second<P>(T2, T1, T, nec);
   } else {
-    vt_first<DIM, P>(in, T1, T, nec);
+    vt_first<DIM, P, MF>(in, T1, T, nec);
   }
   __syncthreads();
   for (int o = tid; o < nec * NL; o += nth) {
@@ -601,9 +604,9 @@ __device__ __forceinline__ void xform_VVt(const double* in, double* T1, double* 
   if constexpr (DIM == 3) {
     v_second<P>(T1, T2, T, nec);
     __syncthreads();
-    v_last<DIM, P>(T2, out, T, nec);
+    v_last<DIM, P, MF>(T2, out, T, nec);
   } else {
-    v_last<DIM, P>(T1, out, T, nec);
+    v_last<DIM, P, MF>(T1, out, T, nec);
   }
   __syncthreads();
 }

@@ -64,10 +64,10 @@ __device__ __forceinline__ void weight_adjusted_projection(double* sM, double* s
     xform_Vt_inplace<P, IP::MAXT>(sA, T, nec);
     xform_V_inplace<P, IP::MAXT>(sA, T, nec);
   } else if constexpr (VVT) {
-    xform_VVt<DIM, P>(sA, T1, T2, sA, T, nec);
+    xform_VVt<DIM, P, MfmaEta1<P>::ON_PROJ>(sA, T1, T2, sA, T, nec);
   } else {
-    xform_Vt<DIM, P>(sA, T1, T2, sM, T, nec);
-    xform_V<DIM, P>(sM, T1, T2, sA, T, nec);
+    xform_Vt<DIM, P, MfmaEta1<P>::ON_PROJ>(sA, T1, T2, sM, T, nec);
+    xform_V<DIM, P, MfmaEta1<P>::ON_PROJ>(sM, T1, T2, sA, T, nec);
   }
   aI.each(nel * NQ, ld_wi, [&](int o, double wi) {
     const int k = o % NQ, el = o / NQ;
@@ -76,7 +76,7 @@ __device__ __forceinline__ void weight_adjusted_projection(double* sM, double* s
   });
   __syncthreads();
   if constexpr (INPLACE) xform_Vt_inplace<P, IP::MAXT>(sA, T, nec);
-  else xform_Vt<DIM, P>(sA, T1, T2, sM, T, nec);
+  else xform_Vt<DIM, P, MfmaEta1<P>::ON_PROJ>(sA, T1, T2, sM, T, nec);
 }
 
 // Entropy projection of a block of elements whose modal state u~ is in sM
@@ -99,7 +99,7 @@ __device__ __forceinline__ void project_block(double* sM, double* sA, double* sS
   using IP = K1Inplace<DIM, P>;
   auto ld_wJ = [&](int o) { return gvol[((e0 + o / NQ) * NGV + NGV - 2) * NQ + o % NQ]; };
   if constexpr (INPLACE) xform_V_inplace<P, IP::MAXT>(sA, T, nec);
-  else xform_V<DIM, P>(sM, T1, T2, sA, T, nec);
+  else xform_V<DIM, P, MfmaEta1<P>::ON_PROJ>(sM, T1, T2, sA, T, nec);
   // entropy variables times w J at every volume node
   bool bad = false;
   aJ.each(nel * NQ, ld_wJ, [&](int o, double wJ) {
@@ -126,7 +126,7 @@ __device__ __forceinline__ void project_block(double* sM, double* sA, double* sS
   for (int o = tid; o < nec * NP; o += nth) wt[e0 * NC * NP + o] = sM[o];
   // facet values of the projected entropy variables, w^z = R^z V w~
   if constexpr (INPLACE) xform_V_inplace<P, IP::MAXT>(sA, T, nec);
-  else xform_V<DIM, P>(sM, T1, T2, sA, T, nec);
+  else xform_V<DIM, P, MfmaEta1<P>::ON_PROJ>(sM, T1, T2, sA, T, nec);
   double* wfe = wf + e0 * NC * NFQ;
   facet_values<DIM, P>(sA, sS, T, nec, [&](int o, double v) { wfe[o] = v; });
 }
