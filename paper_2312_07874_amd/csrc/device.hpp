@@ -50,9 +50,11 @@ struct Launch<3, P> {
   // measured on MI355X (K2 at p = 4..8): 128, 192, 256, 256, 512 threads
   static constexpr int BS = P <= 3 ? 64 : (P == 4 ? 128 : (P == 5 ? 192 : (P <= 7 ? 256 : 512)));
   // K1 and K2 are compiled for up to BSMAX threads and launched with BS or with
-  // the block size the autotuner picked (their loops take any size)
+  // the block size the autotuner picked (their loops take any multiple of 64:
+  // the matrix-core transform stages need whole waves)
   static constexpr int BSMAX = 512;
   static_assert(P <= 10, "tetrahedra up to p = 10");
+  static_assert(BS % 64 == 0 && BSMAX % 64 == 0, "whole waves");
 };
 template <int P>
 struct Launch<2, P> {
@@ -62,6 +64,7 @@ struct Launch<2, P> {
   static constexpr int NQ = (P + 1) * (P + 1);
   static constexpr int BS = ((EPB * NQ + 63) / 64) * 64;
   static constexpr int BSMAX = 2 * BS < 768 ? 2 * BS : (BS > 768 ? BS : 768);   // <= 3 waves per SIMD
+  static_assert(BS % 64 == 0 && BSMAX % 64 == 0, "whole waves");
 };
 
 __device__ __forceinline__ int pair_index(int P, int a1, int a2) { return a1 * (P + 1) - a1 * (a1 - 1) / 2 + a2; }
@@ -308,7 +311,9 @@ __device__ __forceinline__ void v_second(const double* T1, double* T2, const Dev
 // and costs below (p = 4 0.79 -> 0.91, p = 5 1.50 -> 1.77: few lines per
 // element, tiles half padding, and the extra registers cost occupancy).
 // Each wave reads all Q values of its 16 lines before writing any, so the
-// stages stay in place over a line's own slots.
+// stages stay in place over a line's own slots.  The instruction reads the
+// registers of all 64 lanes: the tiles go to whole waves (block sizes are
+// multiples of 64), the lanes of a tile's missing lines contribute zeros.
 typedef double mf_d4 __attribute__((ext_vector_type(4)));
 template <int P>
 struct MfmaEta1 {
