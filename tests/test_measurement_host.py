@@ -1,8 +1,12 @@
 """Host logic of the measurement: the work model's pair counts against their
 closed forms, the byte model's ordering of the RK4 stage variants, and the
-rocprofv3 CSV readers on synthetic files of known content.  No GPU."""
+rocprofv3 CSV readers on synthetic files of known content, and that the
+stand-alone measurement programs still cross-compile for gfx950.  No GPU."""
 import csv
 import json
+import os
+import shutil
+import subprocess
 
 import pytest
 
@@ -149,3 +153,17 @@ def test_stats_picks_the_plain_right_hand_side(tmp_path, capsys):
     prof.stats(str(path))
     out = capsys.readouterr().out
     assert "K1 0.001 ms, mixed-degree interface 0.000 ms, K2 0.002 ms" in out
+
+
+MEASURE = os.path.join(os.path.dirname(prof.__file__), "measure")
+
+
+@pytest.mark.parametrize("src", ["probe_fp64_ops.hip", "transform_mfma.hip"])
+def test_measurement_programs_compile_for_gfx950(src, tmp_path):
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not installed")
+    cmd = [hipcc, "-O3", "--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           "-c", os.path.join(MEASURE, src), "-o", str(tmp_path / "m.o")]
+    r = subprocess.run(cmd, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
