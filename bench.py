@@ -308,7 +308,7 @@ def run_dense_vs_lines():
     kernel's distinct pairs, the all-pairs count of the dense loops, and the
     paper's reduction factors (tensor-product vs multidimensional operators on
     their own node sets, Sec. 5.3), which it counts on symmetric quadrature
-    rules this build does not have."""
+    rules this library does not have."""
     import torch
 
     import paper_2312_07874_amd as esd
@@ -451,7 +451,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (the sharding design is "
+        print("bench.py runs on one GPU only: this library has no multi-GPU path (the sharding design is "
               "in the design notes); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.workload == HEADLINE:
